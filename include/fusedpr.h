@@ -1,0 +1,243 @@
+/*
+ * fusedpr.h -- C ABI of the MI355X (gfx950) PageRank library.
+ *
+ * The library computes the PageRank vector of a directed graph: the fixed
+ * point of the paper's recurrence (Section 1, Eq. 1; restated per iteration
+ * as Eq. 2)
+ *
+ *     x_u = (1-d) p_u + d * ( sum_{v -> u} w(v->u) x_v / W_v  +  D / n )
+ *
+ * with W_v the out-weight sum of v (its out-degree when unweighted), D the
+ * total rank of dangling vertices (W_v = 0), spread uniformly, and p the
+ * teleport vector (1/n everywhere unless given).  It is reached either by the
+ * edge-centric Jacobi pull (Section 3, Algorithm 1) or by the loop-fused
+ * in-place Gauss-Seidel-like sweep (Section 4, Algorithm 2; Eq. 9), run
+ * block-asynchronously as in the paper's parallel variant (Section 6.3).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: PR_OK (0) on success, PR_NOT_CONVERGED (1) when an
+ *     iteration stopped at max_iter (outputs are valid), a negative PR_E*
+ *     code on error.  No entry point aborts or exits; the message of the last
+ *     error on the calling thread is returned by pr_last_error().
+ *   - Arguments are validated before any GPU work is queued; an invalid
+ *     argument returns PR_EINVAL and leaves outputs untouched.
+ *   - Pointers documented as "device" must be device memory of the current
+ *     HIP device (e.g. from PyTorch); "host" pointers are ordinary memory.
+ *     Input pointers are borrowed for the duration of the call only.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Entry
+ *     points that return host-side results (iteration counts, residuals)
+ *     synchronise that stream before returning; device outputs are complete
+ *     when they return.
+ *   - Vertex ids are int32 in [0, n); edge counts up to 2^32 - 2 per graph.
+ *   - Calls on one pr_graph must not overlap (each graph owns its workspace);
+ *     distinct graphs may be used from distinct threads.
+ */
+#ifndef FUSEDPR_H
+#define FUSEDPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pr_status {
+  PR_OK = 0,
+  PR_NOT_CONVERGED = 1,
+  PR_EINVAL = -1,
+  PR_ENOMEM = -2,
+  PR_EDEVICE = -3
+};
+
+/* Message of the most recent error on this thread ("" if none).  The string
+ * stays valid until the next library call on the same thread. */
+const char *pr_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Canonical graph on the host.
+ *
+ * The paper keeps per-vertex in- and out-adjacency (inList / outList) and an
+ * offsetList mapping each out-edge to the contributionList slot of the same
+ * edge (Section 3, the example of Fig. 1).  pr_build_csr produces that layout
+ * in compressed form:
+ *   in_ptr[n+1], in_src[m], in_w[m]   in-edges grouped by destination
+ *                                     (destinations ascending), sources
+ *                                     ascending within a destination
+ *   out_ptr[n+1], out_dst[m], out_w[m] out-edges grouped by source,
+ *                                     destinations ascending
+ *   out_to_in[m]                      offsetList: out position -> in position
+ *   out_deg[n], in_deg[n]             degrees of the stored graph
+ *   edge_map[m_input]                 input edge i -> its out position,
+ *                                     -1 if it was a dropped self-loop
+ * Self-loops are dropped and repeated (src, dst) pairs are merged into one
+ * edge whose weight is the sum of their weights, added in input order.  The
+ * weight arrays are NULL for an unweighted graph.  All arrays are allocated
+ * by the library and released by pr_csr_free.
+ * ---------------------------------------------------------------------- */
+typedef struct pr_csr {
+  int64_t n;
+  int64_t m;
+  int64_t *in_ptr;
+  int32_t *in_src;
+  double *in_w;
+  int64_t *out_ptr;
+  int32_t *out_dst;
+  double *out_w;
+  int64_t *out_to_in;
+  int32_t *out_deg;
+  int32_t *in_deg;
+  int64_t m_input;
+  int64_t *edge_map;
+} pr_csr;
+
+/* Build the canonical graph from an edge list (host arrays src[m], dst[m],
+ * optional host weights w[m], each finite and > 0).  n >= 1, m >= 0.
+ * PR_EINVAL on an id outside [0, n) or a bad weight; PR_ENOMEM on allocation
+ * failure.  *out is zeroed first and owns the result on success. */
+int pr_build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                 pr_csr *out);
+void pr_csr_free(pr_csr *csr);
+
+/* ------------------------------------------------------------------------
+ * Device graph.
+ *
+ * pr_graph_create copies the graph to the current device and builds the
+ * execution plan: vertices are binned by in-degree (thread-, wavefront- or
+ * workgroup-per-vertex; very long rows split across workgroups) and the
+ * in-edges are re-laid in bin order.  The library owns that device memory and
+ * the per-graph workspace; pr_graph_destroy releases them.
+ * ---------------------------------------------------------------------- */
+typedef struct pr_graph pr_graph;
+
+typedef struct pr_plan_opts {
+  int light_max;     /* largest in-degree handled thread-per-vertex (default 32) */
+  int medium_max;    /* largest in-degree handled wavefront-per-vertex (default 2048) */
+  int split;         /* edges per workgroup chunk of a long row (default 8192) */
+  int block_edges;   /* edge budget of a thread-per-vertex block (default 2048) */
+  int with_adjoint;  /* also plan the out-edge (transposed) pull for pr_adjoint */
+} pr_plan_opts;
+
+void pr_plan_opts_default(pr_plan_opts *o);
+
+/* csr: a canonical graph from pr_build_csr (host memory).  opts may be NULL. */
+int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_graph **out);
+void pr_graph_destroy(pr_graph *g);
+
+typedef struct pr_graph_stats {
+  int64_t n, m;
+  int64_t n_light, n_medium, n_heavy; /* vertices per bin */
+  int64_t e_light, e_medium, e_heavy; /* in-edges per bin */
+  int64_t n_items;                    /* work items per sweep */
+  int64_t n_dangling;
+  int64_t device_bytes;               /* graph + plan bytes held on the device */
+  int grid;                           /* persistent workgroups per sweep */
+} pr_graph_stats;
+
+int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *out);
+
+/* ------------------------------------------------------------------------
+ * Solver options.
+ * ---------------------------------------------------------------------- */
+enum pr_mode { PR_JACOBI = 0, PR_FUSED = 1 };
+enum pr_precision { PR_FP64 = 0, PR_FP32 = 1 };
+enum pr_dangling { PR_DANGLING_UNIFORM = 0, PR_DANGLING_LEAK = 1 };
+enum pr_norm { PR_NORM_L1 = 0, PR_NORM_LINF = 1 };
+
+typedef struct pr_opts {
+  int mode;             /* PR_JACOBI (Algorithm 1) or PR_FUSED (Algorithm 2, in place) */
+  int precision;        /* PR_FP64, or PR_FP32: ranks and contributions stored and summed
+                           in FP32 with compensated sums; residual and dangling mass in FP64 */
+  int dangling;         /* PR_DANGLING_UNIFORM, or PR_DANGLING_LEAK (the paper's literal
+                           algorithms, which drop dangling mass) */
+  int norm;             /* residual norm: PR_NORM_L1, or PR_NORM_LINF (Eq. 3; Jacobi only) */
+  int warm_start;       /* 1: start from the x passed in; 0: start from p */
+  int fused_scaled;     /* PR_FUSED only: scale the teleport term by the previous sweep's
+                           total mass (default 1); 0 = plain lagged-dangling sweep */
+  int sweeps_per_poll;  /* sweeps queued between host convergence polls (default 8) */
+  int use_hip_graph;    /* capture the queued sweeps in a hipGraph (default 1) */
+  double refine_tol;    /* PR_FP32: FP64 refinement sweeps continue until the FP64 residual
+                           is below this (0 = no refinement; default: the solve's tol) */
+  double fp32_tol;      /* PR_FP32: residual at which the FP32 stage hands over to the FP64
+                           refinement (default max(tol, 1e-7)) */
+  double *trace;        /* optional host array[max_iter]: residual after each sweep */
+} pr_opts;
+
+void pr_opts_default(pr_opts *o);
+
+/* ------------------------------------------------------------------------
+ * Forward solve.
+ *
+ * pr_solve iterates until the residual (the norm of the change between
+ * successive iterates, Eq. 3 with the chosen norm) drops below tol, or
+ * max_iter sweeps.  Algorithm 1 / Algorithm 2 loop structure: the pull, the
+ * update, the dangling-mass and residual reductions and the convergence test
+ * are fused into one kernel per sweep.
+ *   d        damping factor, 0 < d < 1 (the paper uses 0.85)
+ *   tol      > 0;  max_iter >= 1
+ *   p        device double[n] teleport vector (finite, >= 0, sum 1), or NULL for 1/n
+ *   x        device double[n]: start vector if o->warm_start, else ignored on entry;
+ *            the ranks on return (sum 1 for uniform dangling)
+ *   iters    host: sweeps executed (FP32: FP32 sweeps + FP64 refinement sweeps)
+ *   resid    host: residual of the last sweep
+ * Returns PR_NOT_CONVERGED (x valid) when max_iter is reached first.
+ * ---------------------------------------------------------------------- */
+int pr_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, const double *p,
+             double *x, int *iters, double *resid, void *stream);
+
+/* Exactly `sweeps` sweeps from the x passed in (no convergence test), FP64.
+ * resid (host, nullable) receives the residual of the last sweep. */
+int pr_iterate(pr_graph *g, double d, const pr_opts *o, const double *p, double *x, int sweeps,
+               double *resid, void *stream);
+
+/* ||F(x) - x||_1 for any device vector x (FP64), where F is one exact
+ * application of the recurrence above.  Bounds the error of x:
+ * ||x - x*||_1 <= ||F(x) - x||_1 / (1 - d).  result: host double. */
+int pr_certificate(pr_graph *g, double d, const double *p, const double *x, double *result,
+                   void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched personalized PageRank: k teleport vectors, each one-hot on
+ * seeds[j], solved together as one k-column pull per sweep (Jacobi).
+ * Dangling mass is spread uniformly.  Ranks are FP32, per-column residual
+ * and dangling mass FP64; a column stops updating once its L1 residual is
+ * below tol.
+ *   seeds   device int32[k], ids in [0, n);  1 <= k <= 1024
+ *   X       device float[n * k], row-major (vertex-major): X[v * k + j]
+ *   iters   host int[k]: sweeps until column j converged (or max_iter)
+ *   resid   host double[k]: last residual of each column
+ *   tile    columns processed per pass (1..64, dividing k); 0 = autotuned
+ * ---------------------------------------------------------------------- */
+int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter, int k, const int32_t *seeds,
+                     int tile, float *X, int *iters, double *resid, void *stream);
+
+/* Autotuner for pr_solve_batched: times the candidate tile widths on this
+ * graph and device and returns the fastest in *tile.  When cache_path is not
+ * NULL the choice is read from / appended to that JSON-lines file, keyed by
+ * the graph's size signature, k and the device name. */
+int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, int *tile, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (implicit differentiation of the fixed point).
+ *
+ * For a scalar loss L(x) with dL/dx = g, solves (I - dP)^T lam = g by the
+ * transposed Jacobi pull over out-edges, then
+ *   dL/dp_u       = (1-d) lam_u
+ *   dL/dw(v->u)   = d * x_v / W_v * (lam_u - (P^T lam)_v)
+ * (the second term is the derivative of the normalisation by W_v).
+ *   x      device double[n]: the forward solution
+ *   g      device double[n]
+ *   lam    device double[n] out
+ *   dLdp   device double[n] out (nullable)
+ *   dLdw   device double[m] out in out-edge (pr_csr out_*) order (nullable)
+ *   tol    on max |lam' - lam|;  iters / resid: host
+ * The graph must have been created with with_adjoint = 1.
+ * ---------------------------------------------------------------------- */
+int pr_adjoint(pr_graph *g, double d, const double *x, const double *dLdx, double tol, int max_iter,
+               double *lam, double *dLdp, double *dLdw, int *iters, double *resid, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FUSEDPR_H */

@@ -1,0 +1,119 @@
+// Internal declarations of the fusedpr library (host side and kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fusedpr.h"
+
+// ----------------------------------------------------------------- errors --
+int pr_fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void pr_clear_error();
+
+#define PR_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return pr_fail(e_ == hipErrorOutOfMemory ? PR_ENOMEM : PR_EDEVICE, "%s: %s (%s:%d)", \
+                     #call, hipGetErrorString(e_), __FILE__, __LINE__);               \
+  } while (0)
+
+// ------------------------------------------------------------- constants --
+namespace fpr {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kWaves = kBlock / 64;  // wavefronts per workgroup
+constexpr int kLightCap = 2048;      // max edges staged in LDS by a thread-per-vertex block
+
+enum ItemKind : int { kLight = 0, kMedium = 1, kHeavy = 2 };
+
+// Sweep flags (runtime, uniform across the grid)
+enum SweepFlags : int {
+  kFlagLeak = 1,      // no dangling term (the paper's literal algorithms)
+  kFlagLinf = 2,      // max-norm residual instead of L1
+  kFlagScaled = 4,    // teleport scaled by the previous sweep's total mass
+  kFlagUniformP = 8,  // p == 1/n (p pointer unused)
+};
+
+// Device-resident state of an iteration; one per graph and pull direction.
+struct SweepState {
+  unsigned ticket;    // next work item of the running sweep
+  unsigned finished;  // workgroups that finished the running sweep
+  int iter;           // sweeps completed
+  int done;           // 1 once the residual is below tol or iter == max_iter
+  int max_iter;
+  int pad0;
+  double tol;
+  double D;      // dangling mass of the current iterate
+  double S;      // total mass of the current iterate
+  double resid;  // residual of the last sweep
+  double raw;    // unscaled L1 (or max) change of the last sweep
+};
+
+// One binned pull layout: vertices grouped by degree, neighbours re-laid in
+// bin order.  Used for the forward pull over in-edges and the transposed
+// pull over out-edges.
+struct DevPlan {
+  int64_t n = 0, m = 0;
+  uint32_t *rows = nullptr;   // [n] vertex ids in bin order
+  uint32_t *rptr = nullptr;   // [n+1] edge offsets (bin order)
+  int32_t *idx = nullptr;     // [m] neighbour ids
+  double *w = nullptr;        // [m] edge weights or null
+  int4 *items = nullptr;      // [n_items] {kind, a, b, c}
+  uint32_t *hbase = nullptr;  // [n_heavy] first partial slot of each heavy row
+  double *hpart = nullptr;    // [n_chunks] partial sums of heavy row chunks
+  unsigned *hcnt = nullptr;   // [n_heavy] chunk arrival counters
+  double *item_part = nullptr;  // [n_items * 3] per-item (change, dangling, total)
+  SweepState *st = nullptr;
+  int n_items = 0;
+  int n_heavy = 0;
+  int n_chunks = 0;
+  int split = 8192;
+  int64_t n_light = 0, n_medium = 0, n_heavy_rows = 0;
+  int64_t e_light = 0, e_medium = 0, e_heavy = 0;
+  int64_t bytes = 0;
+};
+
+}  // namespace fpr
+
+struct pr_graph {
+  int device = 0;
+  int n_cu = 0;
+  int64_t n = 0, m = 0;
+  bool weighted = false;
+  pr_plan_opts popts{};
+  fpr::DevPlan fwd, adj;
+  bool has_adj = false;
+  double *inv_w = nullptr;      // [n] 1 / W_v, 0 for dangling vertices
+  uint32_t *out_ptr = nullptr;  // [n+1] out-edge offsets (adjoint gradient layout)
+  int64_t n_dangling = 0;
+  int grid = 0;  // persistent workgroups per sweep
+  hipStream_t work = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // workspace (allocated on first use)
+  double *c64[2] = {nullptr, nullptr};
+  float *c32[2] = {nullptr, nullptr};
+  float *x32 = nullptr;
+  double *xtmp = nullptr;
+  double *trace_dev = nullptr;
+  int trace_cap = 0;
+  fpr::SweepState *host_st = nullptr;  // pinned mirror of the state
+  double *red_tmp = nullptr;           // small reduction scratch
+  // batched workspace
+  float *Xb[2] = {nullptr, nullptr};
+  size_t Xb_elems = 0;
+  double *bstate = nullptr;  // per-column state
+  double *bpart = nullptr;   // per-item per-column partials
+  size_t bpart_elems = 0;
+  int *bhost = nullptr;
+  int64_t device_bytes = 0;
+  std::vector<void *> owned;  // device allocations released by pr_graph_destroy
+};
+
+// plan.hip
+int fpr_dev_alloc(pr_graph *g, void **p, size_t bytes);
+// sweep.hip
+int fpr_grid_for(pr_graph *g);

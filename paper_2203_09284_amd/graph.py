@@ -1,0 +1,242 @@
+"""Python binding of the fusedpr C ABI: argument marshalling only.
+
+Every step of the computation runs in libfusedpr.so (hipcc, gfx950).  PyTorch
+provides device memory for the vectors (ranks, teleport vectors, gradients)
+and the stream the calls are ordered on.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+MODES = {"jacobi": L.PR_JACOBI, "fused": L.PR_FUSED}
+PRECISIONS = {"fp64": L.PR_FP64, "fp32": L.PR_FP32}
+DANGLING = {"uniform": L.PR_DANGLING_UNIFORM, "leak": L.PR_DANGLING_LEAK}
+NORMS = {"l1": L.PR_NORM_L1, "linf": L.PR_NORM_LINF}
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor | None, dtype, n: int | None, name: str):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, dtype))
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class CanonicalCSR:
+    """Host copy of the library's canonical graph (pr_build_csr)."""
+    n: int
+    m: int
+    in_ptr: np.ndarray
+    in_src: np.ndarray
+    in_w: np.ndarray | None
+    out_ptr: np.ndarray
+    out_dst: np.ndarray
+    out_w: np.ndarray | None
+    out_to_in: np.ndarray
+    out_deg: np.ndarray
+    in_deg: np.ndarray
+    edge_map: np.ndarray
+
+
+def build_csr(n: int, src, dst, weights=None, keep: bool = True):
+    """Run pr_build_csr on host arrays.  Returns (PrCsr owned by the library,
+    CanonicalCSR numpy copy or None)."""
+    lib = L.lib()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst differ in length")
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+    if w is not None and w.shape != src.shape:
+        raise ValueError("weights differ in length from the edge list")
+    csr = L.PrCsr()
+    rc = lib.pr_build_csr(n, len(src), src.ctypes.data_as(L.vp), dst.ctypes.data_as(L.vp),
+                          None if w is None else w.ctypes.data_as(L.vp), ctypes.byref(csr))
+    L.check(rc)
+    copy = None
+    if keep:
+        n_, m_ = csr.n, csr.m
+
+        def arr(ptr, count, dt):
+            if not ptr or count == 0:
+                return np.zeros(0, dt)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+
+        copy = CanonicalCSR(
+            n=n_, m=m_,
+            in_ptr=arr(csr.in_ptr, n_ + 1, np.int64), in_src=arr(csr.in_src, m_, np.int32),
+            in_w=arr(csr.in_w, m_, np.float64) if csr.in_w else None,
+            out_ptr=arr(csr.out_ptr, n_ + 1, np.int64), out_dst=arr(csr.out_dst, m_, np.int32),
+            out_w=arr(csr.out_w, m_, np.float64) if csr.out_w else None,
+            out_to_in=arr(csr.out_to_in, m_, np.int64), out_deg=arr(csr.out_deg, n_, np.int32),
+            in_deg=arr(csr.in_deg, n_, np.int32), edge_map=arr(csr.edge_map, csr.m_input, np.int64))
+    return csr, copy
+
+
+class Graph:
+    """A graph resident on the current GPU, with its execution plan."""
+
+    def __init__(self, n: int, src, dst, weights=None, with_adjoint: bool = False,
+                 plan: dict | None = None, keep_csr: bool = False):
+        lib = L.lib()
+        csr, copy = build_csr(n, src, dst, weights, keep=True)
+        self.csr = copy if keep_csr else None
+        self.edge_map = torch.from_numpy(copy.edge_map) if weights is not None else None
+        po = L.PrPlanOpts()
+        lib.pr_plan_opts_default(ctypes.byref(po))
+        for k, v in (plan or {}).items():
+            setattr(po, k, int(v))
+        po.with_adjoint = 1 if with_adjoint else 0
+        handle = ctypes.c_void_p()
+        try:
+            rc = lib.pr_graph_create(ctypes.byref(csr), ctypes.byref(po), ctypes.byref(handle))
+            L.check(rc)
+        finally:
+            lib.pr_csr_free(ctypes.byref(csr))
+        self._h = handle
+        self.n = int(copy.n)
+        self.m = int(copy.m)
+        self.weighted = weights is not None
+        self.with_adjoint = with_adjoint
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().pr_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        s = L.PrGraphStats()
+        L.check(L.lib().pr_graph_stats_get(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in L.PrGraphStats._fields_}
+
+    # ------------------------------------------------------------- solve --
+    def _opts(self, mode, precision, dangling, norm, warm, fused_scaled, sweeps_per_poll,
+              use_hip_graph, refine_tol, fp32_tol, trace_buf):
+        o = L.PrOpts()
+        L.lib().pr_opts_default(ctypes.byref(o))
+        o.mode = MODES[mode]
+        o.precision = PRECISIONS[precision]
+        o.dangling = DANGLING[dangling]
+        o.norm = NORMS[norm]
+        o.warm_start = 1 if warm else 0
+        o.fused_scaled = 1 if fused_scaled else 0
+        if sweeps_per_poll is not None:
+            o.sweeps_per_poll = int(sweeps_per_poll)
+        o.use_hip_graph = 1 if use_hip_graph else 0
+        if refine_tol is not None:
+            o.refine_tol = float(refine_tol)
+        if fp32_tol is not None:
+            o.fp32_tol = float(fp32_tol)
+        if trace_buf is not None:
+            o.trace = trace_buf.ctypes.data_as(L.c_f64p)
+        return o
+
+    def solve(self, d: float = 0.85, tol: float = 1e-8, max_iter: int = 1000, mode: str = "jacobi",
+              precision: str = "fp64", p: torch.Tensor | None = None, x: torch.Tensor | None = None,
+              warm_start: bool = False, dangling: str = "uniform", norm: str = "l1",
+              fused_scaled: bool = True, sweeps_per_poll: int | None = None,
+              use_hip_graph: bool = True, refine_tol: float | None = None,
+              fp32_tol: float | None = None, trace: bool = False, stream=None):
+        """pr_solve.  Returns (x, sweeps, residual, converged[, trace])."""
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        tr = np.zeros(max_iter) if trace else None
+        o = self._opts(mode, precision, dangling, norm, warm_start, fused_scaled, sweeps_per_poll,
+                       use_hip_graph, refine_tol, fp32_tol, tr)
+        it = ctypes.c_int(0)
+        res = ctypes.c_double(0.0)
+        rc = L.lib().pr_solve(self._h, d, tol, max_iter, ctypes.byref(o),
+                              _dev_ptr(p, torch.float64, self.n, "p"),
+                              _dev_ptr(x, torch.float64, self.n, "x"), ctypes.byref(it),
+                              ctypes.byref(res), _stream_ptr(stream))
+        L.check(rc)
+        out = (x, it.value, res.value, rc == L.PR_OK)
+        if trace:
+            return out + (tr[:it.value].copy(),)
+        return out
+
+    def iterate(self, x: torch.Tensor, sweeps: int, d: float = 0.85, mode: str = "jacobi",
+                p: torch.Tensor | None = None, dangling: str = "uniform", norm: str = "l1",
+                fused_scaled: bool = True, stream=None) -> float:
+        """pr_iterate: exactly `sweeps` FP64 sweeps from x, in place.  Returns the last residual."""
+        o = self._opts(mode, "fp64", dangling, norm, True, fused_scaled, None, False, None, None, None)
+        res = ctypes.c_double(0.0)
+        rc = L.lib().pr_iterate(self._h, d, ctypes.byref(o), _dev_ptr(p, torch.float64, self.n, "p"),
+                                _dev_ptr(x, torch.float64, self.n, "x"), int(sweeps),
+                                ctypes.byref(res), _stream_ptr(stream))
+        L.check(rc)
+        return res.value
+
+    def certificate(self, x: torch.Tensor, d: float = 0.85, p: torch.Tensor | None = None,
+                    stream=None) -> float:
+        """||F(x) - x||_1, computed on the GPU; ||x - x*||_1 <= this / (1 - d)."""
+        out = ctypes.c_double(0.0)
+        rc = L.lib().pr_certificate(self._h, d, _dev_ptr(p, torch.float64, self.n, "p"),
+                                    _dev_ptr(x, torch.float64, self.n, "x"), ctypes.byref(out),
+                                    _stream_ptr(stream))
+        L.check(rc)
+        return out.value
+
+    # ---------------------------------------------------------- batched --
+    def solve_batched(self, seeds: torch.Tensor, d: float = 0.85, tol: float = 1e-6,
+                      max_iter: int = 1000, tile: int = 0, X: torch.Tensor | None = None,
+                      stream=None):
+        """pr_solve_batched.  Returns (X [n, k] float32, iters[k], residuals[k])."""
+        k = int(seeds.numel())
+        if X is None:
+            X = torch.empty((self.n, k), dtype=torch.float32, device=self.device)
+        its = (ctypes.c_int * k)()
+        res = (ctypes.c_double * k)()
+        rc = L.lib().pr_solve_batched(self._h, d, tol, max_iter, k,
+                                      _dev_ptr(seeds, torch.int32, k, "seeds"), int(tile),
+                                      _dev_ptr(X, torch.float32, self.n * k, "X"), its, res,
+                                      _stream_ptr(stream))
+        L.check(rc)
+        return X, np.array(its[:], np.int64), np.array(res[:], np.float64)
+
+    def autotune_batched(self, k: int, cache_path: str | None = None, stream=None) -> int:
+        tile = ctypes.c_int(0)
+        rc = L.lib().pr_autotune_batched(self._h, int(k), None if cache_path is None else cache_path.encode(),
+                                         ctypes.byref(tile), _stream_ptr(stream))
+        L.check(rc)
+        return tile.value
+
+    # ---------------------------------------------------------- adjoint --
+    def adjoint(self, x: torch.Tensor, dLdx: torch.Tensor, d: float = 0.85, tol: float = 1e-14,
+                max_iter: int = 10_000, want_p: bool = True, want_w: bool = True, stream=None):
+        """pr_adjoint.  Returns (lam, dL/dp or None, dL/dw in out-edge order or None, sweeps, residual)."""
+        lam = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        gp = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_p else None
+        gw = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device) if want_w else None
+        it = ctypes.c_int(0)
+        res = ctypes.c_double(0.0)
+        rc = L.lib().pr_adjoint(self._h, d, _dev_ptr(x, torch.float64, self.n, "x"),
+                                _dev_ptr(dLdx, torch.float64, self.n, "dLdx"), tol, max_iter,
+                                _dev_ptr(lam, torch.float64, None, "lam"),
+                                _dev_ptr(gp, torch.float64, None, "dLdp"),
+                                _dev_ptr(gw, torch.float64, None, "dLdw"), ctypes.byref(it),
+                                ctypes.byref(res), _stream_ptr(stream))
+        L.check(rc)
+        return lam, gp, (gw[:self.m] if gw is not None else None), it.value, res.value

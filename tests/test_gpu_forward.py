@@ -1,0 +1,282 @@
+"""GPU parity of the forward solve (Jacobi and fused forms, FP64 and FP32)
+against the FP64 CPU oracle's fixed point.  Bar: L1 <= 1e-9 (FP64),
+L1 <= 1e-5 (FP32); CSR and degrees are checked bit-exact on the host side.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+
+
+def _fpr():
+    import paper_2203_09284_amd as fpr
+    return fpr
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def l1(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).sum())
+
+
+def cases():
+    out = []
+    src, dst = gg.random_graph(300, 1500, 11)
+    out.append(("random300", 300, src, dst, None, None))
+    s, t = gg.rmat(10, 8, seed=12)
+    out.append(("rmat10", 1024, s, t, None, None))
+    src, dst = gg.random_graph(500, 2500, 13)
+    out.append(("weighted500", 500, src, dst, gg.weights(len(src), 13), None))
+    src, dst = gg.random_graph(400, 1200, 14)
+    p = gg.uniforms(14, 9, 400)
+    out.append(("personalized400", 400, src, dst, None, p / p.sum()))
+    s, t = gg.rmat(14, 16, seed=2)
+    out.append(("rmat14", 1 << 14, s, t, None, None))
+    d = gg.er_10k()
+    out.append(("er10k", d["n"], d["src"], d["dst"], None, None))
+    return out
+
+
+CASES = cases()
+# plans that force every bin, many heavy chunks and ragged blocks on small graphs
+PLANS = [None, dict(light_max=2, medium_max=40, split=256, block_edges=37),
+         dict(light_max=0, medium_max=8, split=256, block_edges=1)]
+
+
+def _ref(n, src, dst, w, p, tol=1e-15):
+    og = oracle.csr(n, src, dst, w)
+    x, _, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=5000, p=p)
+    return og, x
+
+
+def _p_dev(p):
+    return None if p is None else torch.tensor(p, dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("plan", range(len(PLANS)))
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("mode", ["jacobi", "fused"])
+def test_fp64_fixed_point(case, plan, mode):
+    name, n, src, dst, w, p = CASES[case]
+    say("case %s plan %d mode %s" % (name, plan, mode))
+    fpr = _fpr()
+    _, xr = _ref(n, src, dst, w, p)
+    g = fpr.Graph(n, src, dst, w, plan=PLANS[plan])
+    x, it, res, ok = g.solve(d=D, tol=1e-13, max_iter=3000, mode=mode, p=_p_dev(p))
+    assert ok, (it, res)
+    err = l1(x.cpu().numpy(), xr)
+    say("  sweeps=%d resid=%.2e L1=%.2e" % (it, res, err))
+    assert err <= 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_fused_plain_lagged_form(case):
+    name, n, src, dst, w, p = CASES[case]
+    say("case %s fused unscaled" % name)
+    fpr = _fpr()
+    _, xr = _ref(n, src, dst, w, p)
+    g = fpr.Graph(n, src, dst, w)
+    x, it, res, ok = g.solve(d=D, tol=1e-13, max_iter=5000, mode="fused", fused_scaled=False,
+                             p=_p_dev(p))
+    assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("mode", ["jacobi", "fused"])
+def test_fp32(case, mode):
+    name, n, src, dst, w, p = CASES[case]
+    say("case %s fp32 %s" % (name, mode))
+    fpr = _fpr()
+    _, xr = _ref(n, src, dst, w, p)
+    g = fpr.Graph(n, src, dst, w)
+    # FP32 only (no refinement): within the FP32 bar
+    x, it, res, ok = g.solve(d=D, tol=1e-7, max_iter=3000, mode=mode, precision="fp32",
+                             refine_tol=0.0, p=_p_dev(p))
+    e32 = l1(x.cpu().numpy(), xr)
+    # FP32 then FP64 refinement: within the FP64 bar
+    x2, it2, res2, ok2 = g.solve(d=D, tol=1e-13, max_iter=3000, mode=mode, precision="fp32",
+                                 p=_p_dev(p))
+    e64 = l1(x2.cpu().numpy(), xr)
+    say("  fp32 sweeps=%d L1=%.2e | refined sweeps=%d L1=%.2e" % (it, e32, it2, e64))
+    assert e32 <= 1e-5
+    assert ok2 and e64 <= 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_one_sweep_equals_oracle_F(case):
+    name, n, src, dst, w, p = CASES[case]
+    say("case %s one sweep" % name)
+    fpr = _fpr()
+    og = oracle.csr(n, src, dst, w)
+    x0 = gg.uniforms(99, 1, n)
+    x0 /= x0.sum()
+    want = oracle.apply_F(og, x0, D, p)
+    g = fpr.Graph(n, src, dst, w, plan=PLANS[1])
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    r = g.iterate(x, 1, d=D, p=_p_dev(p))
+    got = x.cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want))
+    assert abs(r - np.abs(want - x0).sum()) <= 1e-12 * max(r, 1e-300)
+    cert = g.certificate(torch.tensor(x0, dtype=torch.float64, device="cuda"), d=D, p=_p_dev(p))
+    assert abs(cert - np.abs(want - x0).sum()) <= 1e-12 * cert
+    g.close()
+
+
+CLOSED = [("cycle", gg.cycle(9), lambda n: np.full(n, 1.0 / n)),
+          ("in_star", gg.in_star(65), None), ("out_star", gg.out_star(65), None),
+          ("bi_star", gg.bi_star(65), None)]
+
+
+def _closed(name, n):
+    if name == "in_star":
+        xh = (1 + (n - 1) * D) / (n + (n - 1) * D)
+        return np.array([xh] + [((1 - D) + D * xh) / n] * (n - 1))
+    if name == "out_star":
+        return np.array([1.0 / (n + D)] + [(n + D - 1) / ((n + D) * (n - 1))] * (n - 1))
+    if name == "bi_star":
+        xh = (D + (1 - D) / n) / (1 + D)
+        return np.array([xh] + [(1 - xh) / (n - 1)] * (n - 1))
+    return np.full(n, 1.0 / n)
+
+
+@pytest.mark.parametrize("ci", range(len(CLOSED)), ids=[c[0] for c in CLOSED])
+@pytest.mark.parametrize("mode", ["jacobi", "fused"])
+def test_closed_forms(ci, mode):
+    name, (s, t), _ = CLOSED[ci]
+    n = int(max(s.max(), t.max())) + 1
+    say("closed form %s %s" % (name, mode))
+    fpr = _fpr()
+    g = fpr.Graph(n, s, t)
+    x, it, res, ok = g.solve(d=D, tol=1e-15, max_iter=500, mode=mode)
+    want = _closed(name, n)
+    assert np.max(np.abs(x.cpu().numpy() - want)) <= 1e-15 * max(1.0, n * want.max())
+    g.close()
+
+
+def test_path_leak_mode_and_linf():
+    fpr = _fpr()
+    n = 40
+    s, t = gg.path(n)
+    say("path leak")
+    g = fpr.Graph(n, s, t)
+    want = np.array([(1 - D ** (i + 1)) / n for i in range(n)])
+    x, it, res, ok = g.solve(d=D, tol=1e-17, max_iter=500, dangling="leak", norm="linf")
+    assert ok and np.max(np.abs(x.cpu().numpy() - want)) <= 1e-15 * want.max()
+    og = oracle.csr(n, s, t)
+    _, ito, _ = oracle.pagerank_ec(og, D, tol=1e-17, max_iter=500, dangling="leak", norm="linf")
+    assert abs(it - ito) <= 1
+    g.close()
+
+
+def test_leak_mode_iterates_follow_the_oracle():
+    fpr = _fpr()
+    s, t = gg.rmat(12, 8, seed=3)
+    n = 1 << 12
+    og = oracle.csr(n, s, t)
+    say("leak trajectory")
+    g = fpr.Graph(n, s, t, plan=PLANS[1])
+    for sweeps in (1, 3, 10):
+        xr, _, _ = oracle.pagerank_ec(og, D, tol=0.0, max_iter=sweeps, dangling="leak")
+        x = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+        g.iterate(x, sweeps, d=D, dangling="leak")
+        assert np.max(np.abs(x.cpu().numpy() - xr)) <= 1e-14 * xr.max()
+    g.close()
+
+
+@pytest.mark.parametrize("n,edges", [(1, ([], [])), (7, ([], [])), (3, ([1, 1], [1, 1])),
+                                     (2, ([0], [1])), (5, ([0, 0, 0, 4], [1, 1, 1, 1]))])
+def test_edge_cases(n, edges):
+    fpr = _fpr()
+    s = np.array(edges[0], np.int32)
+    t = np.array(edges[1], np.int32)
+    say("edge case n=%d m=%d" % (n, len(s)))
+    xr = oracle.pagerank_ec(oracle.csr(n, s, t), D, tol=1e-16, max_iter=500)[0]
+    g = fpr.Graph(n, s, t)
+    for mode in ("jacobi", "fused"):
+        for prec in ("fp64", "fp32"):
+            x, it, res, ok = g.solve(d=D, tol=1e-14, max_iter=500, mode=mode, precision=prec)
+            assert l1(x.cpu().numpy(), xr) <= 1e-12, (mode, prec)
+    g.close()
+
+
+def test_jacobi_is_bit_reproducible_and_graph_capture_neutral():
+    fpr = _fpr()
+    s, t = gg.rmat(14, 16, seed=5)
+    n = 1 << 14
+    say("determinism")
+    g = fpr.Graph(n, s, t)
+    a = g.solve(d=D, tol=1e-12, mode="jacobi")
+    b = g.solve(d=D, tol=1e-12, mode="jacobi")
+    c = g.solve(d=D, tol=1e-12, mode="jacobi", use_hip_graph=False, sweeps_per_poll=3)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[0], c[0]) and a[1] == b[1] == c[1]
+    g.close()
+
+
+def test_fused_across_schedules():
+    """The fused form's trajectory depends on the schedule; its fixed point must not."""
+    fpr = _fpr()
+    s, t = gg.rmat(13, 16, seed=6)
+    n = 1 << 13
+    _, xr = _ref(n, s, t, None, None)
+    say("fused schedules")
+    for plan in PLANS:
+        g = fpr.Graph(n, s, t, plan=plan)
+        for rep in range(3):
+            x, it, res, ok = g.solve(d=D, tol=1e-13, mode="fused", sweeps_per_poll=1 + rep)
+            assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
+        g.close()
+
+
+def test_trace_and_warm_start():
+    fpr = _fpr()
+    s, t = gg.rmat(12, 16, seed=7)
+    n = 1 << 12
+    og, xr = _ref(n, s, t, None, None)
+    say("trace / warm start")
+    g = fpr.Graph(n, s, t)
+    x, it, res, ok, tr = g.solve(d=D, tol=1e-4, trace=True)
+    _, ito, _, tro, _ = oracle.pagerank_ec(og, D, tol=1e-4, max_iter=1000, trace=True)
+    assert len(tr) == it and abs(it - ito) <= 1
+    assert np.allclose(tr[:min(it, ito)], tro[:min(it, ito)], rtol=1e-9, atol=1e-18)
+    # checkpoint at 1e-4, resume to 1e-12 == direct solve
+    x2, it2, res2, ok2 = g.solve(d=D, tol=1e-12, x=x.clone(), warm_start=True)
+    assert ok2 and l1(x2.cpu().numpy(), xr) <= 1e-9
+    g.close()
+
+
+def test_not_converged_status():
+    fpr = _fpr()
+    s, t = gg.rmat(12, 16, seed=8)
+    say("max_iter")
+    g = fpr.Graph(1 << 12, s, t)
+    x, it, res, ok = g.solve(d=D, tol=1e-14, max_iter=3)
+    assert not ok and it == 3 and res > 1e-14
+    g.close()
+
+
+def test_invalid_arguments():
+    fpr = _fpr()
+    from paper_2203_09284_amd._lib import FusedPRError
+    s, t = gg.cycle(10)
+    say("invalid args")
+    g = fpr.Graph(10, s, t)
+    for kw in (dict(d=1.0), dict(d=0.0), dict(tol=0.0), dict(max_iter=0)):
+        with pytest.raises(FusedPRError):
+            g.solve(**kw)
+    with pytest.raises(FusedPRError):
+        g.solve(mode="fused", norm="linf")
+    with pytest.raises(FusedPRError):
+        g.solve(mode="fused", dangling="leak")
+    with pytest.raises(ValueError):
+        g.solve(p=torch.zeros(3, dtype=torch.float64, device="cuda"))
+    g.close()

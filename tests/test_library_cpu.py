@@ -1,0 +1,121 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/fusedpr.h declares, and its host CSR builder matches
+the oracle's independent CSR bit for bit."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fusedpr.h")
+
+
+def _lib():
+    from paper_2203_09284_amd import _lib as L
+    return L, L.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(pr_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pr_build_csr", "pr_solve", "pr_iterate", "pr_solve_batched", "pr_adjoint",
+                     "pr_graph_create", "pr_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L, lib = _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\sT\s(pr_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(lib, n)
+        assert n in L.SIGNATURES, "binding lacks %s" % n
+
+
+def _compare_csr(n, src, dst, w=None):
+    from paper_2203_09284_amd.graph import build_csr
+    L, lib = _lib()
+    csr, c = build_csr(n, src, dst, w)
+    lib.pr_csr_free(ctypes.byref(csr))
+    o = oracle.csr(n, src, dst, w)
+    assert c.m == o.m
+    assert np.array_equal(c.in_ptr, o.in_ptr)
+    assert np.array_equal(c.in_src, o.in_src)
+    assert np.array_equal(c.out_ptr, o.out_ptr)
+    assert np.array_equal(c.out_dst, o.out_dst)
+    assert np.array_equal(c.out_to_in, o.offset)
+    assert np.array_equal(c.out_deg, o.out_deg)
+    assert np.array_equal(c.in_deg, o.in_deg)
+    assert np.array_equal(c.edge_map, o.edge_map)
+    if w is not None:
+        assert np.array_equal(c.in_w, o.in_w)  # bit-exact: same summation order
+        assert np.array_equal(c.out_w, o.out_w)
+    else:
+        assert c.in_w is None and c.out_w is None
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_csr_bit_exact_small(seed):
+    src, dst = gg.random_graph(60, 700, seed)
+    _compare_csr(60, src, dst)
+    _compare_csr(60, src, dst, gg.weights(len(src), seed))
+
+
+def test_csr_bit_exact_er10k():
+    d = gg.er_10k()
+    _compare_csr(d["n"], d["src"], d["dst"])
+
+
+def test_csr_bit_exact_rmat16_with_repeats():
+    s, t = gg.rmat(16, 16, seed=2)
+    _compare_csr(1 << 16, s, t)
+    _compare_csr(1 << 16, s, t, gg.weights(len(s), 2))
+
+
+def test_csr_edge_cases():
+    _compare_csr(1, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    _compare_csr(5, np.array([1, 1, 1], np.int32), np.array([1, 1, 1], np.int32))  # only self-loops
+    _compare_csr(3, np.array([0, 0, 0, 2], np.int32), np.array([1, 1, 1, 1], np.int32))
+    _compare_csr(*((6,) + gg.complete(6)))
+
+
+def test_csr_errors():
+    from paper_2203_09284_amd.graph import build_csr
+    from paper_2203_09284_amd._lib import FusedPRError
+    with pytest.raises(FusedPRError, match="outside"):
+        build_csr(4, np.array([0, 5], np.int32), np.array([1, 2], np.int32))
+    with pytest.raises(FusedPRError, match="outside"):
+        build_csr(4, np.array([0, -1], np.int32), np.array([1, 2], np.int32))
+    with pytest.raises(FusedPRError, match="weight"):
+        build_csr(4, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([1.0, np.nan]))
+    with pytest.raises(FusedPRError, match="weight"):
+        build_csr(4, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([1.0, 0.0]))
+    with pytest.raises(FusedPRError):
+        build_csr(0, np.zeros(0, np.int32), np.zeros(0, np.int32))
+
+
+def test_error_message_is_thread_local_and_cleared():
+    from paper_2203_09284_amd.graph import build_csr
+    from paper_2203_09284_amd._lib import FusedPRError
+    L, lib = _lib()
+    with pytest.raises(FusedPRError):
+        build_csr(4, np.array([0, 9], np.int32), np.array([1, 2], np.int32))
+    assert b"outside" in lib.pr_last_error()
+    csr, _ = build_csr(4, np.array([0], np.int32), np.array([1], np.int32))
+    lib.pr_csr_free(ctypes.byref(csr))
+    assert lib.pr_last_error() == b""
