@@ -103,19 +103,27 @@ void pr_csr_free(pr_csr *csr);
  * Device graph.
  *
  * pr_graph_create copies the graph to the current device and builds the
- * execution plan: vertices are binned by in-degree (thread-, wavefront- or
- * workgroup-per-vertex; very long rows split across workgroups) and the
- * in-edges are re-laid in bin order.  The library owns that device memory and
- * the per-graph workspace; pr_graph_destroy releases them.
+ * execution plan: vertices are binned by in-degree (one lane up to a whole
+ * wavefront per vertex; very long lists split over several wavefronts), the
+ * in-edges are re-laid in bin order, and the gathered array is laid out by
+ * gather count so its hottest part can sit in LDS.  The library owns that
+ * device memory and the per-graph workspace; pr_graph_destroy releases them.
  * ---------------------------------------------------------------------- */
 typedef struct pr_graph pr_graph;
 
 typedef struct pr_plan_opts {
-  int light_max;     /* largest in-degree handled thread-per-vertex (default 32) */
-  int medium_max;    /* largest in-degree handled wavefront-per-vertex (default 2048) */
-  int split;         /* edges per workgroup chunk of a long row (default 8192) */
-  int block_edges;   /* edge budget of a thread-per-vertex block (default 2048) */
-  int with_adjoint;  /* also plan the out-edge (transposed) pull for pr_adjoint */
+  int chunk;             /* lists longer than this are split into chunks of this many edges,
+                            one wavefront each (default 2048, range [64, 2^20]) */
+  int tile_max_row;      /* lists of 1..tile_max_row edges are packed into 512-edge tiles
+                            (default 512, at most min(512, chunk)); longer ones get a
+                            wavefront each */
+  int tile_rows;         /* rows per tile at most (1..128, default 128) */
+  int steps;             /* one-wavefront rows per work item (default 4) */
+  int hot_slots;         /* gather slots staged in LDS per sweep workgroup (-1 = as many as fit,
+                            0 = none) */
+  int gather_layout;     /* 1 (default): store the gathered array sorted by gather count,
+                            so the hottest vertices come first; 0: vertex-id order */
+  int with_adjoint;      /* also plan the out-edge (transposed) pull for pr_adjoint */
 } pr_plan_opts;
 
 void pr_plan_opts_default(pr_plan_opts *o);
@@ -126,12 +134,12 @@ void pr_graph_destroy(pr_graph *g);
 
 typedef struct pr_graph_stats {
   int64_t n, m;
-  int64_t n_light, n_medium, n_heavy; /* vertices per bin */
+  int64_t n_light, n_medium, n_heavy; /* vertices per bin: one lane, several lanes, chunked */
   int64_t e_light, e_medium, e_heavy; /* in-edges per bin */
-  int64_t n_items;                    /* work items per sweep */
+  int64_t n_items;                    /* wavefront work items per sweep */
   int64_t n_dangling;
   int64_t device_bytes;               /* graph + plan bytes held on the device */
-  int grid;                           /* persistent workgroups per sweep */
+  int grid;                           /* workgroups of one sweep launch (one per CU) */
 } pr_graph_stats;
 
 int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *out);
@@ -185,10 +193,14 @@ void pr_opts_default(pr_opts *o);
 int pr_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, const double *p,
              double *x, int *iters, double *resid, void *stream);
 
-/* Exactly `sweeps` sweeps from the x passed in (no convergence test), FP64.
- * resid (host, nullable) receives the residual of the last sweep. */
+/* Exactly `sweeps` sweeps from the x passed in (no convergence test), FP64,
+ * in the form o->mode selects.  resid (host, nullable) receives the residual
+ * of the last sweep.  elapsed_ms (host, nullable) receives the time between
+ * HIP events recorded on the library's work stream right before the first
+ * and right after the last sweep kernel (launched as one hipGraph when
+ * o->use_hip_graph), i.e. the sweeps' device time. */
 int pr_iterate(pr_graph *g, double d, const pr_opts *o, const double *p, double *x, int sweeps,
-               double *resid, void *stream);
+               double *resid, double *elapsed_ms, void *stream);
 
 /* ||F(x) - x||_1 for any device vector x (FP64), where F is one exact
  * application of the recurrence above.  Bounds the error of x:

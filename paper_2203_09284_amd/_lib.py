@@ -28,9 +28,9 @@ class PrCsr(ctypes.Structure):
 
 
 class PrPlanOpts(ctypes.Structure):
-    _fields_ = [("light_max", ctypes.c_int), ("medium_max", ctypes.c_int),
-                ("split", ctypes.c_int), ("block_edges", ctypes.c_int),
-                ("with_adjoint", ctypes.c_int)]
+    _fields_ = [("chunk", ctypes.c_int), ("tile_max_row", ctypes.c_int), ("tile_rows", ctypes.c_int),
+                ("steps", ctypes.c_int), ("hot_slots", ctypes.c_int),
+                ("gather_layout", ctypes.c_int), ("with_adjoint", ctypes.c_int)]
 
 
 class PrGraphStats(ctypes.Structure):
@@ -61,7 +61,8 @@ SIGNATURES = {
     "pr_opts_default": (None, [ctypes.POINTER(PrOpts)]),
     "pr_solve": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(PrOpts),
                                 vp, vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
-    "pr_iterate": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts), vp, vp, ctypes.c_int, c_f64p, vp]),
+    "pr_iterate": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts), vp, vp, ctypes.c_int, c_f64p,
+                                  c_f64p, vp]),
     "pr_certificate": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, c_f64p, vp]),
     "pr_solve_batched": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
                                         ctypes.c_int, vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),

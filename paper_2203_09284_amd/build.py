@@ -8,6 +8,7 @@ sources go through the same driver.  The library lands next to this file as
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -36,7 +37,8 @@ def hipcc() -> str:
 
 def _compile(src: str, extra: list[str]) -> str:
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
+    tag = ("." + hashlib.sha1(" ".join(extra).encode()).hexdigest()[:8]) if extra else ""
+    obj = os.path.join(BUILD, src + tag + ".o")
     if src.endswith(".hip"):
         cmd = [hipcc(), *COMMON, *DEVICE, *extra, "-c", path, "-o", obj]
     else:
@@ -47,21 +49,24 @@ def _compile(src: str, extra: list[str]) -> str:
     return obj
 
 
-def build(extra: list[str] | None = None, verbose: bool = False) -> str:
+def build(extra: list[str] | None = None, verbose: bool = False, out: str | None = None) -> str:
+    """Compile and link; `extra` flags go to every compile, `out` overrides the
+    library path (variants built for measurements)."""
     os.makedirs(BUILD, exist_ok=True)
     extra = list(extra or [])
+    lib_path = out or LIB
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib_path + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib_path)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

@@ -24,11 +24,23 @@ void pr_clear_error();
 // ------------------------------------------------------------- constants --
 namespace fpr {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
-constexpr int kWaves = kBlock / 64;  // wavefronts per workgroup
-constexpr int kLightCap = 2048;      // max edges staged in LDS by a thread-per-vertex block
+constexpr int kBlock = 256;          // threads per workgroup of the small kernels
+constexpr int kWaves = kBlock / 64;
+#ifndef FPR_SWEEP_BLOCK
+#define FPR_SWEEP_BLOCK 512
+#endif
+#ifndef FPR_HOT_KB
+#define FPR_HOT_KB 44
+#endif
+constexpr int kSweepBlock = FPR_SWEEP_BLOCK;  // threads per workgroup of the sweep
+constexpr int kSweepWaves = kSweepBlock / 64;
+constexpr int kBatch = 8;                     // loads in flight per lane and batch
+constexpr int kPrefetch = 4;                  // row rounds whose list bounds are loaded up front
+constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather slots, per workgroup
+constexpr int kTileEdges = 512;               // edges of a tile: 8 consecutive per lane
+constexpr int kTileRows = 128;                // rows of a tile at most (row sums staged in LDS)
 
-enum ItemKind : int { kLight = 0, kMedium = 1, kHeavy = 2 };
+enum ItemKind : int { kTile = 0, kRows = 1, kHeavy = 2, kZero = 3 };
 
 // Sweep flags (runtime, uniform across the grid)
 enum SweepFlags : int {
@@ -40,12 +52,9 @@ enum SweepFlags : int {
 
 // Device-resident state of an iteration; one per graph and pull direction.
 struct SweepState {
-  unsigned ticket;    // next work item of the running sweep
-  unsigned finished;  // workgroups that finished the running sweep
   int iter;           // sweeps completed
   int done;           // 1 once the residual is below tol or iter == max_iter
   int max_iter;
-  int pad0;
   double tol;
   double D;      // dangling mass of the current iterate
   double S;      // total mass of the current iterate
@@ -59,20 +68,29 @@ struct SweepState {
 struct DevPlan {
   int64_t n = 0, m = 0;
   uint32_t *rows = nullptr;   // [n] vertex ids in bin order
+  uint32_t *rowpos = nullptr; // [n] gather-layout slot of rows[i]
+  uint32_t *gpos = nullptr;   // [n] gather-layout slot of every vertex
   uint32_t *rptr = nullptr;   // [n+1] edge offsets (bin order)
-  int32_t *idx = nullptr;     // [m] neighbour ids
+  int32_t *idx = nullptr;     // [m] gather-layout slots of the neighbours
   double *w = nullptr;        // [m] edge weights or null
-  int4 *items = nullptr;      // [n_items] {kind, a, b, c}
-  uint32_t *hbase = nullptr;  // [n_heavy] first partial slot of each heavy row
-  double *hpart = nullptr;    // [n_chunks] partial sums of heavy row chunks
-  unsigned *hcnt = nullptr;   // [n_heavy] chunk arrival counters
-  double *item_part = nullptr;  // [n_items * 3] per-item (change, dangling, total)
+  int4 *items = nullptr;      // [n_items] {kTile, tile} | {kRows, first, end, lanes per row} |
+                              // {kHeavy, row, chunk, slot} | {kZero, first, end}
+  int4 *tiles = nullptr;      // [n_tiles] {first row, rows, edges, 0}
+  int32_t *tidx = nullptr;    // [n_tiles * 512] tile edges, lane-transposed: [k][lane] = edge 8*lane+k
+  double *tw = nullptr;       // [n_tiles * 512] their weights, same layout (or null)
+  uint8_t *tmask = nullptr;   // [n_tiles * 64] per lane: bit k set if edge 8*lane+k starts a row
+  int4 *hsplit = nullptr;     // [n_split] rows split into chunks: {row index, first slot, chunks, 0}
+  double *hpart = nullptr;    // [n_chunks] partial sums of the chunks of split rows
+  double *wave_part = nullptr;  // [3][waves] per-wavefront change, dangling mass, total mass
   SweepState *st = nullptr;
   int n_items = 0;
+  int n_tiles = 0;
   int n_heavy = 0;
+  int n_split = 0;
   int n_chunks = 0;
-  int split = 8192;
-  int64_t n_light = 0, n_medium = 0, n_heavy_rows = 0;
+  int chunk = 2048;
+  int n_waves = 0;  // wavefronts of one sweep launch
+  int64_t n_light = 0, n_medium = 0, n_heavy_rows = 0;  // rows in tiles, one wavefront each, chunked
   int64_t e_light = 0, e_medium = 0, e_heavy = 0;
   int64_t bytes = 0;
 };

@@ -1,15 +1,28 @@
 // Device graph and execution plan (pr_graph_create).
 //
-// The plan bins vertices by the length of the list they pull over (in-degree
-// for the forward pull, out-degree for the transposed pull of the adjoint):
-//   light  (<= light_max):  thread per vertex; up to 256 consecutive light
-//                           vertices form one block whose edges (<= block_edges)
-//                           are gathered edge-parallel into LDS first
-//   medium (<= medium_max): wavefront per vertex; groups of rows per workgroup
-//   heavy  (>  medium_max): workgroup per chunk of `split` edges; the last
-//                           chunk to finish combines the partial sums in order
-// The neighbour lists are copied in bin order (heavy, medium, light; vertex
-// ids ascending inside a bin) so every work item reads one contiguous range.
+// The sweep pulls, for every vertex, over a list (in-edges for the forward
+// pull, out-edges for the transposed pull of the adjoint).  Every work item
+// runs on one wavefront.  The plan bins vertices by list length L:
+//   L = 0            zero rows: lane per vertex, no gathers (the update only).
+//   1 <= L <= tmax   tiles: consecutive rows packed into 512-edge tiles, at
+//                    most 128 rows each.  Lane l takes edges 8l..8l+7 of the
+//                    tile; the tile's edge ids are stored lane-transposed so
+//                    each load instruction reads 256 contiguous bytes, with a
+//                    bit per edge marking row starts.  A segmented scan
+//                    across the lanes completes rows that span lanes.
+//   tmax < L <= chunk  a wavefront per vertex, lanes striding the list.
+//   L > chunk        hubs: each chunk of `chunk` edges is one item; the
+//                    chunk sums go to per-chunk slots and the sweep's
+//                    finalize kernel adds them in chunk order.
+// Rows are laid out hubs, one-wavefront rows, tile rows, zero rows (vertex ids
+// ascending inside each bin); that is also the order work items run in.
+//
+// Gather layout: the array the pull gathers from (contributions forward,
+// adjoint values backward) is stored with vertices sorted by how often they
+// are gathered (descending, ties by id), and the neighbour lists hold those
+// slots.  On power-law graphs the few vertices that feed most edges then pack
+// into the first slots, which each sweep workgroup keeps in LDS.  Values are
+// unchanged; only addresses move.
 #include <math.h>
 #include <string.h>
 
@@ -22,10 +35,12 @@ using namespace fpr;
 
 extern "C" void pr_plan_opts_default(pr_plan_opts *o) {
   if (!o) return;
-  o->light_max = 32;
-  o->medium_max = 2048;
-  o->split = 8192;
-  o->block_edges = kLightCap;
+  o->chunk = 2048;
+  o->tile_max_row = kTileEdges;
+  o->tile_rows = kTileRows;
+  o->steps = 4;
+  o->hot_slots = -1;
+  o->gather_layout = 1;
   o->with_adjoint = 0;
 }
 
@@ -56,89 +71,147 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
                       const double *w, const pr_plan_opts &o) {
   P.n = n;
   P.m = ptr[n];
-  P.split = o.split;
-  std::vector<uint32_t> heavy, medium, light;
+  P.chunk = o.chunk;
+  const int64_t m = P.m;
+  // bins: 0 hubs, 1 one-wavefront rows, 2 tile rows, 3 zero rows
+  std::vector<uint32_t> bins[4];
   for (int64_t v = 0; v < n; ++v) {
     int64_t L = ptr[v + 1] - ptr[v];
-    if (L <= o.light_max) light.push_back((uint32_t)v);
-    else if (L <= o.medium_max) medium.push_back((uint32_t)v);
-    else heavy.push_back((uint32_t)v);
+    int b = L > o.chunk ? 0 : L > o.tile_max_row ? 1 : L > 0 ? 2 : 3;
+    bins[b].push_back((uint32_t)v);
   }
   std::vector<uint32_t> rows;
   rows.reserve(n);
-  rows.insert(rows.end(), heavy.begin(), heavy.end());
-  rows.insert(rows.end(), medium.begin(), medium.end());
-  rows.insert(rows.end(), light.begin(), light.end());
+  for (auto &b : bins) rows.insert(rows.end(), b.begin(), b.end());
   std::vector<uint32_t> rptr(n + 1);
   rptr[0] = 0;
   for (int64_t i = 0; i < n; ++i) {
     uint32_t v = rows[i];
     rptr[i + 1] = rptr[i] + (uint32_t)(ptr[v + 1] - ptr[v]);
   }
-  const int64_t m = P.m;
+  // gather layout: slot of each vertex
+  std::vector<uint32_t> pos(n);
+  if (o.gather_layout) {
+    std::vector<uint32_t> freq(n, 0), order(n);
+    for (int64_t e = 0; e < m; ++e) freq[nbr[e]]++;
+    for (int64_t v = 0; v < n; ++v) order[v] = (uint32_t)v;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return freq[a] > freq[b]; });
+    for (int64_t k = 0; k < n; ++k) pos[order[k]] = (uint32_t)k;
+  } else {
+    for (int64_t v = 0; v < n; ++v) pos[v] = (uint32_t)v;
+  }
+  std::vector<uint32_t> rowpos(n);
+  for (int64_t i = 0; i < n; ++i) rowpos[i] = pos[rows[i]];
   std::vector<int32_t> idx(m);
   std::vector<double> wv(w ? m : 0);
   for (int64_t i = 0; i < n; ++i) {
     uint32_t v = rows[i];
     int64_t L = ptr[v + 1] - ptr[v];
-    memcpy(&idx[rptr[i]], nbr + ptr[v], sizeof(int32_t) * L);
+    for (int64_t k = 0; k < L; ++k) idx[rptr[i] + k] = (int32_t)pos[nbr[ptr[v] + k]];
     if (w) memcpy(&wv[rptr[i]], w + ptr[v], sizeof(double) * L);
   }
 
-  // work items, in ticket order: heavy chunks, medium groups, light blocks
-  std::vector<int4> items;
-  std::vector<uint32_t> hbase;
+  // work items in launch order: hub chunks, one-wavefront rows, tiles, zero rows
+  std::vector<int4> items, hsplit, tiles;
+  std::vector<int32_t> tidx;
+  std::vector<double> tw;
+  std::vector<uint8_t> tmask;
   int64_t i = 0, chunks = 0;
-  for (size_t h = 0; h < heavy.size(); ++h, ++i) {
+  for (size_t h = 0; h < bins[0].size(); ++h, ++i) {
     int64_t L = rptr[i + 1] - rptr[i];
-    int64_t nch = (L + o.split - 1) / o.split;
-    hbase.push_back((uint32_t)chunks);
-    for (int64_t c = 0; c < nch; ++c) items.push_back(make_int4(kHeavy, (int)i, (int)c, (int)h));
+    int64_t nch = (L + o.chunk - 1) / o.chunk;
+    int slot = (int)chunks;
+    hsplit.push_back(make_int4((int)i, slot, (int)nch, 0));
     chunks += nch;
+    for (int64_t c = 0; c < nch; ++c) items.push_back(make_int4(kHeavy, (int)i, (int)c, slot));
     P.e_heavy += L;
   }
-  const int64_t med_end = i + (int64_t)medium.size();
-  while (i < med_end) {
-    int64_t i0 = i, edges = 0;
-    while (i < med_end && i - i0 < 64 && edges < 8192) {
-      edges += rptr[i + 1] - rptr[i];
-      ++i;
-    }
-    items.push_back(make_int4(kMedium, (int)i0, (int)i, 0));
-    P.e_medium += edges;
+  P.n_heavy_rows = (int64_t)bins[0].size();
+  {
+    const int64_t end = i + (int64_t)bins[1].size();
+    for (int64_t i0 = i; i0 < end; i0 += o.steps)
+      items.push_back(make_int4(kRows, (int)i0, (int)std::min(end, i0 + o.steps), 64));
+    P.n_medium = end - i;
+    P.e_medium = rptr[end] - rptr[i];
+    i = end;
   }
-  while (i < n) {
-    int64_t i0 = i, edges = 0;
-    while (i < n && i - i0 < kBlock) {
-      int64_t L = rptr[i + 1] - rptr[i];
-      if (edges + L > o.block_edges) break;
-      edges += L;
-      ++i;
+  {
+    const int64_t end = i + (int64_t)bins[2].size();
+    P.n_light = end - i;
+    P.e_light = rptr[end] - rptr[i];
+    while (i < end) {
+      const int64_t r0 = i;
+      int64_t edges = 0;
+      while (i < end && i - r0 < o.tile_rows) {
+        const int64_t L = rptr[i + 1] - rptr[i];
+        if (edges + L > kTileEdges) break;
+        edges += L;
+        ++i;
+      }
+      const int t = (int)tiles.size();
+      tiles.push_back(make_int4((int)r0, (int)(i - r0), (int)edges, 0));
+      items.push_back(make_int4(kTile, t, 0, 0));
+      tidx.resize((size_t)(t + 1) * kTileEdges, 0);
+      if (w) tw.resize((size_t)(t + 1) * kTileEdges, 0.0);
+      tmask.resize((size_t)(t + 1) * 64, 0);
+      int64_t j = 0;
+      for (int64_t r = r0; r < i; ++r) {
+        tmask[(size_t)t * 64 + (j >> 3)] |= (uint8_t)(1u << (j & 7));
+        for (uint32_t e = rptr[r]; e < rptr[r + 1]; ++e, ++j) {
+          const size_t at = (size_t)t * kTileEdges + (size_t)(j & 7) * 64 + (size_t)(j >> 3);
+          tidx[at] = idx[e];
+          if (w) tw[at] = wv[e];
+        }
+      }
     }
-    items.push_back(make_int4(kLight, (int)i0, (int)i, 0));
-    P.e_light += edges;
   }
-  P.n_light = (int64_t)light.size();
-  P.n_medium = (int64_t)medium.size();
-  P.n_heavy_rows = (int64_t)heavy.size();
+  {
+    const int64_t end = i + (int64_t)bins[3].size();
+    for (int64_t i0 = i; i0 < end; i0 += 256)
+      items.push_back(make_int4(kZero, (int)i0, (int)std::min(end, i0 + 256), 0));
+    P.n_light += end - i;
+    i = end;
+  }
   P.n_items = (int)items.size();
-  P.n_heavy = (int)heavy.size();
+  P.n_tiles = (int)tiles.size();
+  P.n_heavy = (int)bins[0].size();
+  P.n_split = (int)hsplit.size();
   P.n_chunks = (int)chunks;
+
+  // host-side check of what the kernels assume
+  for (const int4 &it : items) {
+    bool ok = false;
+    if (it.x == kHeavy)
+      ok = it.y >= 0 && it.y < n && it.w >= 0 && it.w + it.z < chunks &&
+           (int64_t)it.z * o.chunk < (int64_t)(rptr[it.y + 1] - rptr[it.y]);
+    else if (it.x == kRows || it.x == kZero)
+      ok = it.y >= 0 && it.y < it.z && it.z <= n;
+    else if (it.x == kTile) {
+      const int4 d = tiles[it.y];
+      ok = d.x >= 0 && d.y >= 1 && d.y <= kTileRows && d.x + d.y <= n && d.z >= d.y && d.z <= kTileEdges &&
+           (int64_t)(rptr[d.x + d.y] - rptr[d.x]) == d.z;
+    }
+    if (!ok) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
+  }
 
   int64_t before = g->device_bytes;
   int rc;
   if ((rc = upload(g, &P.rows, rows.data(), rows.size()))) return rc;
+  if ((rc = upload(g, &P.rowpos, rowpos.data(), rowpos.size()))) return rc;
+  if ((rc = upload(g, &P.gpos, pos.data(), pos.size()))) return rc;
   if ((rc = upload(g, &P.rptr, rptr.data(), rptr.size()))) return rc;
   if ((rc = upload(g, &P.idx, idx.data(), idx.size()))) return rc;
   if (w && (rc = upload(g, &P.w, wv.data(), wv.size()))) return rc;
   if ((rc = upload(g, &P.items, items.data(), items.size()))) return rc;
-  if ((rc = upload(g, &P.hbase, hbase.data(), hbase.size()))) return rc;
+  if ((rc = upload(g, &P.hsplit, hsplit.data(), hsplit.size()))) return rc;
+  if ((rc = upload(g, &P.tiles, tiles.data(), tiles.size()))) return rc;
+  if ((rc = upload(g, &P.tidx, tidx.data(), tidx.size()))) return rc;
+  if (w && (rc = upload(g, &P.tw, tw.data(), tw.size()))) return rc;
+  if ((rc = upload(g, &P.tmask, tmask.data(), tmask.size()))) return rc;
   if ((rc = fpr_dev_alloc(g, (void **)&P.hpart, sizeof(double) * (chunks > 0 ? chunks : 1)))) return rc;
-  if ((rc = fpr_dev_alloc(g, (void **)&P.hcnt, sizeof(unsigned) * (P.n_heavy > 0 ? P.n_heavy : 1))))
-    return rc;
-  PR_HIP(hipMemset(P.hcnt, 0, sizeof(unsigned) * (P.n_heavy > 0 ? P.n_heavy : 1)));
-  if ((rc = fpr_dev_alloc(g, (void **)&P.item_part, sizeof(double) * 3 * (P.n_items > 0 ? P.n_items : 1))))
-    return rc;
+  P.n_waves = g->grid * kSweepWaves;
+  if ((rc = fpr_dev_alloc(g, (void **)&P.wave_part, sizeof(double) * 3 * (size_t)P.n_waves))) return rc;
   if ((rc = fpr_dev_alloc(g, (void **)&P.st, sizeof(SweepState)))) return rc;
   PR_HIP(hipMemset(P.st, 0, sizeof(SweepState)));
   P.bytes = g->device_bytes - before;
@@ -176,12 +249,12 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
   pr_plan_opts o;
   pr_plan_opts_default(&o);
   if (opts) o = *opts;
-  if (o.block_edges < 1 || o.block_edges > kLightCap || o.light_max < 0 ||
-      o.light_max > o.block_edges || o.medium_max <= o.light_max || o.split < kBlock)
+  if (o.chunk < 64 || o.chunk > (1 << 20) || o.tile_max_row < 0 || o.tile_max_row > kTileEdges ||
+      o.tile_max_row > o.chunk || o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 ||
+      o.steps > 64)
     return pr_fail(PR_EINVAL,
-                   "pr_graph_create: need 0 <= light_max <= block_edges <= %d, medium_max > "
-                   "light_max, split >= %d",
-                   kLightCap, kBlock);
+                   "pr_graph_create: need 64 <= chunk <= 2^20, 0 <= tile_max_row <= min(512, chunk), "
+                   "1 <= tile_rows <= 128, 1 <= steps <= 64");
   int dev_count = 0;
   hipError_t he = hipGetDeviceCount(&dev_count);
   if (he != hipSuccess || dev_count < 1)
@@ -199,40 +272,39 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
     return pr_fail(PR_EDEVICE, "pr_graph_create: cannot query the current device");
   }
   g->n_cu = prop.multiProcessorCount;
-
-  rc = [&]() -> int {
-  // 1 / W_v, W_v summed over out-edges in out order
-  const int64_t n = g->n;
-  int rc2;
-  std::vector<double> inv_w(n);
-  for (int64_t v = 0; v < n; ++v) {
-    double W;
-    if (csr->out_w) {
-      W = 0.0;
-      for (int64_t e = csr->out_ptr[v]; e < csr->out_ptr[v + 1]; ++e) W += csr->out_w[e];
-    } else {
-      W = (double)csr->out_deg[v];
-    }
-    inv_w[v] = W > 0.0 ? 1.0 / W : 0.0;
-    if (W == 0.0) g->n_dangling++;
-  }
-  if ((rc2 = upload(g, &g->inv_w, inv_w.data(), inv_w.size()))) return rc2;
-  if ((rc2 = build_plan(g, g->fwd, n, csr->in_ptr, csr->in_src, csr->in_w, o))) return rc2;
-  if (o.with_adjoint) {
-    if ((rc2 = build_plan(g, g->adj, n, csr->out_ptr, csr->out_dst, csr->out_w, o))) return rc2;
-    std::vector<uint32_t> op(n + 1);
-    for (int64_t v = 0; v <= n; ++v) op[v] = (uint32_t)csr->out_ptr[v];
-    if ((rc2 = upload(g, &g->out_ptr, op.data(), op.size()))) return rc2;
-    g->has_adj = true;
-  }
-  if (hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming) != hipSuccess ||
-      hipHostMalloc((void **)&g->host_st, sizeof(SweepState)) != hipSuccess)
-    return pr_fail(PR_EDEVICE, "pr_graph_create: stream/event/pinned allocation failed");
-  if ((rc2 = fpr_dev_alloc(g, (void **)&g->red_tmp, sizeof(double) * 4096))) return rc2;
   g->grid = fpr_grid_for(g);
-  return PR_OK;
+  rc = [&]() -> int {
+    // 1 / W_v, W_v summed over out-edges in out order
+    const int64_t n = g->n;
+    int rc2;
+    std::vector<double> inv_w(n);
+    for (int64_t v = 0; v < n; ++v) {
+      double W;
+      if (csr->out_w) {
+        W = 0.0;
+        for (int64_t e = csr->out_ptr[v]; e < csr->out_ptr[v + 1]; ++e) W += csr->out_w[e];
+      } else {
+        W = (double)csr->out_deg[v];
+      }
+      inv_w[v] = W > 0.0 ? 1.0 / W : 0.0;
+      if (W == 0.0) g->n_dangling++;
+    }
+    if ((rc2 = upload(g, &g->inv_w, inv_w.data(), inv_w.size()))) return rc2;
+    if ((rc2 = build_plan(g, g->fwd, n, csr->in_ptr, csr->in_src, csr->in_w, o))) return rc2;
+    if (o.with_adjoint) {
+      if ((rc2 = build_plan(g, g->adj, n, csr->out_ptr, csr->out_dst, csr->out_w, o))) return rc2;
+      std::vector<uint32_t> op(n + 1);
+      for (int64_t v = 0; v <= n; ++v) op[v] = (uint32_t)csr->out_ptr[v];
+      if ((rc2 = upload(g, &g->out_ptr, op.data(), op.size()))) return rc2;
+      g->has_adj = true;
+    }
+    if (hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&g->host_st, sizeof(SweepState)) != hipSuccess)
+      return pr_fail(PR_EDEVICE, "pr_graph_create: stream/event/pinned allocation failed");
+    if ((rc2 = fpr_dev_alloc(g, (void **)&g->red_tmp, sizeof(double) * 4096))) return rc2;
+    return PR_OK;
   }();
   if (rc != PR_OK) {
     destroy(g);

@@ -4,21 +4,28 @@
 //  * Jacobi (Section 3, Algorithm 1): contributions are double-buffered; sweep
 //    k reads c_k and writes c_{k+1}, so every vertex sees the previous sweep.
 //  * Fused (Section 4, Algorithm 2; Eq. 9): one contribution array, updated in
-//    place right after each vertex's rank; work items are claimed in ticket
-//    order, so items that start later read the contributions written by items
-//    that finished earlier in the same sweep (the paper's parallel variant,
-//    Section 6.3, an asynchronous Gauss-Seidel iteration).  Reads and writes
-//    of the shared array are relaxed atomics: a reader gets either the old or
-//    the new value, never a torn one.
+//    place right after each vertex's rank; work items run one per workgroup
+//    in dispatch order, so items that start later read the contributions
+//    written by items that finished earlier in the same sweep (the paper's
+//    parallel variant, Section 6.3, an asynchronous Gauss-Seidel iteration).
+//    Reads and writes of the shared array are relaxed atomics: a reader gets
+//    either the old or the new value, never a torn one.
 //
 // Per vertex u the update is Eq. 1 with the dangling mass D spread uniformly,
 //     x_u <- (1-d) p_u s + d (sum_{v->u} w c_v + D/n),   c_u <- x_u / W_u,
 // where s = 1, except in the fused mass-scaled mode where s is the previous
 // sweep's total mass (see the mode flag kFlagScaled).  The per-vertex change,
 // the new dangling mass and the new total mass are reduced in FP64 per work
-// item; the last workgroup to finish sums the item partials in item order
-// (deterministic), sets the residual, the iteration count and the stop flag,
-// and resets the ticket, so the next launch needs no host work.
+// item; a one-workgroup finalize kernel after each sweep sums the item
+// partials in a fixed order (deterministic), completes rows that were split
+// across workgroups, and sets the residual, the iteration count and the stop
+// flag, so the next sweep needs no host work.  The hot kernel has no fences
+// and no atomics besides the relaxed loads/stores of the fused form.
+//
+// Work layout: a few workgroups per CU; each keeps the hottest slots of the
+// gathered array in LDS and its wavefronts take work items round-robin; an
+// item is a tile of short rows, a few long rows (a wavefront each), one chunk
+// of a hub's list, or a run of vertices without in-edges.
 //
 // FP32 storage (ranks and contributions) sums with Neumaier compensation per
 // lane and TwoSum when lanes combine; the rank update and every reduction are
@@ -34,9 +41,13 @@
 using namespace fpr;
 
 // Memory scope of the relaxed atomic loads/stores of the shared contribution
-// array in the fused form.
+// array in the fused form.  Workgroup scope compiles to ordinary cached
+// loads/stores (no tearing for naturally aligned 4/8-byte values); a reader
+// in another workgroup may then see a value up to one sweep old, since kernel
+// boundaries make every write visible.  Agent scope (-DFPR_FUSED_SCOPE=
+// __HIP_MEMORY_SCOPE_AGENT) forces device-coherent accesses instead.
 #ifndef FPR_FUSED_SCOPE
-#define FPR_FUSED_SCOPE __HIP_MEMORY_SCOPE_AGENT
+#define FPR_FUSED_SCOPE __HIP_MEMORY_SCOPE_WORKGROUP
 #endif
 
 namespace {
@@ -52,9 +63,18 @@ struct LaneSum<double> {
   double s = 0.0;
   __device__ __forceinline__ void add(double v) { s += v; }
   __device__ __forceinline__ double value() const { return s; }
-  __device__ __forceinline__ void wave_reduce() {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  __device__ __forceinline__ LaneSum shfl_up(int off) const {
+    LaneSum r;
+    r.s = __shfl_up(s, off, 64);
+    return r;
+  }
+  // this = earlier + this
+  __device__ __forceinline__ void add_before(const LaneSum &earlier) { s = earlier.s + s; }
+  // this = this + later
+  __device__ __forceinline__ void combine_with(const LaneSum &later) { s = s + later.s; }
+  // butterfly over the lpr-lane group (lpr a power of two, uniform in the wavefront)
+  __device__ __forceinline__ void group_reduce(int lpr) {
+    for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   }
 };
 
@@ -69,6 +89,18 @@ struct LaneSum<float> {
     s = t;
   }
   __device__ __forceinline__ double value() const { return (double)s + (double)c; }
+  __device__ __forceinline__ LaneSum shfl_up(int off) const {
+    LaneSum r;
+    r.s = __shfl_up(s, off, 64);
+    r.c = __shfl_up(c, off, 64);
+    return r;
+  }
+  __device__ __forceinline__ void add_before(const LaneSum &earlier) {
+    LaneSum e = earlier;
+    e.combine(s, c);
+    *this = e;
+  }
+  __device__ __forceinline__ void combine_with(const LaneSum &later) { combine(later.s, later.c); }
   // TwoSum of the leading parts, compensations added
   __device__ __forceinline__ void combine(float s2, float c2) {
 #pragma clang fp contract(off)
@@ -78,9 +110,8 @@ struct LaneSum<float> {
     c = c + c2 + err;
     s = t;
   }
-  __device__ __forceinline__ void wave_reduce() {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+  __device__ __forceinline__ void group_reduce(int lpr) {
+    for (int off = lpr >> 1; off > 0; off >>= 1) {
       float s2 = __shfl_xor(s, off, 64);
       float c2 = __shfl_xor(c, off, 64);
       combine(s2, c2);
@@ -122,16 +153,23 @@ __device__ __forceinline__ void st_c(T *p, T v) {
 // ------------------------------------------------------------ arguments --
 
 template <typename T>
+constexpr int kHotSlots = kHotBytes / (int)sizeof(T);
+
+template <typename T>
 struct SweepArgs {
   const uint32_t *rows;
+  const uint32_t *rowpos;
   const uint32_t *rptr;
   const int32_t *idx;
   const double *w;
   const int4 *items;
-  const uint32_t *hbase;
+  const int4 *tiles;
+  const int32_t *tidx;
+  const double *tw;
+  const uint8_t *tmask;
+  const int4 *hsplit;
   double *hpart;
-  unsigned *hcnt;
-  double *item_part;
+  double *wave_part;
   SweepState *st;
   const double *inv_w;
   const double *p;
@@ -142,13 +180,17 @@ struct SweepArgs {
   double d;
   double inv_n;
   int n_items;
-  int split;
+  int n_split;
+  int n_waves;
+  int chunk;
+  int hot;  // gather slots staged in LDS (<= kHotSlots<T>)
   int flags;
 };
 
 template <typename T>
 struct Ctx {
   const uint32_t *rows;
+  const uint32_t *rowpos;
   const uint32_t *rptr;
   const int32_t *idx;
   const double *w;
@@ -161,238 +203,19 @@ struct Ctx {
   double d;
   double dterm;  // D / n, 0 in leak mode
   double inv_n;
+  int hot;
   int flags;
 };
 
+// The iterate's state as of the start of the sweep (written by the previous
+// finalize kernel) and the buffers it selects.
 template <typename T, bool FUSED>
-__device__ __forceinline__ void update_vertex(const Ctx<T> &C, uint32_t u, double s, Red &red) {
-  const double xo = (double)C.x[u];
-  const double pu = (C.flags & kFlagUniformP) ? C.inv_n : C.p[u];
-  const double xn = C.tele * pu + C.d * (s + C.dterm);
-  const T xs = (T)xn;
-  C.x[u] = xs;
-  const double xd = (double)xs;
-  const double iw = C.inv_w[u];
-  if (iw != 0.0) st_c<FUSED>(C.cout + u, (T)(xd * iw));
-  else red.dang += xd;
-  const double dl = fabs(xd - xo);
-  red.chg = (C.flags & kFlagLinf) ? fmax(red.chg, dl) : red.chg + dl;
-  red.tot += xd;
-}
-
-// ---------------------------------------------------- work item kinds --
-
-// Thread per vertex: the block's edges (contiguous, <= kLightCap) are
-// gathered edge-parallel into LDS, then each thread sums its vertex's slice.
-template <typename T, bool FUSED, bool WEIGHTED>
-__device__ __forceinline__ void light_block(const Ctx<T> &C, int i0, int i1, T *lds, Red &red) {
-  const uint32_t eb = C.rptr[i0];
-  const int ne = (int)(C.rptr[i1] - eb);
-  constexpr int K = kLightCap / kBlock;
-  int32_t src[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int j = threadIdx.x + k * kBlock;
-    src[k] = j < ne ? C.idx[eb + j] : 0;
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int j = threadIdx.x + k * kBlock;
-    if (j < ne) {
-      T v = ld_c<FUSED>(C.cin + src[k]);
-      if constexpr (WEIGHTED) v = (T)((double)v * C.w[eb + j]);
-      lds[j] = v;
-    }
-  }
-  __syncthreads();
-  const int r = i0 + (int)threadIdx.x;
-  if (r < i1) {
-    const int a = (int)(C.rptr[r] - eb), b = (int)(C.rptr[r + 1] - eb);
-    LaneSum<T> acc;
-    for (int j = a; j < b; ++j) acc.add(lds[j]);
-    update_vertex<T, FUSED>(C, C.rows[r], acc.value(), red);
-  }
-  __syncthreads();
-}
-
-// Wavefront per vertex: 64 lanes stride over the vertex's edges.
-template <typename T, bool FUSED, bool WEIGHTED>
-__device__ __forceinline__ void medium_group(const Ctx<T> &C, int i0, int i1, Red &red) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int r = i0 + wave; r < i1; r += kWaves) {
-    const uint32_t eb = C.rptr[r];
-    const int L = (int)(C.rptr[r + 1] - eb);
-    LaneSum<T> acc;
-    for (int j0 = 0; j0 < L; j0 += 4 * 64) {
-      int32_t s[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int j = j0 + lane + 64 * k;
-        s[k] = j < L ? C.idx[eb + j] : 0;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int j = j0 + lane + 64 * k;
-        if (j < L) {
-          T v = ld_c<FUSED>(C.cin + s[k]);
-          if constexpr (WEIGHTED) v = (T)((double)v * C.w[eb + j]);
-          acc.add(v);
-        }
-      }
-    }
-    acc.wave_reduce();
-    if (lane == 0) update_vertex<T, FUSED>(C, C.rows[r], acc.value(), red);
-  }
-}
-
-// Workgroup per chunk of a long row; chunk partials combined in order by the
-// last chunk to arrive.
-template <typename T, bool FUSED, bool WEIGHTED>
-__device__ __forceinline__ void heavy_chunk(const Ctx<T> &C, const SweepArgs<T> &a, int i, int c,
-                                            int h, Red &red) {
-  __shared__ double s_part[kWaves];
-  const uint32_t rb = C.rptr[i];
-  const int L = (int)(C.rptr[i + 1] - rb);
-  const int split = a.split;
-  const uint32_t eb = rb + (uint32_t)c * (uint32_t)split;
-  const int ne = min(split, L - c * split);
-  LaneSum<T> acc;
-  for (int j0 = 0; j0 < ne; j0 += 8 * kBlock) {
-    int32_t s[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int j = j0 + (int)threadIdx.x + kBlock * k;
-      s[k] = j < ne ? C.idx[eb + j] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int j = j0 + (int)threadIdx.x + kBlock * k;
-      if (j < ne) {
-        T v = ld_c<FUSED>(C.cin + s[k]);
-        if constexpr (WEIGHTED) v = (T)((double)v * C.w[eb + j]);
-        acc.add(v);
-      }
-    }
-  }
-  acc.wave_reduce();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) s_part[wave] = acc.value();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sum = 0.0;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) sum += s_part[k];
-    const int nch = (L + split - 1) / split;
-    if (nch == 1) {
-      update_vertex<T, FUSED>(C, C.rows[i], sum, red);
-    } else {
-      const uint32_t base = a.hbase[h];
-      a.hpart[base + c] = sum;
-      __threadfence();
-      const unsigned prev = atomicAdd(&a.hcnt[h], 1u);
-      if (prev == (unsigned)(nch - 1)) {
-        __threadfence();
-        double tot = 0.0;
-        for (int k = 0; k < nch; ++k) tot += __hip_atomic_load(&a.hpart[base + k], __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-        a.hcnt[h] = 0u;
-        update_vertex<T, FUSED>(C, C.rows[i], tot, red);
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// Block reduction of a thread's Red; thread 0 writes the item partial.
-__device__ __forceinline__ void store_item_partial(Red &red, double *dst, bool linf) {
-  __shared__ double s_red[3][kWaves];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double chg = linf ? wave_max(red.chg) : wave_sum(red.chg);
-  double dang = wave_sum(red.dang);
-  double tot = wave_sum(red.tot);
-  if (lane == 0) {
-    s_red[0][wave] = chg;
-    s_red[1][wave] = dang;
-    s_red[2][wave] = tot;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = s_red[0][0], b = s_red[1][0], c = s_red[2][0];
-#pragma unroll
-    for (int k = 1; k < kWaves; ++k) {
-      a = linf ? fmax(a, s_red[0][k]) : a + s_red[0][k];
-      b += s_red[1][k];
-      c += s_red[2][k];
-    }
-    dst[0] = a;
-    dst[1] = b;
-    dst[2] = c;
-  }
-  __syncthreads();
-}
-
-// Sum the per-item partials in item order (fixed split over the threads, fixed
-// tree), then publish the sweep result.  Runs in the last workgroup.
-template <typename T>
-__device__ void finalize_sweep(const SweepArgs<T> &a, double S_old, double *scratch) {
-  double(*s_red)[kBlock] = reinterpret_cast<double(*)[kBlock]>(scratch);
-  const bool linf = (a.flags & kFlagLinf) != 0;
-  const int n = a.n_items;
-  const int per = (n + kBlock - 1) / kBlock;
-  const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
-  double chg = 0.0, dang = 0.0, tot = 0.0;
-  for (int i = lo; i < hi; ++i) {
-    const double *q = a.item_part + 3 * (size_t)i;
-    const double c0 = __hip_atomic_load(q + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    chg = linf ? fmax(chg, c0) : chg + c0;
-    dang += __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    tot += __hip_atomic_load(q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  s_red[0][threadIdx.x] = chg;
-  s_red[1][threadIdx.x] = dang;
-  s_red[2][threadIdx.x] = tot;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      s_red[0][threadIdx.x] = linf ? fmax(s_red[0][threadIdx.x], s_red[0][threadIdx.x + s])
-                                   : s_red[0][threadIdx.x] + s_red[0][threadIdx.x + s];
-      s_red[1][threadIdx.x] += s_red[1][threadIdx.x + s];
-      s_red[2][threadIdx.x] += s_red[2][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    SweepState *st = a.st;
-    const double raw = s_red[0][0];
-    const double Sn = s_red[2][0];
-    double resid = raw;
-    if (a.flags & kFlagScaled) resid = (raw + fabs(Sn - S_old)) / S_old;
-    st->raw = raw;
-    st->resid = resid;
-    st->D = s_red[1][0];
-    st->S = Sn;
-    const int it = st->iter + 1;
-    st->iter = it;
-    if (a.trace) a.trace[it - 1] = resid;
-    if (!(resid >= st->tol) || it >= st->max_iter) st->done = 1;
-    st->ticket = 0u;
-    st->finished = 0u;
-  }
-}
-
-static_assert(kLightCap * sizeof(float) >= 3 * kBlock * sizeof(double), "LDS reuse by the final reduction");
-
-template <typename T, bool FUSED, bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> a) {
-  __shared__ __attribute__((aligned(16))) T lds[kLightCap];
-  __shared__ int s_item;
-  __shared__ int s_last;
-  SweepState *st = a.st;
-  if (st->done) return;
+__device__ __forceinline__ Ctx<T> make_ctx(const SweepArgs<T> &a, const SweepState *st) {
   const int it = st->iter;
   const double S = st->S, D = st->D;
   Ctx<T> C;
   C.rows = a.rows;
+  C.rowpos = a.rowpos;
   C.rptr = a.rptr;
   C.idx = a.idx;
   C.w = a.w;
@@ -408,46 +231,418 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> a) {
   }
   C.d = a.d;
   C.inv_n = a.inv_n;
+  C.hot = a.hot;
   C.flags = a.flags;
   C.tele = (1.0 - a.d) * ((a.flags & kFlagScaled) ? S : 1.0);
   C.dterm = (a.flags & kFlagLeak) ? 0.0 : D * a.inv_n;
-  const bool linf = (a.flags & kFlagLinf) != 0;
+  return C;
+}
 
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(&st->ticket, 1u);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= a.n_items) break;
-    const int4 wi = a.items[item];
-    Red red;
-    if (wi.x == kLight) light_block<T, FUSED, WEIGHTED>(C, wi.y, wi.z, lds, red);
-    else if (wi.x == kMedium) medium_group<T, FUSED, WEIGHTED>(C, wi.y, wi.z, red);
-    else heavy_chunk<T, FUSED, WEIGHTED>(C, a, wi.y, wi.z, wi.w, red);
-    store_item_partial(red, a.item_part + 3 * (size_t)item, linf);
+// Row-table entry i: vertex u = rows[i], its gather slot rowpos[i].  In the
+// fused form the workgroup's LDS copy of a hot slot is refreshed as well, so
+// later wavefronts of the workgroup read the new value.
+template <typename T, bool FUSED>
+__device__ __forceinline__ void update_vertex(const Ctx<T> &C, T *hot, int i, double s, Red &red) {
+  const uint32_t u = C.rows[i];
+  const double xo = (double)C.x[u];
+  const double pu = (C.flags & kFlagUniformP) ? C.inv_n : C.p[u];
+  const double xn = C.tele * pu + C.d * (s + C.dterm);
+  const T xs = (T)xn;
+  C.x[u] = xs;
+  const double xd = (double)xs;
+  const double iw = C.inv_w[u];
+  if (iw != 0.0) {
+    const uint32_t slot = C.rowpos[i];
+    const T cv = (T)(xd * iw);
+    st_c<FUSED>(C.cout + slot, cv);
+    if (FUSED && hot != nullptr && slot < (uint32_t)C.hot) hot[slot] = cv;
+  } else {
+    red.dang += xd;
   }
+  const double dl = fabs(xd - xo);
+  red.chg = (C.flags & kFlagLinf) ? fmax(red.chg, dl) : red.chg + dl;
+  red.tot += xd;
+}
 
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->finished, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+// The rank update with its operands already loaded (see update_vertex).
+template <typename T, bool FUSED>
+__device__ __forceinline__ void update_loaded(const Ctx<T> &C, T *hot, uint32_t u, uint32_t slot,
+                                              double xo, double iw, double pu, double s, Red &red) {
+  const double xn = C.tele * pu + C.d * (s + C.dterm);
+  const T xs = (T)xn;
+  C.x[u] = xs;
+  const double xd = (double)xs;
+  if (iw != 0.0) {
+    const T cv = (T)(xd * iw);
+    st_c<FUSED>(C.cout + slot, cv);
+    if (FUSED && hot != nullptr && slot < (uint32_t)C.hot) hot[slot] = cv;
+  } else {
+    red.dang += xd;
+  }
+  const double dl = fabs(xd - xo);
+  red.chg = (C.flags & kFlagLinf) ? fmax(red.chg, dl) : red.chg + dl;
+  red.tot += xd;
+}
+
+// Gather of slot s (always a valid slot).  Both the LDS copy and the global
+// array are read unconditionally, at slot 0 of the side that is not used, and
+// the value is selected: this keeps the gathers of a batch independent (no
+// branch, no address-space select that would turn them into flat loads).
+#ifndef FPR_GATHER_MASKED
+#define FPR_GATHER_MASKED 1
+#endif
+template <typename T, bool FUSED>
+__device__ __forceinline__ T gather(const Ctx<T> &C, const T *hot, int32_t s) {
+  const bool h = s < C.hot;
+  const T vh = hot[h ? s : 0];
+#if FPR_GATHER_MASKED
+  // global load only on the lanes whose slot is not in LDS
+  T vg = vh;
+  if (!h) vg = ld_c<FUSED>(C.cin + s);
+  return vg;
+#else
+  const T vg = ld_c<FUSED>(C.cin + (h ? 0 : s));
+  return h ? vh : vg;
+#endif
+}
+
+// ---------------------------------------------------- work item kinds --
+
+// A wavefront works on 64/lpr consecutive rows at a time, lpr lanes per row;
+// each lane issues up to kBatch index loads, then kBatch gathers, per batch.
+// The lpr partial sums of a row combine by a butterfly inside the lane group.
+// The list bounds of up to kPrefetch rounds are loaded before the first round,
+// and each round issues its rank-update loads before its gathers, so a round
+// costs about two dependent memory latencies.
+template <typename T, bool FUSED, bool WEIGHTED>
+__device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i1, int lpr,
+                                          Red &red) {
+  const int lane = threadIdx.x & 63;
+  const int q = lane & (lpr - 1);
+  const int g = lane / lpr;
+  const int per = 64 / lpr;
+  for (int rb = i0; rb < i1; rb += per * kPrefetch) {
+    uint32_t eb[kPrefetch];
+    int len[kPrefetch];
+#pragma unroll
+    for (int k = 0; k < kPrefetch; ++k) {
+      const int r = rb + k * per + g;
+      eb[k] = 0;
+      len[k] = 0;
+      if (r < i1) {
+        eb[k] = C.rptr[r];
+        len[k] = (int)(C.rptr[r + 1] - eb[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPrefetch; ++k) {
+      const int r = rb + k * per + g;
+      if (rb + k * per >= i1) break;
+      const bool active = r < i1;
+      const bool owner = active && q == 0;
+      // rank-update operands, loaded ahead of the gathers
+      uint32_t u = 0, slot = 0;
+      double xo = 0.0, iw = 0.0, pu = C.inv_n;
+      if (owner) {
+        u = C.rows[r];
+        slot = C.rowpos[r];
+        xo = (double)C.x[u];
+        iw = C.inv_w[u];
+        if (!(C.flags & kFlagUniformP)) pu = C.p[u];
+      }
+      const uint32_t e0 = eb[k];
+      const int L = len[k];
+      LaneSum<T> acc;
+      for (int j0 = q; j0 < L; j0 += kBatch * lpr) {
+        int32_t s[kBatch];
+        double wt[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int j = j0 + b * lpr;
+          s[b] = j < L ? C.idx[e0 + j] : 0;
+          if constexpr (WEIGHTED) wt[b] = j < L ? C.w[e0 + j] : 0.0;
+        }
+        T v[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) v[b] = gather<T, FUSED>(C, hot, s[b]);
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          T x = j0 + b * lpr < L ? v[b] : (T)0;
+          if constexpr (WEIGHTED) x = (T)((double)x * wt[b]);
+          acc.add(x);
+        }
+      }
+      acc.group_reduce(lpr);
+      if (owner) update_loaded<T, FUSED>(C, hot, u, slot, xo, iw, pu, acc.value(), red);
+    }
+  }
+}
+
+// A tile of consecutive rows (<= kTileRows rows, <= kTileEdges edges).  Lane
+// l loads edges 8l..8l+7 (lane-transposed storage: each load instruction reads
+// 256 contiguous bytes), gathers them, and sums runs between row starts.  A
+// row that starts in lane a and ends in lane b > a is completed by a
+// segmented inclusive scan over the lanes: lane values are the sum after the
+// lane's last row start (or the whole lane when it has none), segments reset
+// at lanes that hold a row start.  Completed row sums go to the wavefront's
+// LDS slice; then lane r updates rows r and r + 64 with operands it loaded
+// before the gathers.
+template <typename T, bool FUSED, bool WEIGHTED>
+__device__ __forceinline__ void tile_rows(const Ctx<T> &C, const SweepArgs<T> &a, T *hot,
+                                          double *rowsum, int t, Red &red) {
+  const int lane = threadIdx.x & 63;
+  const int4 d = a.tiles[t];
+  const int r0 = d.x, nr = d.y, ne = d.z;
+  // rank-update operands of rows r0 + lane and r0 + 64 + lane
+  uint32_t u[2] = {0, 0}, slot[2] = {0, 0};
+  double xo[2] = {0.0, 0.0}, iw[2] = {0.0, 0.0}, pu[2] = {C.inv_n, C.inv_n};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = lane + 64 * k;
+    if (r < nr) {
+      u[k] = C.rows[r0 + r];
+      slot[k] = C.rowpos[r0 + r];
+      xo[k] = (double)C.x[u[k]];
+      iw[k] = C.inv_w[u[k]];
+      if (!(C.flags & kFlagUniformP)) pu[k] = C.p[u[k]];
+    }
+  }
+  const size_t base = (size_t)t * kTileEdges;
+  int32_t s[kBatch];
+#pragma unroll
+  for (int k = 0; k < kBatch; ++k) s[k] = a.tidx[base + k * 64 + lane];
+  const uint32_t fl = a.tmask[(size_t)t * 64 + lane];
+  T v[kBatch];
+#pragma unroll
+  for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, s[k]);
+#pragma unroll
+  for (int k = 0; k < kBatch; ++k) {
+    if constexpr (WEIGHTED) v[k] = (T)((double)v[k] * a.tw[base + k * 64 + lane]);  // padding weight 0
+    else v[k] = lane * kBatch + k < ne ? v[k] : (T)0;
+  }
+  // row index (within the tile) of this lane's first row start
+  const int pc = __popc(fl);
+  int incl = pc;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  const int rowbase = incl - pc;
+  // lane-local runs: head = before the first start, complete rows, tail = after the last start
+  LaneSum<T> cur, head;
+  bool seen = false;
+  int j = 0;
+#pragma unroll
+  for (int k = 0; k < kBatch; ++k) {
+    const bool st = (fl >> k) & 1u;
+    if (st && seen) rowsum[rowbase + j - 1] = cur.value();
+    head = (st && !seen) ? cur : head;
+    j += st ? 1 : 0;
+    seen = seen || st;
+    cur = st ? LaneSum<T>() : cur;
+    cur.add(v[k]);
+  }
+  if (!seen) head = cur;
+  // segmented inclusive scan over lanes of (flag, value)
+  LaneSum<T> sc = cur;
+  bool f = seen;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    LaneSum<T> prev = sc.shfl_up(off);
+    const bool pf = __shfl_up((int)f, off, 64) != 0;
+    if (lane >= off) {
+      if (!f) sc.add_before(prev);
+      f = f || pf;
+    }
+  }
+  LaneSum<T> carry = sc.shfl_up(1);
+  if (lane == 0) carry = LaneSum<T>();
+  if (seen && lane > 0) {
+    carry.combine_with(head);
+    rowsum[rowbase - 1] = carry.value();
+  }
+  if (lane == ((ne - 1) >> 3)) rowsum[nr - 1] = sc.value();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = lane + 64 * k;
+    if (r < nr) update_loaded<T, FUSED>(C, hot, u[k], slot[k], xo[k], iw[k], pu[k], rowsum[r], red);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Vertices without in-edges: lane per vertex, the update only.
+template <typename T, bool FUSED>
+__device__ __forceinline__ void zero_rows(const Ctx<T> &C, T *hot, int i0, int i1, Red &red) {
+  const int lane = threadIdx.x & 63;
+  for (int r = i0 + lane; r < i1; r += 64) update_vertex<T, FUSED>(C, hot, r, 0.0, red);
+}
+
+// One chunk of a hub's list per wavefront; the chunk sum goes to its slot.
+template <typename T, bool FUSED, bool WEIGHTED>
+__device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double *hpart, int chunk,
+                                          int i, int c, int slot) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t rb = C.rptr[i];
+  const int L = (int)(C.rptr[i + 1] - rb);
+  const uint32_t eb = rb + (uint32_t)c * (uint32_t)chunk;
+  const int ne = min(chunk, L - c * chunk);
+  LaneSum<T> acc;
+  for (int j0 = lane; j0 < ne; j0 += kBatch * 64) {
+    int32_t s[kBatch];
+    double wt[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int j = j0 + 64 * k;
+      s[k] = j < ne ? C.idx[eb + j] : 0;
+      if constexpr (WEIGHTED) wt[k] = j < ne ? C.w[eb + j] : 0.0;
+    }
+    T v[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, s[k]);
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      T x = j0 + 64 * k < ne ? v[k] : (T)0;
+      if constexpr (WEIGHTED) x = (T)((double)x * wt[k]);
+      acc.add(x);
+    }
+  }
+  acc.group_reduce(64);
+  if (lane == 0) hpart[slot + c] = acc.value();
+}
+
+// Wavefront reduction of a Red; lane 0 writes the wavefront's partials (SoA).
+__device__ __forceinline__ void store_wave_partial(Red &red, double *part, int n_waves, int gw,
+                                                   bool linf) {
+  const double chg = linf ? wave_max(red.chg) : wave_sum(red.chg);
+  const double dang = wave_sum(red.dang);
+  const double tot = wave_sum(red.tot);
+  if ((threadIdx.x & 63) == 0) {
+    part[gw] = chg;
+    part[(size_t)n_waves + gw] = dang;
+    part[2 * (size_t)n_waves + gw] = tot;
+  }
+}
+
+// One workgroup per CU.  The workgroup first copies the hottest gather slots
+// (the first `hot` of the gather layout) into LDS, then each wavefront takes
+// work items gw, gw + W, gw + 2W, ... (W wavefronts in the launch), so the
+// items run roughly in order: hubs first, then rows by decreasing length.
+// Every wavefront accumulates its rows' change / dangling / total mass and
+// writes one partial; a fixed item-to-wavefront map keeps the sums
+// reproducible.
+#ifndef FPR_WAVES_PER_EU
+#define FPR_WAVES_PER_EU 6
+#endif
+
+template <typename T, bool FUSED, bool WEIGHTED>
+__global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(FPR_WAVES_PER_EU)))
+void k_sweep(SweepArgs<T> a) {
+  __shared__ T hot[kHotSlots<T>];
+  __shared__ double rowsum_all[kSweepWaves][kTileRows];
+  const SweepState *st = a.st;
+  if (st->done) return;
+  const Ctx<T> C = make_ctx<T, FUSED>(a, st);
+  for (int s = threadIdx.x; s < C.hot; s += kSweepBlock) hot[s] = ld_c<FUSED>(C.cin + s);
+  __syncthreads();
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kSweepWaves + (threadIdx.x >> 6)));
+  Red red;
+  double *rowsum = rowsum_all[threadIdx.x >> 6];
+  for (int item = gw; item < a.n_items; item += a.n_waves) {
+    const int4 wi = a.items[item];
+    if (wi.x == kTile) tile_rows<T, FUSED, WEIGHTED>(C, a, hot, rowsum, wi.y, red);
+    else if (wi.x == kRows) row_group<T, FUSED, WEIGHTED>(C, hot, wi.y, wi.z, wi.w, red);
+    else if (wi.x == kHeavy) hub_chunk<T, FUSED, WEIGHTED>(C, hot, a.hpart, a.chunk, wi.y, wi.z, wi.w);
+    else zero_rows<T, FUSED>(C, hot, wi.y, wi.z, red);
+  }
+  store_wave_partial(red, a.wave_part, a.n_waves, gw, (a.flags & kFlagLinf) != 0);
+}
+
+constexpr int kFinBlock = 1024;
+
+// Completes the sweep in one workgroup: updates the hubs from their chunk sums
+// (in chunk order), sums the wavefront partials in a fixed order, and
+// publishes residual, dangling mass, total mass, iteration count and the stop
+// flag.
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(kFinBlock) void k_finalize(SweepArgs<T> a) {
+  __shared__ double s_red[3][kFinBlock / 64];
+  SweepState *st = a.st;
+  if (st->done) return;
+  const Ctx<T> C = make_ctx<T, FUSED>(a, st);
+  const double S_old = st->S;
+  const bool linf = (a.flags & kFlagLinf) != 0;
+  Red red;
+  for (int h = threadIdx.x; h < a.n_split; h += kFinBlock) {
+    const int4 hs = a.hsplit[h];
+    const uint32_t u = C.rows[hs.x];
+    const uint32_t slot = C.rowpos[hs.x];
+    const double xo = (double)C.x[u];
+    const double iw = C.inv_w[u];
+    const double pu = (C.flags & kFlagUniformP) ? C.inv_n : C.p[u];
+    double tot = 0.0;
+    for (int k0 = 0; k0 < hs.z; k0 += 8) {
+      double part[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) part[k] = k0 + k < hs.z ? a.hpart[hs.y + k0 + k] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) tot += part[k];
+    }
+    update_loaded<T, FUSED>(C, nullptr, u, slot, xo, iw, pu, tot, red);
+  }
+  const int n = a.n_waves;
+  for (int i = threadIdx.x; i < n; i += kFinBlock) {
+    const double c0 = a.wave_part[i];
+    red.chg = linf ? fmax(red.chg, c0) : red.chg + c0;
+    red.dang += a.wave_part[(size_t)n + i];
+    red.tot += a.wave_part[2 * (size_t)n + i];
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double chg = linf ? wave_max(red.chg) : wave_sum(red.chg);
+  double dang = wave_sum(red.dang);
+  double tot = wave_sum(red.tot);
+  if (lane == 0) {
+    s_red[0][wave] = chg;
+    s_red[1][wave] = dang;
+    s_red[2][wave] = tot;
   }
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  finalize_sweep<T>(a, S, reinterpret_cast<double *>(lds));
+  if (threadIdx.x == 0) {
+    double raw = s_red[0][0], Dn = s_red[1][0], Sn = s_red[2][0];
+    for (int k = 1; k < kFinBlock / 64; ++k) {
+      raw = linf ? fmax(raw, s_red[0][k]) : raw + s_red[0][k];
+      Dn += s_red[1][k];
+      Sn += s_red[2][k];
+    }
+    double resid = raw;
+    if (a.flags & kFlagScaled) resid = (raw + fabs(Sn - S_old)) / S_old;
+    st->raw = raw;
+    st->resid = resid;
+    st->D = Dn;
+    st->S = Sn;
+    const int it = st->iter + 1;
+    st->iter = it;
+    if (a.trace) a.trace[it - 1] = resid;
+    if (!(resid >= st->tol) || it >= st->max_iter) st->done = 1;
+  }
 }
 
 // ------------------------------------------------------- init / finish --
 
 template <typename T>
 struct InitArgs {
+  const uint32_t *gpos;
   const double *inv_w;
   const double *p;
   const double *x_in;  // warm start (FP64), or null: start from p
   T *x;
   T *c;
-  double *part;  // [gridDim.x * 2]
+  double *part;  // [2][gridDim.x]
   int64_t n;
   double inv_n;
   int uniform_p;
@@ -464,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs<T> a) {
     a.x[u] = xs;
     const double xd = (double)xs;
     const double iw = a.inv_w[u];
-    if (iw != 0.0) a.c[u] = (T)(xd * iw);
+    if (iw != 0.0) a.c[a.gpos[u]] = (T)(xd * iw);
     else dang += xd;
     tot += xd;
   }
@@ -482,21 +677,34 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs<T> a) {
       a0 += s_red[0][k];
       a1 += s_red[1][k];
     }
-    a.part[2 * blockIdx.x] = a0;
-    a.part[2 * blockIdx.x + 1] = a1;
+    a.part[blockIdx.x] = a0;
+    a.part[gridDim.x + blockIdx.x] = a1;
   }
 }
 
-__global__ void k_init_final(const double *part, int nparts, SweepState *st, double tol,
-                             int max_iter) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kFinBlock) void k_init_final(const double *part, int nparts,
+                                                          SweepState *st, double tol, int max_iter) {
+  __shared__ double s_red[2][kFinBlock / 64];
   double D = 0.0, S = 0.0;
-  for (int i = 0; i < nparts; ++i) {
-    D += part[2 * i];
-    S += part[2 * i + 1];
+  for (int i = threadIdx.x; i < nparts; i += kFinBlock) {
+    D += part[i];
+    S += part[nparts + i];
   }
-  st->ticket = 0u;
-  st->finished = 0u;
+  D = wave_sum(D);
+  S = wave_sum(S);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    s_red[0][wave] = D;
+    s_red[1][wave] = S;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  D = 0.0;
+  S = 0.0;
+  for (int k = 0; k < kFinBlock / 64; ++k) {
+    D += s_red[0][k];
+    S += s_red[1][k];
+  }
   st->iter = 0;
   st->done = 0;
   st->max_iter = max_iter;
@@ -555,6 +763,7 @@ template <typename T>
 int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T *x, double tol,
                 int max_iter) {
   InitArgs<T> a;
+  a.gpos = P.gpos;
   a.inv_w = g->inv_w;
   a.p = p;
   a.x_in = x_in;
@@ -566,8 +775,8 @@ int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T 
   a.uniform_p = p == nullptr;
   const int grid = (int)std::min<int64_t>(kInitGrid, (g->n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_init<T>, dim3(grid), dim3(kBlock), 0, g->work, a);
-  hipLaunchKernelGGL(k_init_final, dim3(1), dim3(64), 0, g->work, (const double *)g->red_tmp, grid,
-                     P.st, tol, max_iter);
+  hipLaunchKernelGGL(k_init_final, dim3(1), dim3(kFinBlock), 0, g->work, (const double *)g->red_tmp,
+                     grid, P.st, tol, max_iter);
   PR_HIP(hipGetLastError());
   return PR_OK;
 }
@@ -578,14 +787,18 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   SweepArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.rows = P.rows;
+  a.rowpos = P.rowpos;
   a.rptr = P.rptr;
   a.idx = P.idx;
   a.w = P.w;
   a.items = P.items;
-  a.hbase = P.hbase;
+  a.tiles = P.tiles;
+  a.tidx = P.tidx;
+  a.tw = P.tw;
+  a.tmask = P.tmask;
+  a.hsplit = P.hsplit;
   a.hpart = P.hpart;
-  a.hcnt = P.hcnt;
-  a.item_part = P.item_part;
+  a.wave_part = P.wave_part;
   a.st = P.st;
   a.inv_w = g->inv_w;
   a.p = p;
@@ -596,21 +809,35 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
   a.n_items = P.n_items;
-  a.split = P.split;
+  a.n_split = P.n_split;
+  a.n_waves = P.n_waves;
+  a.chunk = P.chunk;
+  {
+    int64_t hot = g->popts.hot_slots < 0 ? kHotSlots<T> : std::min<int64_t>(g->popts.hot_slots, kHotSlots<T>);
+    a.hot = (int)std::min<int64_t>(hot, g->n);
+  }
   a.flags = flags | (p ? 0 : kFlagUniformP);
   return a;
+}
+
+template <typename T, bool FUSED, bool WEIGHTED>
+void launch_one(const SweepArgs<T> &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_sweep<T, FUSED, WEIGHTED>), dim3(a.n_waves / kSweepWaves), dim3(kSweepBlock), 0,
+                     s, a);
+  hipLaunchKernelGGL((k_finalize<T, FUSED>), dim3(1), dim3(kFinBlock), 0, s, a);
 }
 
 template <typename T>
 void launch_sweeps(pr_graph *g, const SweepArgs<T> &a, bool fused, bool weighted, int count,
                    hipStream_t s) {
+  (void)g;
   for (int k = 0; k < count; ++k) {
     if (fused) {
-      if (weighted) hipLaunchKernelGGL((k_sweep<T, true, true>), dim3(g->grid), dim3(kBlock), 0, s, a);
-      else hipLaunchKernelGGL((k_sweep<T, true, false>), dim3(g->grid), dim3(kBlock), 0, s, a);
+      if (weighted) launch_one<T, true, true>(a, s);
+      else launch_one<T, true, false>(a, s);
     } else {
-      if (weighted) hipLaunchKernelGGL((k_sweep<T, false, true>), dim3(g->grid), dim3(kBlock), 0, s, a);
-      else hipLaunchKernelGGL((k_sweep<T, false, false>), dim3(g->grid), dim3(kBlock), 0, s, a);
+      if (weighted) launch_one<T, false, true>(a, s);
+      else launch_one<T, false, false>(a, s);
     }
   }
 }
@@ -742,12 +969,11 @@ struct StreamJoin {
 
 int fpr_grid_for(pr_graph *g) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<double, false, false>, kBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<double, false, false>, kSweepBlock, 0) !=
           hipSuccess ||
       nb < 1)
-    nb = 4;
-  nb = std::min(nb, 8);
-  return std::max(1, g->n_cu) * nb;
+    nb = 1;
+  return std::max(1, g->n_cu) * nb;  // workgroups resident at once
 }
 
 extern "C" void pr_opts_default(pr_opts *o) {
@@ -832,7 +1058,7 @@ extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const p
 }
 
 extern "C" int pr_iterate(pr_graph *g, double d, const pr_opts *opts, const double *p, double *x,
-                          int sweeps, double *resid, void *stream) {
+                          int sweeps, double *resid, double *elapsed_ms, void *stream) {
   pr_clear_error();
   pr_opts o;
   pr_opts_default(&o);
@@ -848,13 +1074,28 @@ extern "C" int pr_iterate(pr_graph *g, double d, const pr_opts *opts, const doub
   if ((rc = launch_init<double>(g, P, p, x, x, -1.0, std::max(1, sweeps)))) return rc;
   const int flags = flags_of(o);
   SweepArgs<double> a = make_args<double>(g, P, p, x, d, flags, nullptr);
-  if (sweeps > 0) launch_sweeps(g, a, o.mode == PR_FUSED, g->weighted, sweeps, g->work);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (elapsed_ms) {
+    PR_HIP(hipEventCreate(&e0));
+    PR_HIP(hipEventCreate(&e1));
+    PR_HIP(hipEventRecord(e0, g->work));
+  }
+  if (sweeps > 0 && (rc = run_sweeps<double>(g, a, o.mode == PR_FUSED, o.use_hip_graph != 0, sweeps)))
+    return rc;
+  if (elapsed_ms) PR_HIP(hipEventRecord(e1, g->work));
   if (flags & kFlagScaled)
     hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const double *)x, x,
                        g->n, (const SweepState *)P.st, 1);
   PR_HIP(hipGetLastError());
   if ((rc = poll_state(g, P))) return rc;
   if (resid) *resid = sweeps > 0 ? g->host_st->resid : INFINITY;
+  if (elapsed_ms) {
+    float ms = 0.0f;
+    PR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *elapsed_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   return PR_OK;
 }
 

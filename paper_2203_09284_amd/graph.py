@@ -179,15 +179,20 @@ class Graph:
 
     def iterate(self, x: torch.Tensor, sweeps: int, d: float = 0.85, mode: str = "jacobi",
                 p: torch.Tensor | None = None, dangling: str = "uniform", norm: str = "l1",
-                fused_scaled: bool = True, stream=None) -> float:
-        """pr_iterate: exactly `sweeps` FP64 sweeps from x, in place.  Returns the last residual."""
-        o = self._opts(mode, "fp64", dangling, norm, True, fused_scaled, None, False, None, None, None)
+                fused_scaled: bool = True, use_hip_graph: bool = False, timed: bool = False,
+                stream=None):
+        """pr_iterate: exactly `sweeps` FP64 sweeps from x, in place.  Returns the last
+        residual, or (residual, device milliseconds of the sweeps) when timed."""
+        o = self._opts(mode, "fp64", dangling, norm, True, fused_scaled, None, use_hip_graph, None,
+                       None, None)
         res = ctypes.c_double(0.0)
+        ms = ctypes.c_double(0.0)
         rc = L.lib().pr_iterate(self._h, d, ctypes.byref(o), _dev_ptr(p, torch.float64, self.n, "p"),
                                 _dev_ptr(x, torch.float64, self.n, "x"), int(sweeps),
-                                ctypes.byref(res), _stream_ptr(stream))
+                                ctypes.byref(res), ctypes.byref(ms) if timed else None,
+                                _stream_ptr(stream))
         L.check(rc)
-        return res.value
+        return (res.value, ms.value) if timed else res.value
 
     def certificate(self, x: torch.Tensor, d: float = 0.85, p: torch.Tensor | None = None,
                     stream=None) -> float:

@@ -46,8 +46,9 @@ def cases():
 
 CASES = cases()
 # plans that force every bin, many heavy chunks and ragged blocks on small graphs
-PLANS = [None, dict(light_max=2, medium_max=40, split=256, block_edges=37),
-         dict(light_max=0, medium_max=8, split=256, block_edges=1)]
+PLANS = [None, dict(chunk=64, tile_max_row=9, tile_rows=5, steps=3, hot_slots=100),
+         dict(chunk=256, tile_max_row=0, steps=1, hot_slots=0, gather_layout=0),
+         dict(chunk=96, tile_max_row=90, tile_rows=128, steps=2, hot_slots=7)]
 
 
 def _ref(n, src, dst, w, p, tol=1e-15):
@@ -207,6 +208,21 @@ def test_edge_cases(n, edges):
             x, it, res, ok = g.solve(d=D, tol=1e-14, max_iter=500, mode=mode, precision=prec)
             assert l1(x.cpu().numpy(), xr) <= 1e-12, (mode, prec)
     g.close()
+
+
+def test_gather_layout_does_not_change_jacobi_bits():
+    """The gather layout only moves addresses: same values, same summation order."""
+    fpr = _fpr()
+    s, t = gg.rmat(14, 16, seed=9)
+    n = 1 << 14
+    say("gather layout")
+    a = fpr.Graph(n, s, t, plan=dict(gather_layout=1))
+    b = fpr.Graph(n, s, t, plan=dict(gather_layout=0))
+    xa = a.solve(d=D, tol=1e-12, mode="jacobi")
+    xb = b.solve(d=D, tol=1e-12, mode="jacobi")
+    assert torch.equal(xa[0], xb[0]) and xa[1] == xb[1]
+    a.close()
+    b.close()
 
 
 def test_jacobi_is_bit_reproducible_and_graph_capture_neutral():
