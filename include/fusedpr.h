@@ -115,8 +115,8 @@ typedef struct pr_plan_opts {
   int chunk;             /* lists longer than this are split into chunks of this many edges,
                             one wavefront each (default 2048, range [64, 2^20]) */
   int tile_max_row;      /* lists of 1..tile_max_row edges are packed into 512-edge tiles
-                            (default 512, at most min(512, chunk)); longer ones get a
-                            wavefront each */
+                            (default 512, at most 512; lowered to chunk if larger); longer
+                            ones get a wavefront each */
   int tile_rows;         /* rows per tile at most (1..128, default 128) */
   int steps;             /* one-wavefront rows per work item (default 4) */
   int hot_slots;         /* gather slots staged in LDS per sweep workgroup (-1 = as many as fit,
@@ -210,15 +210,17 @@ int pr_certificate(pr_graph *g, double d, const double *p, const double *x, doub
 
 /* ------------------------------------------------------------------------
  * Batched personalized PageRank: k teleport vectors, each one-hot on
- * seeds[j], solved together as one k-column pull per sweep (Jacobi).
- * Dangling mass is spread uniformly.  Ranks are FP32, per-column residual
- * and dangling mass FP64; a column stops updating once its L1 residual is
- * below tol.
- *   seeds   device int32[k], ids in [0, n);  1 <= k <= 1024
+ * seeds[j] (Eq. 1 with a personalised teleport term), solved together as a
+ * multi-column Jacobi pull per sweep.  Dangling mass is spread uniformly.
+ * Ranks are FP32 (compensated sums), per-column residual and dangling mass
+ * FP64; a column is frozen once its L1 residual is below tol.
+ *   seeds   device int32[k], ids in [0, n) (checked: PR_EINVAL);  1 <= k <= 1024
  *   X       device float[n * k], row-major (vertex-major): X[v * k + j]
- *   iters   host int[k]: sweeps until column j converged (or max_iter)
+ *   iters   host int[k]: sweeps until column j froze (or max_iter)
  *   resid   host double[k]: last residual of each column
- *   tile    columns processed per pass (1..64, dividing k); 0 = autotuned
+ *   tile    columns advanced per launch (a multiple of 4, at most 64; four
+ *           columns share each gather); 0 = autotuned (pr_autotune_batched,
+ *           cache file from the FUSEDPR_TUNE_CACHE environment variable)
  * ---------------------------------------------------------------------- */
 int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter, int k, const int32_t *seeds,
                      int tile, float *X, int *iters, double *resid, void *stream);

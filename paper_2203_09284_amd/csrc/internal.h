@@ -48,6 +48,7 @@ enum SweepFlags : int {
   kFlagLinf = 2,      // max-norm residual instead of L1
   kFlagScaled = 4,    // teleport scaled by the previous sweep's total mass
   kFlagUniformP = 8,  // p == 1/n (p pointer unused)
+  kFlagAdjoint = 16,  // transposed iteration: lam' = g + d (W^-1 sum w lam + [W = 0] sum(lam) / n)
 };
 
 // Device-resident state of an iteration; one per graph and pull direction.
@@ -107,6 +108,9 @@ struct pr_graph {
   bool has_adj = false;
   double *inv_w = nullptr;      // [n] 1 / W_v, 0 for dangling vertices
   uint32_t *out_ptr = nullptr;  // [n+1] out-edge offsets (adjoint gradient layout)
+  int32_t *out_dst = nullptr;   // [m] out-edge destinations in pr_csr order (adjoint gradients)
+  double *out_w = nullptr;      // [m] their weights (or null)
+  double *ca64[2] = {nullptr, nullptr};  // adjoint gather buffers
   int64_t n_dangling = 0;
   int grid = 0;  // persistent workgroups per sweep
   hipStream_t work = nullptr;
@@ -135,3 +139,9 @@ struct pr_graph {
 int fpr_dev_alloc(pr_graph *g, void **p, size_t bytes);
 // sweep.hip
 int fpr_grid_for(pr_graph *g);
+void fpr_sweep_release(pr_graph *g);    // drops cached hipGraphs of g
+// batched.hip
+void fpr_batched_release(pr_graph *g);  // drops g's batched workspace bookkeeping
+// adjoint.hip: dL/dp = (1-d) lam and dL/dw (out-edge order) from the converged lam
+int fpr_adjoint_gradients(pr_graph *g, double d, const double *x, const double *lam, double *dLdp,
+                          double *dLdw, hipStream_t s);

@@ -224,6 +224,8 @@ static void destroy(pr_graph *g) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(g->device);
   if (g->work) (void)hipStreamSynchronize(g->work);
+  fpr_sweep_release(g);
+  fpr_batched_release(g);
   for (void *p : g->owned) (void)hipFree(p);
   g->owned.clear();
   if (g->host_st) (void)hipHostFree(g->host_st);
@@ -250,11 +252,11 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
   pr_plan_opts_default(&o);
   if (opts) o = *opts;
   if (o.chunk < 64 || o.chunk > (1 << 20) || o.tile_max_row < 0 || o.tile_max_row > kTileEdges ||
-      o.tile_max_row > o.chunk || o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 ||
-      o.steps > 64)
+      o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 || o.steps > 64)
     return pr_fail(PR_EINVAL,
-                   "pr_graph_create: need 64 <= chunk <= 2^20, 0 <= tile_max_row <= min(512, chunk), "
+                   "pr_graph_create: need 64 <= chunk <= 2^20, 0 <= tile_max_row <= 512, "
                    "1 <= tile_rows <= 128, 1 <= steps <= 64");
+  o.tile_max_row = std::min(o.tile_max_row, o.chunk);
   int dev_count = 0;
   hipError_t he = hipGetDeviceCount(&dev_count);
   if (he != hipSuccess || dev_count < 1)
@@ -296,6 +298,8 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
       std::vector<uint32_t> op(n + 1);
       for (int64_t v = 0; v <= n; ++v) op[v] = (uint32_t)csr->out_ptr[v];
       if ((rc2 = upload(g, &g->out_ptr, op.data(), op.size()))) return rc2;
+      if ((rc2 = upload(g, &g->out_dst, csr->out_dst, (size_t)csr->m))) return rc2;
+      if (csr->out_w && (rc2 = upload(g, &g->out_w, csr->out_w, (size_t)csr->m))) return rc2;
       g->has_adj = true;
     }
     if (hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking) != hipSuccess ||

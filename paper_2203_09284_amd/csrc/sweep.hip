@@ -36,9 +36,11 @@
 #include <algorithm>
 #include <vector>
 
+#include "device_common.h"
 #include "internal.h"
 
 using namespace fpr;
+using namespace fpr::dev;
 
 // Memory scope of the relaxed atomic loads/stores of the shared contribution
 // array in the fused form.  Workgroup scope compiles to ordinary cached
@@ -51,92 +53,6 @@ using namespace fpr;
 #endif
 
 namespace {
-
-// ------------------------------------------------------------ arithmetic --
-
-// Per-lane sum: plain FP64, or FP32 with Neumaier compensation.
-template <typename T>
-struct LaneSum;
-
-template <>
-struct LaneSum<double> {
-  double s = 0.0;
-  __device__ __forceinline__ void add(double v) { s += v; }
-  __device__ __forceinline__ double value() const { return s; }
-  __device__ __forceinline__ LaneSum shfl_up(int off) const {
-    LaneSum r;
-    r.s = __shfl_up(s, off, 64);
-    return r;
-  }
-  // this = earlier + this
-  __device__ __forceinline__ void add_before(const LaneSum &earlier) { s = earlier.s + s; }
-  // this = this + later
-  __device__ __forceinline__ void combine_with(const LaneSum &later) { s = s + later.s; }
-  // butterfly over the lpr-lane group (lpr a power of two, uniform in the wavefront)
-  __device__ __forceinline__ void group_reduce(int lpr) {
-    for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  }
-};
-
-template <>
-struct LaneSum<float> {
-  float s = 0.0f, c = 0.0f;
-  __device__ __forceinline__ void add(float v) {
-#pragma clang fp contract(off)
-    float t = s + v;
-    if (fabsf(s) >= fabsf(v)) c += (s - t) + v;
-    else c += (v - t) + s;
-    s = t;
-  }
-  __device__ __forceinline__ double value() const { return (double)s + (double)c; }
-  __device__ __forceinline__ LaneSum shfl_up(int off) const {
-    LaneSum r;
-    r.s = __shfl_up(s, off, 64);
-    r.c = __shfl_up(c, off, 64);
-    return r;
-  }
-  __device__ __forceinline__ void add_before(const LaneSum &earlier) {
-    LaneSum e = earlier;
-    e.combine(s, c);
-    *this = e;
-  }
-  __device__ __forceinline__ void combine_with(const LaneSum &later) { combine(later.s, later.c); }
-  // TwoSum of the leading parts, compensations added
-  __device__ __forceinline__ void combine(float s2, float c2) {
-#pragma clang fp contract(off)
-    float t = s + s2;
-    float bp = t - s;
-    float err = (s - (t - bp)) + (s2 - bp);
-    c = c + c2 + err;
-    s = t;
-  }
-  __device__ __forceinline__ void group_reduce(int lpr) {
-    for (int off = lpr >> 1; off > 0; off >>= 1) {
-      float s2 = __shfl_xor(s, off, 64);
-      float c2 = __shfl_xor(c, off, 64);
-      combine(s2, c2);
-    }
-  }
-};
-
-// Reductions carried per thread through a work item.
-struct Red {
-  double chg = 0.0;   // sum (or max) of |x' - x|
-  double dang = 0.0;  // new dangling mass
-  double tot = 0.0;   // new total mass
-};
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
 
 template <bool FUSED, typename T>
 __device__ __forceinline__ T ld_c(const T *p) {
@@ -233,52 +149,50 @@ __device__ __forceinline__ Ctx<T> make_ctx(const SweepArgs<T> &a, const SweepSta
   C.inv_n = a.inv_n;
   C.hot = a.hot;
   C.flags = a.flags;
-  C.tele = (1.0 - a.d) * ((a.flags & kFlagScaled) ? S : 1.0);
-  C.dterm = (a.flags & kFlagLeak) ? 0.0 : D * a.inv_n;
+  if (a.flags & kFlagAdjoint) {
+    C.tele = 1.0;              // lam' = g + ...
+    C.dterm = S * a.inv_n;     // added for dangling vertices only
+  } else {
+    C.tele = (1.0 - a.d) * ((a.flags & kFlagScaled) ? S : 1.0);
+    C.dterm = (a.flags & kFlagLeak) ? 0.0 : D * a.inv_n;
+  }
   return C;
 }
 
-// Row-table entry i: vertex u = rows[i], its gather slot rowpos[i].  In the
-// fused form the workgroup's LDS copy of a hot slot is refreshed as well, so
-// later wavefronts of the workgroup read the new value.
+// Row-table entry i: vertex u = rows[i], its gather slot rowpos[i].
+template <typename T, bool FUSED>
+__device__ __forceinline__ void update_loaded(const Ctx<T> &C, T *hot, uint32_t u, uint32_t slot,
+                                              double xo, double iw, double pu, double s, Red &red);
+
 template <typename T, bool FUSED>
 __device__ __forceinline__ void update_vertex(const Ctx<T> &C, T *hot, int i, double s, Red &red) {
   const uint32_t u = C.rows[i];
-  const double xo = (double)C.x[u];
   const double pu = (C.flags & kFlagUniformP) ? C.inv_n : C.p[u];
-  const double xn = C.tele * pu + C.d * (s + C.dterm);
-  const T xs = (T)xn;
-  C.x[u] = xs;
-  const double xd = (double)xs;
-  const double iw = C.inv_w[u];
-  if (iw != 0.0) {
-    const uint32_t slot = C.rowpos[i];
-    const T cv = (T)(xd * iw);
-    st_c<FUSED>(C.cout + slot, cv);
-    if (FUSED && hot != nullptr && slot < (uint32_t)C.hot) hot[slot] = cv;
-  } else {
-    red.dang += xd;
-  }
-  const double dl = fabs(xd - xo);
-  red.chg = (C.flags & kFlagLinf) ? fmax(red.chg, dl) : red.chg + dl;
-  red.tot += xd;
+  update_loaded<T, FUSED>(C, hot, u, C.rowpos[i], (double)C.x[u], C.inv_w[u], pu, s, red);
 }
 
-// The rank update with its operands already loaded (see update_vertex).
+// The update of vertex u from its pulled sum s, with its operands loaded:
+// old value xo, 1/W_u (iw), teleport (or adjoint right-hand side) pu, and the
+// slot of u in the gather layout.  In the fused form the workgroup's LDS copy
+// of a hot slot is refreshed as well, so later wavefronts of the workgroup
+// read the new value.
+//   forward: x' = (1-d) p_u s + d (sum + D/n),  gathered value x' / W_u
+//   adjoint: x' = g_u + d (sum / W_u + [W_u = 0] S/n),  gathered value x'
 template <typename T, bool FUSED>
 __device__ __forceinline__ void update_loaded(const Ctx<T> &C, T *hot, uint32_t u, uint32_t slot,
                                               double xo, double iw, double pu, double s, Red &red) {
-  const double xn = C.tele * pu + C.d * (s + C.dterm);
+  const bool adj = (C.flags & kFlagAdjoint) != 0;
+  const double xn = adj ? pu + C.d * (iw * s + (iw == 0.0 ? C.dterm : 0.0))
+                        : C.tele * pu + C.d * (s + C.dterm);
   const T xs = (T)xn;
   C.x[u] = xs;
   const double xd = (double)xs;
-  if (iw != 0.0) {
-    const T cv = (T)(xd * iw);
+  if (adj || iw != 0.0) {
+    const T cv = adj ? xs : (T)(xd * iw);
     st_c<FUSED>(C.cout + slot, cv);
     if (FUSED && hot != nullptr && slot < (uint32_t)C.hot) hot[slot] = cv;
-  } else {
-    red.dang += xd;
   }
+  if (iw == 0.0) red.dang += xd;
   const double dl = fabs(xd - xo);
   red.chg = (C.flags & kFlagLinf) ? fmax(red.chg, dl) : red.chg + dl;
   red.tot += xd;
@@ -646,6 +560,7 @@ struct InitArgs {
   int64_t n;
   double inv_n;
   int uniform_p;
+  int raw;  // adjoint: gathered value = x for every vertex
 };
 
 template <typename T>
@@ -659,8 +574,9 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs<T> a) {
     a.x[u] = xs;
     const double xd = (double)xs;
     const double iw = a.inv_w[u];
-    if (iw != 0.0) a.c[a.gpos[u]] = (T)(xd * iw);
-    else dang += xd;
+    if (a.raw) a.c[a.gpos[u]] = xs;
+    else if (iw != 0.0) a.c[a.gpos[u]] = (T)(xd * iw);
+    if (iw == 0.0) dang += xd;
     tot += xd;
   }
   dang = wave_sum(dang);
@@ -761,14 +677,15 @@ int ensure_trace(pr_graph *g, int max_iter) {
 
 template <typename T>
 int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T *x, double tol,
-                int max_iter) {
+                int max_iter, T *c0 = nullptr, int raw = 0) {
   InitArgs<T> a;
   a.gpos = P.gpos;
   a.inv_w = g->inv_w;
   a.p = p;
   a.x_in = x_in;
   a.x = x;
-  a.c = contrib<T>(g, 0);
+  a.c = c0 ? c0 : contrib<T>(g, 0);
+  a.raw = raw;
   a.part = g->red_tmp;
   a.n = g->n;
   a.inv_n = 1.0 / (double)g->n;
@@ -783,7 +700,7 @@ int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T 
 
 template <typename T>
 SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d, int flags,
-                       double *trace) {
+                       double *trace, T *c0 = nullptr, T *c1 = nullptr) {
   SweepArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.rows = P.rows;
@@ -803,8 +720,8 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   a.inv_w = g->inv_w;
   a.p = p;
   a.x = x;
-  a.c0 = contrib<T>(g, 0);
-  a.c1 = contrib<T>(g, 1);
+  a.c0 = c0 ? c0 : contrib<T>(g, 0);
+  a.c1 = c1 ? c1 : contrib<T>(g, 1);
   a.trace = trace;
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
@@ -967,6 +884,17 @@ struct StreamJoin {
 
 // ------------------------------------------------------------------ ABI --
 
+void fpr_sweep_release(pr_graph *g) {
+  for (size_t i = 0; i < g_graph_cache.size();) {
+    if (g_graph_cache[i].key_graph == g) {
+      (void)hipGraphExecDestroy(g_graph_cache[i].exec);
+      g_graph_cache.erase(g_graph_cache.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
 int fpr_grid_for(pr_graph *g) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<double, false, false>, kSweepBlock, 0) !=
@@ -1118,4 +1046,42 @@ extern "C" int pr_certificate(pr_graph *g, double d, const double *p, const doub
   if ((rc = poll_state(g, P))) return rc;
   *result = g->host_st->raw;
   return PR_OK;
+}
+
+extern "C" int pr_adjoint(pr_graph *g, double d, const double *x, const double *dLdx, double tol,
+                          int max_iter, double *lam, double *dLdp, double *dLdw, int *iters,
+                          double *resid, void *stream) {
+  pr_clear_error();
+  pr_opts o;
+  pr_opts_default(&o);
+  int rc = validate_common(g, d, o);
+  if (rc) return rc;
+  if (!g->has_adj) return pr_fail(PR_EINVAL, "pr_adjoint: the graph was created without with_adjoint");
+  if (!x || !dLdx || !lam || !iters || !resid) return pr_fail(PR_EINVAL, "pr_adjoint: NULL argument");
+  if (!(tol > 0.0)) return pr_fail(PR_EINVAL, "tol=%g must be > 0", tol);
+  if (max_iter < 1) return pr_fail(PR_EINVAL, "max_iter=%d must be >= 1", max_iter);
+  StreamJoin join(g, stream);
+  for (int k = 0; k < 2; ++k)
+    if (!g->ca64[k] && (rc = fpr_dev_alloc(g, (void **)&g->ca64[k], sizeof(double) * (size_t)g->n))) return rc;
+  DevPlan &P = g->adj;
+  // lam^0 = g; gathered value = lam (no 1/W scaling), all vertices
+  if ((rc = launch_init<double>(g, P, dLdx, dLdx, lam, tol, max_iter, g->ca64[0], 1))) return rc;
+  const int flags = kFlagAdjoint | kFlagLinf;
+  SweepArgs<double> a = make_args<double>(g, P, dLdx, lam, d, flags, nullptr, g->ca64[0], g->ca64[1]);
+  const int G = 8;
+  int done_sweeps = 0;
+  for (;;) {
+    const int cnt = std::min(G, max_iter - done_sweeps);
+    launch_sweeps(g, a, false, g->weighted, cnt, g->work);
+    PR_HIP(hipGetLastError());
+    if ((rc = poll_state(g, P))) return rc;
+    done_sweeps = g->host_st->iter;
+    if (g->host_st->done || done_sweeps >= max_iter) break;
+    if (!(g->host_st->resid == g->host_st->resid)) return pr_fail(PR_EDEVICE, "adjoint residual is NaN");
+  }
+  if ((rc = fpr_adjoint_gradients(g, d, x, lam, dLdp, dLdw, g->work))) return rc;
+  PR_HIP(hipStreamSynchronize(g->work));
+  *iters = g->host_st->iter;
+  *resid = g->host_st->resid;
+  return (*resid < tol) ? PR_OK : PR_NOT_CONVERGED;
 }

@@ -1,0 +1,207 @@
+"""GPU parity of the batched personalized solve and of the adjoint (gradients)
+against the FP64 CPU oracle.  Bars: FP32 batched columns L1 <= 1e-5 against
+the oracle's single-vector fixed point; FP64 adjoint relative L1 <= 1e-8."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+from oracle import dense
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _fpr():
+    import paper_2203_09284_amd as fpr
+    return fpr
+
+
+def l1(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).sum())
+
+
+def _ppr_ref(og, n, s, tol=1e-14):
+    p = np.zeros(n)
+    p[s] = 1.0
+    x, _, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=5000, p=p, threads=8)
+    return x
+
+
+BATCH_CASES = [("rmat10", 10, 7, 1), ("rmat12", 12, 64, 2), ("rmat11", 11, 13, 3)]
+
+
+@pytest.mark.parametrize("name,scale,k,seed", BATCH_CASES, ids=[c[0] for c in BATCH_CASES])
+def test_batched_columns_match_oracle(name, scale, k, seed):
+    fpr = _fpr()
+    n = 1 << scale
+    s, t = gg.rmat(scale, 16, seed=seed)
+    og = oracle.csr(n, s, t)
+    seeds = gg.sample_distinct(n, k, seed, 4)
+    say("batched %s k=%d" % (name, k))
+    g = fpr.Graph(n, s, t, plan=dict(chunk=256, tile_rows=37))
+    X, its, res = g.solve_batched(torch.tensor(seeds, dtype=torch.int32, device="cuda"), d=D, tol=1e-6,
+                                  tile=8)
+    Xh = X.cpu().numpy().astype(np.float64)
+    assert np.all(res < 1e-6) and np.all(its >= 1)
+    for j in range(k):
+        xr = _ppr_ref(og, n, seeds[j])
+        assert l1(Xh[:, j], xr) <= 1e-5, j
+    # teleport lower bound and column sums
+    assert np.all(Xh[seeds, np.arange(k)] >= (1 - D) - 1e-6)
+    assert np.max(np.abs(Xh.sum(axis=0) - 1.0)) <= 1e-5
+    g.close()
+
+
+def test_batched_tile_widths_agree_and_linearity():
+    fpr = _fpr()
+    n = 1 << 12
+    s, t = gg.rmat(12, 16, seed=5)
+    g = fpr.Graph(n, s, t)
+    seeds = torch.tensor(gg.sample_distinct(n, 20, 5, 4), dtype=torch.int32, device="cuda")
+    say("tile widths")
+    outs = []
+    for tile in (4, 8, 16, 64, 0):
+        X, its, res = g.solve_batched(seeds, d=D, tol=1e-6, tile=tile)
+        outs.append((X.cpu().numpy(), its))
+    for X, its in outs[1:]:
+        assert np.array_equal(X, outs[0][0]) and np.array_equal(its, outs[0][1])
+    # linearity: the column mean is the PPR of the mean teleport vector
+    og = oracle.csr(n, s, t)
+    p = np.zeros(n)
+    p[seeds.cpu().numpy()] = 1.0 / 20
+    xm, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=5000, p=p)
+    assert l1(outs[0][0].astype(np.float64).mean(axis=1), xm) <= 1e-5
+    g.close()
+
+
+def test_batched_autotune_cache(tmp_path):
+    fpr = _fpr()
+    n = 1 << 11
+    s, t = gg.rmat(11, 8, seed=6)
+    g = fpr.Graph(n, s, t)
+    path = str(tmp_path / "tune.jsonl")
+    say("autotune")
+    tile = g.autotune_batched(32, path)
+    assert tile in (4, 8, 16, 32)
+    text = open(path).read()
+    assert '"tile": %d' % tile in text
+    g.close()
+    g2 = fpr.Graph(n, s, t)
+    assert g2.autotune_batched(32, path) == tile  # read back from the cache file
+    g2.close()
+
+
+def test_batched_rejects_bad_seeds():
+    fpr = _fpr()
+    from paper_2203_09284_amd._lib import FusedPRError
+    s, t = gg.cycle(10)
+    g = fpr.Graph(10, s, t)
+    say("bad seeds")
+    with pytest.raises(FusedPRError):
+        g.solve_batched(torch.tensor([1, 10], dtype=torch.int32, device="cuda"), tile=4)
+    with pytest.raises(FusedPRError):
+        g.solve_batched(torch.tensor([1, -1], dtype=torch.int32, device="cuda"), tile=4)
+    with pytest.raises(FusedPRError):
+        g.solve_batched(torch.tensor([1, 2], dtype=torch.int32, device="cuda"), tile=6)
+    g.close()
+
+
+# ------------------------------------------------------------------ adjoint --
+
+def _adj_case(scale_or_n, seed, small=True):
+    if small:
+        n = scale_or_n
+        src, dst = gg.random_graph(n, 6 * n, seed)
+    else:
+        n = 1 << scale_or_n
+        src, dst = gg.rmat(scale_or_n, 16, seed=seed)
+    w = gg.weights(len(src), seed)
+    targets = gg.sample_distinct(n, max(4, n // 20), seed, 4)
+    gvec = np.zeros(n)
+    gvec[targets] = 1.0
+    return n, src, dst, w, gvec
+
+
+@pytest.mark.parametrize("plan", [None, dict(chunk=64, tile_max_row=5, tile_rows=7, hot_slots=3)])
+def test_adjoint_matches_dense_gradient(plan):
+    fpr = _fpr()
+    n, src, dst, w, gvec = _adj_case(150, 91)
+    say("adjoint dense plan=%s" % plan)
+    g = fpr.Graph(n, src, dst, w, with_adjoint=True, plan=plan)
+    x, it, res, ok = g.solve(d=D, tol=1e-14, max_iter=5000)
+    lam, gp, gw, it2, r2 = g.adjoint(x, torch.tensor(gvec, device="cuda"), d=D, tol=1e-14)
+    lam_d = dense.adjoint(n, src, dst, w, D, gvec)
+    assert l1(lam.cpu().numpy(), lam_d) <= 1e-10 * np.abs(lam_d).sum()
+    assert l1(gp.cpu().numpy(), (1 - D) * lam_d) <= 1e-10 * np.abs(lam_d).sum()
+    og = oracle.csr(n, src, dst, w)
+    ref = dense.gradient_weights(n, src, dst, w, D, None, gvec)
+    want = np.array([ref[(v, int(og.out_dst[e]))] for v in range(n)
+                     for e in range(og.out_ptr[v], og.out_ptr[v + 1])])
+    got = gw.cpu().numpy()
+    assert l1(got, want) <= 1e-8 * np.abs(want).sum()
+    g.close()
+
+
+def test_adjoint_weighted_rmat_matches_oracle():
+    fpr = _fpr()
+    n, src, dst, w, gvec = _adj_case(13, 92, small=False)
+    say("adjoint rmat13")
+    og = oracle.csr(n, src, dst, w)
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=5000, threads=8)
+    lam_o, gp_o, gw_o, _, _ = oracle.adjoint(og, xr, gvec, D, tol=1e-14)
+    g = fpr.Graph(n, src, dst, w, with_adjoint=True)
+    x, it, res, ok = g.solve(d=D, tol=1e-14, max_iter=5000)
+    assert l1(x.cpu().numpy(), xr) <= 1e-9
+    lam, gp, gw, it2, r2 = g.adjoint(x, torch.tensor(gvec, device="cuda"), d=D, tol=1e-14)
+    assert l1(lam.cpu().numpy(), lam_o) <= 1e-8 * np.abs(lam_o).sum()
+    assert l1(gw.cpu().numpy(), gw_o) <= 1e-8 * np.abs(gw_o).sum()
+    # duality L = g.x = (1-d) lam.p, and homogeneity sum_out w dL/dw = 0
+    L = float(np.dot(gvec, x.cpu().numpy()))
+    assert abs(L - (1 - D) * float(lam.cpu().numpy().sum()) / n) <= 1e-12 * abs(L)
+    gwh = gw.cpu().numpy()
+    for v in range(0, n, 97):
+        a, b = og.out_ptr[v], og.out_ptr[v + 1]
+        if b > a:
+            assert abs(float(np.dot(og.out_w[a:b], gwh[a:b]))) <= 1e-12 * max(1e-30, float(np.abs(og.out_w[a:b] * gwh[a:b]).sum())) + 1e-18
+    g.close()
+
+
+def test_pagerank_fn_autograd_matches_finite_differences():
+    fpr = _fpr()
+    n, src, dst, w, gvec = _adj_case(60, 93)
+    say("autograd")
+    g = fpr.Graph(n, src, dst, w, with_adjoint=True)
+    p = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda", requires_grad=True)
+    wt = torch.tensor(w, dtype=torch.float64, device="cuda", requires_grad=True)
+    x = fpr.PageRankFn.apply(p, wt, g, D, 1e-14, 10000)
+    L = (x * torch.tensor(gvec, device="cuda")).sum()
+    L.backward()
+    gw = wt.grad.cpu().numpy()
+    gp = p.grad.cpu().numpy()
+    for i in gg.sample_distinct(len(src), 10, 93, 5).tolist():
+        fd = dense.gradient_fd_weight(n, src, dst, w, D, np.full(n, 1.0 / n), gvec, i)
+        if src[i] == dst[i]:
+            assert gw[i] == 0.0
+        else:
+            assert abs(gw[i] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(gw).max())
+    for u in gg.sample_distinct(n, 5, 93, 6).tolist():
+        fd = dense.gradient_fd_p(n, src, dst, w, D, np.full(n, 1.0 / n), gvec, u)
+        assert abs(gp[u] - fd) <= 1e-7 * max(abs(fd), 1.0)
+    g.close()
+
+
+def test_adjoint_requires_plan():
+    fpr = _fpr()
+    from paper_2203_09284_amd._lib import FusedPRError
+    s, t = gg.cycle(8)
+    g = fpr.Graph(8, s, t)
+    x = torch.full((8,), 1 / 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(FusedPRError):
+        g.adjoint(x, x)
+    g.close()
