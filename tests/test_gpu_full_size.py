@@ -1,0 +1,163 @@
+"""Parity at the benchmark workloads' full sizes, in the configurations the
+benchmark times (default plans, hipGraph sweeps):
+
+  er10k      directed Erdos-Renyi n=10,000 m=80,000, FP64 Jacobi, tol 1e-10, <= 200 sweeps
+  rmat20     R-MAT scale 20 (permuted ids), FP64 Jacobi and fused, tol 1e-8 / 1e-12
+  rmat20 k64 batched personalized, FP32, per-column tol 1e-6 (sampled columns)
+  rmat18w    weighted R-MAT scale 18, adjoint of the sum over 1,024 targets
+  rmat24     R-MAT scale 24 in BFS order, FP32 fused + FP64 refinement
+             (sampled rows, certificate; the oracle cannot build this CSR quickly)
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+THREADS = 16
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def l1(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).sum())
+
+
+def _fpr():
+    import paper_2203_09284_amd as fpr
+    return fpr
+
+
+def test_er10k_config():
+    fpr = _fpr()
+    d = gg.er_10k()
+    og = oracle.csr(d["n"], d["src"], d["dst"])
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=1000)
+    _, it_o, _ = oracle.pagerank_ec(og, D, tol=1e-10, max_iter=200)
+    say("er10k")
+    g = fpr.Graph(d["n"], d["src"], d["dst"])
+    x, it, res, ok = g.solve(d=D, tol=1e-10, max_iter=200, mode="jacobi")
+    assert ok and abs(it - it_o) <= 1
+    assert l1(x.cpu().numpy(), xr) <= 1e-9
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def rmat20():
+    w = gg.rmat20()
+    og = oracle.csr(w["n"], w["src"], w["dst"])
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=1000, threads=THREADS)
+    return w, og, xr
+
+
+@pytest.mark.timeout(600)
+def test_rmat20_csr_and_fixed_point(rmat20):
+    fpr = _fpr()
+    w, og, xr = rmat20
+    say("rmat20 csr")
+    from paper_2203_09284_amd.graph import build_csr
+    import ctypes
+    csr, c = build_csr(w["n"], w["src"], w["dst"])
+    fpr.lib().pr_csr_free(ctypes.byref(csr))
+    assert np.array_equal(c.in_ptr, og.in_ptr) and np.array_equal(c.in_src, og.in_src)
+    assert np.array_equal(c.out_deg, og.out_deg) and np.array_equal(c.in_deg, og.in_deg)
+    assert np.array_equal(c.out_to_in, og.offset)
+    g = fpr.Graph(w["n"], w["src"], w["dst"])
+    for mode in ("jacobi", "fused"):
+        say("rmat20 %s parity grade" % mode)
+        x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=1000, mode=mode)
+        assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
+        say("rmat20 %s tol 1e-8" % mode)
+        x, it, res, ok = g.solve(d=D, tol=1e-8, max_iter=1000, mode=mode)
+        xh = x.cpu().numpy()
+        err = l1(xh, xr)
+        cert_gpu = g.certificate(x, d=D)
+        cert_orc = oracle.certificate(og, xh, D) * (1 - D)
+        # ||F(x) - x||_1 sums differences of nearly equal numbers (|F(x)_u - x_u| is
+        # ~1e-9 of x_u here), so rounding in F(x) shows up at the 1e-4 relative level
+        assert abs(cert_gpu - cert_orc) <= 1e-3 * cert_orc + 1e-16
+        assert ok and err <= cert_gpu / (1 - D) * (1 + 1e-6) + 1e-15 and err <= 1e-7
+        for prec_mode in ("jacobi", "fused"):
+            x32, it32, r32, ok32 = g.solve(d=D, tol=1e-8, max_iter=1000, mode=prec_mode, precision="fp32")
+            assert ok32 and l1(x32.cpu().numpy(), xr) <= 1e-7
+    g.close()
+
+
+@pytest.mark.timeout(600)
+def test_rmat20_batched_k64(rmat20):
+    fpr = _fpr()
+    w, og, xr = rmat20
+    n = w["n"]
+    seeds = gg.ppr_seeds(n)
+    say("rmat20 batched k=64")
+    g = fpr.Graph(n, w["src"], w["dst"])
+    X, its, res = g.solve_batched(torch.tensor(seeds, dtype=torch.int32, device="cuda"), d=D, tol=1e-6)
+    Xh = X.cpu().numpy().astype(np.float64)
+    assert np.all(res < 1e-6)
+    assert np.max(np.abs(Xh.sum(axis=0) - 1.0)) <= 1e-5
+    assert np.all(Xh[seeds, np.arange(64)] >= (1 - D) - 1e-6)
+    for j in (0, 17, 41, 63):
+        p = np.zeros(n)
+        p[seeds[j]] = 1.0
+        xj, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=1000, p=p, threads=THREADS)
+        assert l1(Xh[:, j], xj) <= 1e-5, j
+    g.close()
+
+
+@pytest.mark.timeout(900)
+def test_rmat18_weighted_adjoint():
+    fpr = _fpr()
+    w = gg.rmat18_weighted()
+    n = w["n"]
+    gvec = np.zeros(n)
+    gvec[w["targets"]] = 1.0
+    og = oracle.csr(n, w["src"], w["dst"], w["w"])
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=2000, threads=THREADS)
+    lam_o, gp_o, gw_o, _, _ = oracle.adjoint(og, xr, gvec, D, tol=1e-14)
+    say("rmat18 weighted adjoint")
+    g = fpr.Graph(n, w["src"], w["dst"], w["w"], with_adjoint=True)
+    x, it, res, ok = g.solve(d=D, tol=1e-14, max_iter=2000)
+    assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
+    lam, gp, gw, it2, r2 = g.adjoint(x, torch.tensor(gvec, device="cuda"), d=D, tol=1e-14)
+    assert l1(lam.cpu().numpy(), lam_o) <= 1e-8 * np.abs(lam_o).sum()
+    assert l1(gp.cpu().numpy(), gp_o) <= 1e-8 * np.abs(gp_o).sum()
+    assert l1(gw.cpu().numpy(), gw_o) <= 1e-8 * np.abs(gw_o).sum()
+    # duality L = g.x = (1-d) lam.p; both sides carry the solves' error (L1 tol 1e-14)
+    L = float(np.dot(gvec, x.cpu().numpy()))
+    assert abs(L - (1 - D) * float(lam.cpu().numpy().sum()) / n) <= 1e-10 * abs(L)
+    g.close()
+
+
+@pytest.mark.timeout(1200)
+def test_rmat24_bfs_fp32_fused_refined():
+    fpr = _fpr()
+    say("rmat24 generate")
+    w = gg.rmat24_bfs()
+    n, src, dst = w["n"], w["src"], w["dst"]
+    say("rmat24 graph")
+    g = fpr.Graph(n, src, dst)
+    say("rmat24 solve")
+    x, it, res, ok = g.solve(d=D, tol=1e-8, max_iter=1000, mode="fused", precision="fp32",
+                             fp32_tol=1e-7)
+    assert ok
+    cert = g.certificate(x, d=D)
+    say("rmat24 sweeps=%d resid=%.3e cert=%.3e" % (it, res, cert))
+    assert cert / (1 - D) <= 1e-6
+    xh = x.cpu().numpy()
+    assert abs(xh.sum() - 1.0) <= 1e-9
+    # sampled rows: the in-neighbour lists by brute force over the raw edges,
+    # then F(x) at those rows against x
+    rows = gg.sample_distinct(n, 48, 24, 7)
+    lists = oracle.sample_in_lists(n, src, dst, rows)
+    out_deg = np.bincount(src, minlength=n).astype(np.float64)  # the BFS workload is deduplicated
+    D_mass = float(xh[out_deg == 0].sum())
+    for r, lst in zip(rows, lists):
+        contrib = float(np.sum(xh[lst] / out_deg[lst])) if len(lst) else 0.0
+        fr = (1 - D) / n + D * (contrib + D_mass / n)
+        assert abs(fr - xh[r]) <= 1e-5 * xh[r]
+    g.close()
