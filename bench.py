@@ -1,21 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the PageRank hot path on one MI355X.
 
-Workload (default): R-MAT scale 20 (2^20 vertices, edge factor 16, a=0.57,
+Headline workload: R-MAT scale 20 (2^20 vertices, edge factor 16, a=0.57,
 b=c=0.19, seed 2, randomly permuted ids), d = 0.85, stop at L1 < 1e-8.  A
 "step" is one full solve from x = 1/n to L1 < 1e-8 with the loop-fused form
 (the paper's method) in FP64: init, every sweep (pull + update + dangling /
-residual reductions + convergence test, all in the sweep kernel) and the host
-polls.  `value` = edges traversed per second over those sweeps,
-m * sweeps / time, in GTEPS; inputs are resident in HBM before timing.
+residual reductions + convergence test) and the host polls.  `value` = edges
+traversed per second over those sweeps, m' * sweeps / time, in GTEPS; inputs
+are resident in HBM before timing.
 
-The same JSON line carries, for the same graph and tolerance, the plain FP64
-Jacobi pull, the unscaled fused sweep, the FP32 forms (with FP64 refinement
-to 1e-8), the k = 64 batched personalized solve and the roofline of the
-dominant kernel (the fused FP64 sweep), plus the FP64 CPU oracle timed on the
-host cores as a reported baseline.
+The same JSON line carries, on the same GPU:
+  forms       plain FP64 Jacobi, fused FP64 (mass-scaled and unscaled), FP32
+              Jacobi/fused with FP64 refinement to 1e-8, each with its error
+              against the oracle's fixed point;
+  batched     k = 64 one-hot personalized solves (FP32, per-column tol 1e-6)
+              against 64 sequential plain FP64 single-seed solves;
+  er10k       directed Erdos-Renyi n=10,000, m=80,000, plain FP64, tol 1e-10;
+  adjoint     weighted R-MAT scale 18: forward solve + adjoint + gradients;
+  rmat24      R-MAT scale 24 in BFS order: FP32 fused + FP64 refinement
+              against plain FP64 Jacobi, with the FP32 sweep's roofline;
+  roofline    of the dominant kernel (the fused FP64 sweep at scale 20);
+  cpu_baseline the FP64 CPU oracle (Algorithm 1) timed on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--workload rmat20|er10k|rmat24]
+    python bench.py [--steps K] [--warmup W] [--quick]
+    python bench.py --profile FORM [--workload rmat20|rmat24]   (kernel-only driver
+        for rocprofv3: sweeps of one form, then a reference copy kernel)
+    python bench.py --pmc-summary KEY FETCH_CSV WRITE_CSV DRIVER_LOG  (counter runs of
+        that driver -> HBM bytes per sweep launch, into profiles/traffic.json)
 """
 from __future__ import annotations
 
@@ -34,6 +45,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("GTEPS/iter + time-to-L1 1e-8 (fused/batched/fp32 vs plain fp64), % HBM peak")
 HBM_PEAK_GBS = 8000.0
 D = 0.85
+KERNEL_SOURCES = ("sweep.hip", "device_common.h", "internal.h")
+COPY_BYTES = 256 << 20  # the reference copy kernel reads and writes this many bytes
 
 
 def sig(v, digits=6):
@@ -42,6 +55,10 @@ def sig(v, digits=6):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def rounded(d):
+    return {k: (sig(v) if isinstance(v, float) else v) for k, v in d.items()}
 
 
 def workload(name):
@@ -54,7 +71,10 @@ def workload(name):
         w.update(tol=1e-10, desc="directed Erdos-Renyi n=10,000 m=80,000, seed 1")
     elif name == "rmat24":
         w = gg.rmat24_bfs()
-        w.update(tol=1e-8, desc="R-MAT scale 24, edge factor 16, seed 5, BFS order")
+        w.update(tol=1e-8, desc="R-MAT scale 24, edge factor 16, a=.57 b=c=.19, seed 5, BFS order")
+    elif name == "rmat18w":
+        w = gg.rmat18_weighted()
+        w.update(tol=1e-12, desc="weighted R-MAT scale 18, weights U[0.5,1.5], seed 4")
     else:
         raise SystemExit("unknown workload %s" % name)
     return w
@@ -67,53 +87,231 @@ def b_alg(n, m, s):
     return 4 * m + 8 * (n + 1) + 2 * s * n + 4 * n
 
 
-def timed_solves(torch, g, steps, warmup, **kw):
-    for _ in range(warmup):
-        g.solve(**kw)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    times, its, res, x = [], [], [], None
-    for _ in range(steps):
-        e0.record()
-        x, it, r, ok = g.solve(**kw)
-        e1.record()
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
-        its.append(it)
-        res.append(r)
-    torch.cuda.synchronize()
-    return x, np.array(times), its, res
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2203_09284_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def sweep_kernel_ms(torch, g, mode, sweeps=50, reps=3):
-    """Average device time of one sweep launch: HIP events on the library's
-    work stream around `sweeps` back-to-back launches (one hipGraph)."""
-    best = None
-    for _ in range(reps):
-        x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
-        _, ms = g.iterate(x, sweeps, d=D, mode=mode, use_hip_graph=True, timed=True)
-        best = ms if best is None else min(best, ms)
-    return best / sweeps
-
-
-def traffic_record(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter runs, valid only
-    while the kernel source is unchanged."""
+def traffic_record(key):
+    """HBM bytes per launch from the committed rocprofv3 counter runs
+    (profiles/traffic.json), valid only while the kernel sources are unchanged."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(kernel)
-    except Exception:
+        rec = json.load(open(path)).get(key)
+    except (OSError, ValueError):
         return None
-    if not rec:
-        return None
-    src = os.path.join(ROOT, "paper_2203_09284_amd", "csrc", "sweep.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("source_sha") != h:
+    if not rec or rec.get("source_sha") != kernel_source_sha():
         return None
     return rec.get("bytes_per_launch")
+
+
+def timed(torch, fn, steps, warmup):
+    """Median device time (HIP events on torch's current stream, which the
+    library joins on entry and exit) of `steps` calls after `warmup` calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    times, out = [], None
+    for _ in range(steps):
+        e0.record()
+        out = fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    torch.cuda.synchronize()
+    return float(np.median(times)), out
+
+
+def sweep_kernel_us(g, mode, precision="fp64", sweeps=50, reps=3):
+    """Average device time of one launch of the sweep kernel and of its finalize
+    kernel, in microseconds: HIP events recorded by the library on its own work
+    stream around each kernel (pr_profile_sweeps), best of `reps` runs."""
+    best = None
+    for _ in range(reps):
+        ks, kf = g.profile_sweeps(sweeps, d=D, mode=mode, precision=precision)
+        if best is None or ks < best[0]:
+            best = (ks, kf)
+    return best[0] * 1e3, best[1] * 1e3
+
+
+def solve_legs(torch, g, m, tol, steps, warmup, names, x_ref=None):
+    forms = {}
+    for name in names:
+        mode, prec = name.split("-")[:2]
+        kw = dict(d=D, tol=tol, max_iter=1000, mode=mode, precision=prec)
+        if name.endswith("unscaled"):
+            kw["fused_scaled"] = False
+        t_ms, (x, it, r, ok) = timed(torch, lambda: g.solve(**kw), steps, warmup)
+        f = dict(ms=t_ms, sweeps=it, resid=r, converged=bool(ok), gteps=m * it / (t_ms * 1e-3) / 1e9)
+        if x_ref is not None:
+            f["l1_vs_oracle"] = float(np.abs(x.cpu().numpy() - x_ref).sum())
+        else:
+            f["certificate_bound"] = g.certificate(x, d=D) / (1 - D)
+        forms[name] = f
+        log("%-20s %9.3f ms  sweeps=%3d  GTEPS=%8.2f  resid=%.2e" % (name, t_ms, it, f["gteps"], r))
+    return forms
+
+
+def roofline(achieved_gbs, traffic, kernel, bytes_launch, us_launch):
+    return {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "bytes_per_launch": bytes_launch, "us_per_launch": round(us_launch, 2)}
+
+
+# ----------------------------------------------------------------- legs --
+
+def leg_batched(torch, fpr, g, n, m, steps):
+    import graphgen as gg
+    seeds_h = gg.ppr_seeds(n)
+    seeds = torch.tensor(seeds_h, dtype=torch.int32, device="cuda")
+    tune = g.autotune_batched(64)
+    t_b, (X, its, res) = timed(torch, lambda: g.solve_batched(seeds, d=D, tol=1e-6), max(3, steps // 4), 1)
+    log("batched k=64 tile=%d: %.2f ms, sweeps max %d" % (tune, t_b, its.max()))
+
+    ps = torch.zeros((64, n), dtype=torch.float64, device="cuda")
+    ps[torch.arange(64, device="cuda"), seeds.long()] = 1.0
+    xs = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def sequential():
+        return [g.solve(d=D, tol=1e-6, max_iter=1000, mode="jacobi", p=ps[j], x=xs)[1] for j in range(64)]
+    t_s, its_s = timed(torch, sequential, 1, 1)
+    log("64 sequential FP64 Jacobi PPR solves: %.2f ms" % t_s)
+    col = float(its.sum())
+    return rounded(dict(k=64, tol=1e-6, tile=tune, ms=t_b, max_sweeps=int(its.max()),
+                        column_sweeps=int(col), column_gteps=m * col / (t_b * 1e-3) / 1e9,
+                        sequential_fp64_ms=t_s, sequential_sweeps=int(sum(its_s)),
+                        speedup_vs_sequential_fp64=t_s / t_b))
+
+
+def leg_er10k(torch, fpr, oracle, steps, warmup):
+    w = workload("er10k")
+    og = oracle.csr(w["n"], w["src"], w["dst"])
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=1000)
+    g = fpr.Graph(w["n"], w["src"], w["dst"])
+    forms = solve_legs(torch, g, g.m, 1e-10, steps, warmup, ["jacobi-fp64", "fused-fp64"], xr)
+    g.close()
+    return dict(workload="er10k", n=w["n"], m=og.m, tol=1e-10, forms={k: rounded(v) for k, v in forms.items()})
+
+
+def leg_adjoint(torch, fpr, oracle, steps, warmup, threads):
+    w = workload("rmat18w")
+    n = w["n"]
+    gvec = np.zeros(n)
+    gvec[w["targets"]] = 1.0
+    g = fpr.Graph(n, w["src"], w["dst"], w["w"], with_adjoint=True)
+    gdev = torch.tensor(gvec, device="cuda")
+    t_f, (x, it, _, _) = timed(torch, lambda: g.solve(d=D, tol=1e-12, max_iter=2000), steps, warmup)
+    t_a, (lam, gp, gw, it2, _) = timed(torch, lambda: g.adjoint(x, gdev, d=D, tol=1e-12), steps, warmup)
+    log("adjoint rmat18w: forward %.3f ms (%d sweeps), adjoint+grads %.3f ms (%d sweeps)" % (t_f, it, t_a, it2))
+    og = oracle.csr(n, w["src"], w["dst"], w["w"])
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=2000, threads=threads)
+    lam_o, gp_o, gw_o, _, _ = oracle.adjoint(og, xr, gvec, D, tol=1e-14)
+    rel = lambda a, b: float(np.abs(a.cpu().numpy() - b).sum() / np.abs(b).sum())
+    out = dict(workload="rmat18w", n=n, m=g.m, tol=1e-12, forward_ms=t_f, forward_sweeps=it,
+               adjoint_ms=t_a, adjoint_sweeps=it2, rel_l1_lambda=rel(lam, lam_o), rel_l1_dLdp=rel(gp, gp_o),
+               rel_l1_dLdw=rel(gw, gw_o))
+    g.close()
+    return rounded(out)
+
+
+def leg_rmat24(torch, fpr, steps, warmup):
+    t0 = time.perf_counter()
+    w = workload("rmat24")
+    n = w["n"]
+    log("generated rmat24 in %.1fs" % (time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    g = fpr.Graph(n, w["src"], w["dst"])
+    del w
+    m = g.m
+    log("rmat24 on device: m'=%d setup %.1fs" % (m, time.perf_counter() - t0))
+    forms = solve_legs(torch, g, m, 1e-8, steps, warmup, ["jacobi-fp64", "fused-fp32", "jacobi-fp32",
+                                                          "fused-fp64"])
+    k32, f32 = sweep_kernel_us(g, "fused", "fp32", sweeps=20)
+    k64, _ = sweep_kernel_us(g, "jacobi", "fp64", sweeps=20)
+    b32 = b_alg(n, m, 4)
+    ach = b32 / (k32 * 1e-6) / 1e9
+    log("rmat24 sweep kernel: fused fp32 %.1f us (%.0f GB/s alg) + finalize %.1f us, jacobi fp64 %.1f us"
+        % (k32, ach, f32, k64))
+    out = dict(workload="rmat24", n=n, m=m, tol=1e-8, fp32_tol=1e-7,
+               forms={k: rounded(v) for k, v in forms.items()},
+               speedup_fused_fp32_vs_jacobi_fp64=sig(forms["jacobi-fp64"]["ms"] / forms["fused-fp32"]["ms"]),
+               roofline=roofline(ach, traffic_record("fused_fp32_rmat24"), "k_sweep<float, fused>", b32, k32),
+               finalize_us=round(f32, 2), jacobi_fp64_sweep_kernel_us=round(k64, 2))
+    g.close()
+    return out
+
+
+def profile_driver(args):
+    """Kernel-only run for rocprofv3: `sweeps` sweeps of one form, launched one
+    by one, then five reference copies of COPY_BYTES (read + write) through
+    torch's elementwise kernel, to calibrate the HBM byte counters."""
+    import torch
+    import paper_2203_09284_amd as fpr
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    g = fpr.Graph(w["n"], w["src"], w["dst"])
+    mode, prec = args.profile.split("-")[:2]
+    x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
+    g.iterate(x, args.profile_sweeps, d=D, mode=mode, precision=prec, use_hip_graph=False)
+    torch.cuda.synchronize()
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": args.profile, "workload": args.workload, "n": g.n, "m": g.m,
+                      "sweeps": args.profile_sweeps, "copy_bytes": COPY_BYTES,
+                      "b_alg": b_alg(g.n, g.m, 8 if prec == "fp64" else 4),
+                      "source_sha": kernel_source_sha()}), flush=True)
+    g.close()
+
+
+def pmc_summary(args):
+    """Turn two rocprofv3 --pmc runs of the --profile driver (FETCH_SIZE, then
+    WRITE_SIZE; counter_collection CSVs) into the bytes per launch of the sweep
+    kernel.  Each counter is scaled by bytes / counter-reading of the reference
+    copy kernel of the same run (torch.mul over COPY_BYTES, read + write).
+    Writes the record into profiles/traffic.json under --pmc-key."""
+    import csv
+    key, fetch_csv, write_csv, driver_log = args.pmc_summary
+    drv = json.loads([ln for ln in open(driver_log) if ln.startswith('{"profile"')][-1])
+
+    def read(path, counter):
+        sweep, copy = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
+            if "k_sweep<" in r["Kernel_Name"]:
+                sweep.append(v)
+            elif "MulFunctor" in r["Kernel_Name"]:
+                copy.append(v)
+        if not sweep or not copy:
+            raise SystemExit("%s: no sweep or reference copy dispatches for %s" % (path, counter))
+        return float(np.mean(sweep)), float(np.median(copy)), len(sweep)
+    f_sweep, f_copy, n_f = read(fetch_csv, "FETCH_SIZE")
+    w_sweep, w_copy, n_w = read(write_csv, "WRITE_SIZE")
+    cb = drv["copy_bytes"]
+    rd = f_sweep * cb / f_copy
+    wr = w_sweep * cb / w_copy
+    rec = {"bytes_per_launch": int(round(rd + wr)), "read_bytes": int(round(rd)), "write_bytes": int(round(wr)),
+           "fetch_scale": sig(cb / f_copy), "write_scale": sig(cb / w_copy),
+           "fetch_raw_bytes_per_launch": int(round(f_sweep)), "write_raw_bytes_per_launch": int(round(w_sweep)),
+           "launches": [n_f, n_w], "b_alg": drv["b_alg"], "amplification": sig((rd + wr) / drv["b_alg"], 4),
+           "n": drv["n"], "m": drv["m"], "source_sha": drv["source_sha"]}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    allrec = json.load(open(path)) if os.path.exists(path) else {}
+    allrec[key] = rec
+    with open(path, "w") as f:
+        json.dump(allrec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps({key: rec}))
 
 
 def main():
@@ -121,96 +319,97 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--quick", action="store_true", help="headline workload only (no extra legs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-rmat24", action="store_true")
+    ap.add_argument("--profile", default=None, help="jacobi-fp64|fused-fp64|jacobi-fp32|fused-fp32")
+    ap.add_argument("--profile-sweeps", type=int, default=20)
+    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("KEY", "FETCH_CSV", "WRITE_CSV", "DRIVER_LOG"))
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        profile_driver(args)
+        return
 
     import torch
     import paper_2203_09284_amd as fpr
+    import oracle
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    cores = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
-    w = workload(args.workload)
+    w = workload("rmat20")
     n, tol = w["n"], w["tol"]
-    log("generated %s: n=%d raw m=%d in %.1fs" % (w["name"], n, len(w["src"]), time.perf_counter() - t0))
+    log("generated rmat20: n=%d raw m=%d in %.1fs" % (n, len(w["src"]), time.perf_counter() - t0))
     t0 = time.perf_counter()
     g = fpr.Graph(n, w["src"], w["dst"])
     setup_s = time.perf_counter() - t0
     st = g.stats()
     m = g.m
     log("graph on device: m'=%d items=%d grid=%d setup %.1fs" % (m, st["n_items"], st["grid"], setup_s))
-
-    forms = {}
-    ref = None
-
-    def leg(name, **kw):
-        x, times, its, res = timed_solves(torch, g, args.steps, args.warmup, d=D, tol=tol,
-                                          max_iter=1000, **kw)
-        t_ms = float(np.median(times))
-        it = int(np.median(its))
-        forms[name] = dict(ms=t_ms, sweeps=it, resid=float(res[-1]),
-                           gteps=m * it / (t_ms * 1e-3) / 1e9, x=x.clone())
-        log("%-18s %8.3f ms  sweeps=%3d  GTEPS=%7.2f  resid=%.2e" % (name, t_ms, it, forms[name]["gteps"],
-                                                                      res[-1]))
-
-    leg("jacobi-fp64", mode="jacobi", precision="fp64")
-    leg("fused-fp64", mode="fused", precision="fp64")
-    leg("fused-fp64-unscaled", mode="fused", precision="fp64", fused_scaled=False)
-    leg("jacobi-fp32", mode="jacobi", precision="fp32")
-    leg("fused-fp32", mode="fused", precision="fp32")
-
-    # per-launch device time of the sweep kernels
-    k_fused = sweep_kernel_ms(torch, g, "fused")
-    k_jac = sweep_kernel_ms(torch, g, "jacobi")
-    log("sweep kernel: fused %.1f us, jacobi %.1f us per launch" % (k_fused * 1e3, k_jac * 1e3))
-
-    # batched personalized PageRank, k = 64 one-hot seeds
-    batched = None
-    if not args.no_batched and args.workload == "rmat20":
-        try:
-            import graphgen as gg
-            seeds = torch.tensor(gg.ppr_seeds(n), dtype=torch.int32, device="cuda")
-            for _ in range(1):
-                g.solve_batched(seeds, d=D, tol=1e-6)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            X, its, res = g.solve_batched(seeds, d=D, tol=1e-6)
-            e1.record()
-            e1.synchronize()
-            bms = e0.elapsed_time(e1)
-            batched = dict(k=64, tol=1e-6, ms=bms, max_sweeps=int(its.max()),
-                           column_sweeps=int(its.sum()),
-                           column_gteps=m * float(its.sum()) / (bms * 1e-3) / 1e9)
-            log("batched k=64: %.2f ms, sweeps max %d" % (bms, its.max()))
-        except Exception as e:  # reported, not fatal: the forward legs stand on their own
-            batched = dict(error=str(e)[:200])
-            log("batched leg failed:", e)
-
-    # accuracy of every form against the oracle's fixed point, and the CPU baseline
-    cpu = None
-    import oracle
     og = oracle.csr(n, w["src"], w["dst"])
-    cores = min(os.cpu_count() or 1, 16)
     x_ref, _, _ = oracle.pagerank_ec(og, D, tol=1e-13, max_iter=1000, threads=cores)
-    for name, f in forms.items():
-        f["l1_vs_oracle"] = float(np.abs(f.pop("x").cpu().numpy() - x_ref).sum())
+
+    forms = solve_legs(torch, g, m, tol, args.steps, args.warmup,
+                       ["jacobi-fp64", "fused-fp64", "fused-fp64-unscaled", "jacobi-fp32", "fused-fp32"],
+                       x_ref)
+    kern = {name: sweep_kernel_us(g, *name.split("-")) for name in
+            ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32")}
+    for name, (ks, kf) in kern.items():
+        log("%-12s sweep kernel %.1f us + finalize %.1f us per launch" % (name, ks, kf))
+    k_fused = kern["fused-fp64"][0]
+
+    extra = {}
+    if not args.quick:
+        for name, fn in (("batched", lambda: leg_batched(torch, fpr, g, n, m, args.steps)),
+                         ("er10k", lambda: leg_er10k(torch, fpr, oracle, args.steps, args.warmup)),
+                         ("adjoint", lambda: leg_adjoint(torch, fpr, oracle, args.steps, args.warmup, cores))):
+            try:
+                extra[name] = fn()
+            except Exception as e:  # reported, not fatal: the headline stands on its own
+                extra[name] = dict(error=str(e)[:300])
+                log("%s leg failed: %s" % (name, e))
+
+    cpu = None
     if not args.no_cpu_baseline:
+        # the oracle as it stands: Algorithm 1 with contributionList/offsetList,
+        # FP64, the same graph and tolerance; median of three full solves
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, it_cpu, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=1000, threads=cores)
+            runs.append(time.perf_counter() - t0)
+        cpu_s = float(np.median(runs))
         t0 = time.perf_counter()
-        _, it_cpu, r_cpu = oracle.pagerank_ec(og, D, tol=tol, max_iter=1000, threads=cores)
-        cpu_s = time.perf_counter() - t0
-        cpu = dict(value=og.m * it_cpu / cpu_s / 1e9, unit="GTEPS", cores=cores, kind="oracle",
-                   sample="full solve of the same graph to L1<%g: Algorithm 1 with contributionList "
-                          "and offsetList, FP64, %d sweeps in %.2f s" % (tol, it_cpu, cpu_s))
+        _, it1, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=1000, threads=1)
+        one_s = time.perf_counter() - t0
+        cpu = dict(value=sig(og.m * it_cpu / cpu_s / 1e9), unit="GTEPS", cores=cores, kind="oracle",
+                   sample="full solve of the same R-MAT-20 graph to L1<%g (%d sweeps): Algorithm 1 with "
+                          "contributionList and offsetList, FP64, median of 3 runs of %.2f s on %d threads; "
+                          "1 thread: %.2f s" % (tol, it_cpu, cpu_s, cores, one_s),
+                   single_thread_gteps=sig(og.m * it1 / one_s / 1e9))
+        log("cpu oracle: %.3f GTEPS on %d threads, %.3f on 1" % (cpu["value"], cores, cpu["single_thread_gteps"]))
+    g.close()
+    del og, w
+
+    if not args.quick and not args.no_rmat24:
+        try:
+            extra["rmat24"] = leg_rmat24(torch, fpr, max(3, args.steps // 4), 1)
+        except Exception as e:
+            extra["rmat24"] = dict(error=str(e)[:300])
+            log("rmat24 leg failed: %s" % e)
 
     head = forms["fused-fp64"]
     bytes_sweep = b_alg(n, m, 8)
-    achieved = bytes_sweep / (k_fused * 1e-3) / 1e9
+    achieved = bytes_sweep / (k_fused * 1e-6) / 1e9
     out = {
         "metric": METRIC,
         "value": round(head["gteps"], 3),
@@ -224,23 +423,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w["name"], "graph": w["desc"], "n": n, "m": m, "d": D, "tol": tol,
+        "config": {"workload": "rmat20", "graph": w_desc("rmat20"), "n": n, "m": m, "d": D, "tol": tol,
                    "form": "fused-fp64", "step": "one solve from 1/n to L1<tol"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_record("fused_fp64_" + args.workload),
-                     "kernel": "k_sweep<double, fused>", "bytes_per_launch": bytes_sweep,
-                     "us_per_launch": round(k_fused * 1e3, 2)},
+        "roofline": roofline(achieved, traffic_record("fused_fp64_rmat20"), "k_sweep<double, fused>",
+                             bytes_sweep, k_fused),
         "cpu_baseline": cpu,
-        "forms": {k: {kk: (sig(vv) if isinstance(vv, float) else vv) for kk, vv in f.items()}
-                  for k, f in forms.items()},
-        "jacobi_sweep_us": round(k_jac * 1e3, 2),
-        "speedup_fused_vs_jacobi_time_to_tol": round(forms["jacobi-fp64"]["ms"] / head["ms"], 3),
-        "batched": batched,
+        "forms": {k: rounded(f) for k, f in forms.items()},
+        "kernel_us": {k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
+        "speedup_vs_jacobi_fp64_time_to_tol": {
+            k: sig(forms["jacobi-fp64"]["ms"] / f["ms"]) for k, f in forms.items() if k != "jacobi-fp64"},
         "setup_s": round(setup_s, 2),
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
-    g.close()
+
+
+def w_desc(name):
+    return {"rmat20": "R-MAT scale 20, edge factor 16, a=.57 b=c=.19, seed 2, permuted ids"}[name]
 
 
 if __name__ == "__main__":

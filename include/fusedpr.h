@@ -11,8 +11,9 @@
  * total rank of dangling vertices (W_v = 0), spread uniformly, and p the
  * teleport vector (1/n everywhere unless given).  It is reached either by the
  * edge-centric Jacobi pull (Section 3, Algorithm 1) or by the loop-fused
- * in-place Gauss-Seidel-like sweep (Section 4, Algorithm 2; Eq. 9), run
- * block-asynchronously as in the paper's parallel variant (Section 6.3).
+ * Gauss-Seidel-like sweep (Section 4, Algorithm 2; Eq. 9), here over blocks
+ * of vertices: each block reads the contributions that earlier blocks wrote
+ * in the same sweep (see pr_plan_opts.gs_blocks).
  *
  * Conventions shared by every entry point:
  *   - Return value: PR_OK (0) on success, PR_NOT_CONVERGED (1) when an
@@ -112,18 +113,26 @@ void pr_csr_free(pr_csr *csr);
 typedef struct pr_graph pr_graph;
 
 typedef struct pr_plan_opts {
-  int chunk;             /* lists longer than this are split into chunks of this many edges,
-                            one wavefront each (default 2048, range [64, 2^20]) */
+  int chunk;             /* lists longer than this (hubs) are summed by several wavefronts:
+                            up to 8 * chunk edges by the 8 wavefronts of one workgroup, longer
+                            ones in chunk-edge pieces, one wavefront each, added by the
+                            finalize kernel (default 1024, range [64, 2^20]) */
   int tile_max_row;      /* lists of 1..tile_max_row edges are packed into 512-edge tiles
                             (default 512, at most 512; lowered to chunk if larger); longer
                             ones get a wavefront each */
   int tile_rows;         /* rows per tile at most (1..128, default 128) */
-  int steps;             /* one-wavefront rows per work item (default 4) */
+  int steps;             /* one-wavefront rows per work item (default 1) */
   int hot_slots;         /* gather slots staged in LDS per sweep workgroup (-1 = as many as fit,
                             0 = none) */
   int gather_layout;     /* 1 (default): store the gathered array sorted by gather count,
                             so the hottest vertices come first; 0: vertex-id order */
   int with_adjoint;      /* also plan the out-edge (transposed) pull for pr_adjoint */
+  int gs_blocks;         /* Gauss-Seidel blocks of the fused form (1..64, default 2): the
+                            vertices, in decreasing out-degree, are cut into this many blocks
+                            of equal in-edge count (chunked rows join the last block) and
+                            swept one launch each, so every block reads the contributions the
+                            blocks before it wrote in the same sweep (Eq. 9 over the blocks).
+                            The Jacobi form ignores it. */
 } pr_plan_opts;
 
 void pr_plan_opts_default(pr_plan_opts *o);
@@ -153,7 +162,7 @@ enum pr_dangling { PR_DANGLING_UNIFORM = 0, PR_DANGLING_LEAK = 1 };
 enum pr_norm { PR_NORM_L1 = 0, PR_NORM_LINF = 1 };
 
 typedef struct pr_opts {
-  int mode;             /* PR_JACOBI (Algorithm 1) or PR_FUSED (Algorithm 2, in place) */
+  int mode;             /* PR_JACOBI (Algorithm 1) or PR_FUSED (Algorithm 2, block Gauss-Seidel) */
   int precision;        /* PR_FP64, or PR_FP32: ranks and contributions stored and summed
                            in FP32 with compensated sums; residual and dangling mass in FP64 */
   int dangling;         /* PR_DANGLING_UNIFORM, or PR_DANGLING_LEAK (the paper's literal
@@ -193,14 +202,25 @@ void pr_opts_default(pr_opts *o);
 int pr_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, const double *p,
              double *x, int *iters, double *resid, void *stream);
 
-/* Exactly `sweeps` sweeps from the x passed in (no convergence test), FP64,
- * in the form o->mode selects.  resid (host, nullable) receives the residual
+/* Exactly `sweeps` sweeps from the x passed in (no convergence test), in the
+ * form o->mode and the precision o->precision select.  x is FP64 on entry and
+ * on return; FP32 sweeps run on an internal FP32 copy that is cast back after
+ * the last sweep (no refinement).  resid (host, nullable) receives the residual
  * of the last sweep.  elapsed_ms (host, nullable) receives the time between
  * HIP events recorded on the library's work stream right before the first
  * and right after the last sweep kernel (launched as one hipGraph when
  * o->use_hip_graph), i.e. the sweeps' device time. */
 int pr_iterate(pr_graph *g, double d, const pr_opts *o, const double *p, double *x, int sweeps,
                double *resid, double *elapsed_ms, void *stream);
+
+/* Per-kernel device time of the sweep: `sweeps` sweeps from x (FP64 on entry
+ * and on return, as pr_iterate; teleport 1/n), launched one by one on the
+ * library's work stream with HIP events recorded before the sweep kernel,
+ * between it and its reduction (finalize) kernel, and after the latter.
+ *   sweep_ms, finalize_ms   host: average milliseconds per launch of each
+ * Measurement support for the sweep of the recurrence above; 1 <= sweeps <= 4096. */
+int pr_profile_sweeps(pr_graph *g, double d, const pr_opts *o, double *x, int sweeps, double *sweep_ms,
+                      double *finalize_ms, void *stream);
 
 /* ||F(x) - x||_1 for any device vector x (FP64), where F is one exact
  * application of the recurrence above.  Bounds the error of x:

@@ -1,6 +1,6 @@
 """FusEd-PageRank on MI355X (gfx950): the per-iteration sparse pull of
 PageRank in the paper's edge-centric Jacobi form (Algorithm 1) and its
-loop-fused in-place Gauss-Seidel-like form (Algorithm 2), as hand-written HIP
+loop-fused Gauss-Seidel-like form (Algorithm 2, over vertex blocks), as hand-written HIP
 kernels behind a C ABI (include/fusedpr.h), plus batched personalized
 PageRank and an implicit-differentiation adjoint.
 

@@ -30,7 +30,7 @@ class PrCsr(ctypes.Structure):
 class PrPlanOpts(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int), ("tile_max_row", ctypes.c_int), ("tile_rows", ctypes.c_int),
                 ("steps", ctypes.c_int), ("hot_slots", ctypes.c_int),
-                ("gather_layout", ctypes.c_int), ("with_adjoint", ctypes.c_int)]
+                ("gather_layout", ctypes.c_int), ("with_adjoint", ctypes.c_int), ("gs_blocks", ctypes.c_int)]
 
 
 class PrGraphStats(ctypes.Structure):
@@ -64,6 +64,8 @@ SIGNATURES = {
     "pr_iterate": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts), vp, vp, ctypes.c_int, c_f64p,
                                   c_f64p, vp]),
     "pr_certificate": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, c_f64p, vp]),
+    "pr_profile_sweeps": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts), vp, ctypes.c_int, c_f64p,
+                                         c_f64p, vp]),
     "pr_solve_batched": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
                                         ctypes.c_int, vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
     "pr_autotune_batched": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), vp]),

@@ -516,7 +516,7 @@ BArgs make_bargs(pr_graph *g, BWork &w, double d, int passes, int pass0) {
   a.rowpos = P.rowpos;
   a.rptr = P.rptr;
   a.idx = P.idx;
-  a.items = P.items;
+  a.items = P.bitems;
   a.tiles = P.tiles;
   a.tidx = P.tidx;
   a.tmask = P.tmask;
@@ -533,7 +533,7 @@ BArgs make_bargs(pr_graph *g, BWork &w, double d, int passes, int pass0) {
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
   a.n = g->n;
-  a.n_items = P.n_items;
+  a.n_items = P.n_bitems;
   a.n_split = P.n_split;
   a.n_chunks = std::max(1, P.n_chunks);
   a.n_waves = P.n_waves;

@@ -34,13 +34,14 @@ constexpr int kWaves = kBlock / 64;
 #endif
 constexpr int kSweepBlock = FPR_SWEEP_BLOCK;  // threads per workgroup of the sweep
 constexpr int kSweepWaves = kSweepBlock / 64;
+constexpr int kFinBlock = 1024;  // threads of the one-workgroup finalize kernel
 constexpr int kBatch = 8;                     // loads in flight per lane and batch
 constexpr int kPrefetch = 4;                  // row rounds whose list bounds are loaded up front
 constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather slots, per workgroup
 constexpr int kTileEdges = 512;               // edges of a tile: 8 consecutive per lane
 constexpr int kTileRows = 128;                // rows of a tile at most (row sums staged in LDS)
 
-enum ItemKind : int { kTile = 0, kRows = 1, kHeavy = 2, kZero = 3 };
+enum ItemKind : int { kTile = 0, kRows = 1, kHeavy = 2, kZero = 3, kHubWG = 4 };
 
 // Sweep flags (runtime, uniform across the grid)
 enum SweepFlags : int {
@@ -74,23 +75,35 @@ struct DevPlan {
   uint32_t *rptr = nullptr;   // [n+1] edge offsets (bin order)
   int32_t *idx = nullptr;     // [m] gather-layout slots of the neighbours
   double *w = nullptr;        // [m] edge weights or null
-  int4 *items = nullptr;      // [n_items] {kTile, tile} | {kRows, first, end, lanes per row} |
-                              // {kHeavy, row, chunk, slot} | {kZero, first, end}
+  int4 *items = nullptr;      // [n_items] sweep list: {kTile, tile} | {kRows, first, end, lanes per
+                              // row} | {kHubWG, row} (whole workgroup) | {kHeavy, row, chunk, slot}
+                              // | {kZero, first, end}
+  int4 *bitems = nullptr;     // [n_bitems] batched list: as items, hubs as {kHeavy, row, chunk, slot}
   int4 *tiles = nullptr;      // [n_tiles] {first row, rows, edges, 0}
   int32_t *tidx = nullptr;    // [n_tiles * 512] tile edges, lane-transposed: [k][lane] = edge 8*lane+k
   double *tw = nullptr;       // [n_tiles * 512] their weights, same layout (or null)
   uint8_t *tmask = nullptr;   // [n_tiles * 64] per lane: bit k set if edge 8*lane+k starts a row
   int4 *hsplit = nullptr;     // [n_split] rows split into chunks: {row index, first slot, chunks, 0}
+                              // (batched list: every hub)
+  int4 *msplit = nullptr;     // [n_msplit] the hubs the sweep list splits into chunks (same slots)
   double *hpart = nullptr;    // [n_chunks] partial sums of the chunks of split rows
-  double *wave_part = nullptr;  // [3][waves] per-wavefront change, dangling mass, total mass
+  double *wave_part = nullptr;  // [3][part_stride] per-workgroup change, dangling mass, total mass;
+                                // block b's launch writes from b * (workgroups per launch)
   SweepState *st = nullptr;
   int n_items = 0;
+  int n_bitems = 0;
   int n_tiles = 0;
   int n_heavy = 0;
   int n_split = 0;
+  int n_msplit = 0;
   int n_chunks = 0;
   int chunk = 2048;
   int n_waves = 0;  // wavefronts of one sweep launch
+  int part_stride = 0;
+  int n_blocks = 1;               // Gauss-Seidel blocks of the fused form
+  std::vector<int> block_items;   // [n_blocks + 1] first work item of each block
+  std::vector<int> block_slots;   // [n_blocks + 1] first gather slot of each block's non-hub
+                                  // vertices (the hubs' slots come before block 0's)
   int64_t n_light = 0, n_medium = 0, n_heavy_rows = 0;  // rows in tiles, one wavefront each, chunked
   int64_t e_light = 0, e_medium = 0, e_heavy = 0;
   int64_t bytes = 0;

@@ -14,15 +14,20 @@
 //   L > chunk        hubs: each chunk of `chunk` edges is one item; the
 //                    chunk sums go to per-chunk slots and the sweep's
 //                    finalize kernel adds them in chunk order.
-// Rows are laid out hubs, one-wavefront rows, tile rows, zero rows (vertex ids
-// ascending inside each bin); that is also the order work items run in.
+// The vertices are first cut into Gauss-Seidel blocks for the fused form
+// (gs_blocks; block 0 holds the highest out-degree vertices, the hubs go to
+// the last block).
+// Rows are laid out block by block, and inside a block hubs, one-wavefront
+// rows, tile rows, zero rows (vertex ids ascending inside each bin); that is
+// also the order work items run in.
 //
 // Gather layout: the array the pull gathers from (contributions forward,
-// adjoint values backward) is stored with vertices sorted by how often they
-// are gathered (descending, ties by id), and the neighbour lists hold those
-// slots.  On power-law graphs the few vertices that feed most edges then pack
-// into the first slots, which each sweep workgroup keeps in LDS.  Values are
-// unchanged; only addresses move.
+// adjoint values backward) is stored hubs first, then block by block, each
+// group with its vertices sorted by how often they are gathered (descending,
+// ties by id); the neighbour lists hold those slots.  On power-law graphs the
+// few vertices that feed most edges then pack into the first slots, which
+// each sweep workgroup keeps in LDS, and the slots of each block form one
+// range.  Values are unchanged; only addresses move.
 #include <math.h>
 #include <string.h>
 
@@ -35,13 +40,14 @@ using namespace fpr;
 
 extern "C" void pr_plan_opts_default(pr_plan_opts *o) {
   if (!o) return;
-  o->chunk = 2048;
+  o->chunk = 1024;
   o->tile_max_row = kTileEdges;
   o->tile_rows = kTileRows;
-  o->steps = 4;
+  o->steps = 1;
   o->hot_slots = -1;
   o->gather_layout = 1;
   o->with_adjoint = 0;
+  o->gs_blocks = 2;
 }
 
 int fpr_dev_alloc(pr_graph *g, void **p, size_t bytes) {
@@ -73,13 +79,55 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   P.m = ptr[n];
   P.chunk = o.chunk;
   const int64_t m = P.m;
-  // bins: 0 hubs, 1 one-wavefront rows, 2 tile rows, 3 zero rows
-  std::vector<uint32_t> bins[4];
-  for (int64_t v = 0; v < n; ++v) {
-    int64_t L = ptr[v + 1] - ptr[v];
-    int b = L > o.chunk ? 0 : L > o.tile_max_row ? 1 : L > 0 ? 2 : 3;
-    bins[b].push_back((uint32_t)v);
+  // Gauss-Seidel blocks of the fused form: the vertices other than the
+  // chunked rows (hubs), in decreasing gather count, are cut where the running
+  // in-edge count passes b/B of all edges (equal work per block); the hubs
+  // join the last block, whose chunk sums the finalize kernel adds.  Every
+  // vertex of block b is updated before any vertex of block b+1 reads.
+  std::vector<uint32_t> freq(n, 0), order(n);
+  for (int64_t e = 0; e < m; ++e) freq[nbr[e]]++;
+  for (int64_t v = 0; v < n; ++v) order[v] = (uint32_t)v;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return freq[a] > freq[b]; });
+  auto bin_of = [&](int64_t v) {
+    const int64_t L = ptr[v + 1] - ptr[v];
+    return L > o.chunk ? 0 : L > o.tile_max_row ? 1 : L > 0 ? 2 : 3;
+  };
+  const int B = std::max(1, std::min<int>(o.gs_blocks, 64));
+  std::vector<uint8_t> blk(n, 0);
+  {
+    int64_t cum = 0;
+    for (int64_t k = 0; k < n; ++k) {
+      const uint32_t v = order[k];
+      if (bin_of(v) == 0) {
+        blk[v] = (uint8_t)(B - 1);
+        continue;
+      }
+      blk[v] = (uint8_t)std::min<int64_t>(B - 1, m > 0 ? (cum * B) / m : 0);
+      cum += ptr[v + 1] - ptr[v];
+    }
   }
+  // Gather layout: the hubs first, then the other vertices block by block;
+  // inside each group by decreasing gather count (gather_layout = 1) or by
+  // vertex id (0).  block_slots[b] = first slot of block b's non-hub vertices,
+  // so the slots block b+1 reads fresh are [block_slots[0], block_slots[b+1]).
+  std::vector<uint32_t> pos(n);
+  {
+    std::vector<uint32_t> lay(n);
+    for (int64_t k = 0; k < n; ++k) lay[k] = o.gather_layout ? order[k] : (uint32_t)k;
+    auto group = [&](uint32_t v) { return bin_of(v) == 0 ? -1 : (int)blk[v]; };
+    std::stable_sort(lay.begin(), lay.end(), [&](uint32_t a, uint32_t b) { return group(a) < group(b); });
+    for (int64_t k = 0; k < n; ++k) pos[lay[k]] = (uint32_t)k;
+    P.block_slots.assign(B + 1, (int)n);
+    for (int64_t k = n - 1; k >= 0; --k)
+      if (group(lay[k]) >= 0) P.block_slots[group(lay[k])] = (int)k;
+    for (int b = B - 1; b >= 0; --b) P.block_slots[b] = std::min(P.block_slots[b], P.block_slots[b + 1]);
+  }
+  // bins per block: 0 hubs, 1 one-wavefront rows, 2 tile rows, 3 zero rows
+  std::vector<std::vector<uint32_t>> bins((size_t)B * 4);
+  for (int64_t v = 0; v < n; ++v) bins[(size_t)blk[v] * 4 + bin_of(v)].push_back((uint32_t)v);
+  for (int b = 0; b < B; ++b)  // one-wavefront rows longest first: long items start early
+    std::stable_sort(bins[(size_t)b * 4 + 1].begin(), bins[(size_t)b * 4 + 1].end(),
+                     [&](uint32_t a, uint32_t c) { return ptr[a + 1] - ptr[a] > ptr[c + 1] - ptr[c]; });
   std::vector<uint32_t> rows;
   rows.reserve(n);
   for (auto &b : bins) rows.insert(rows.end(), b.begin(), b.end());
@@ -88,18 +136,6 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   for (int64_t i = 0; i < n; ++i) {
     uint32_t v = rows[i];
     rptr[i + 1] = rptr[i] + (uint32_t)(ptr[v + 1] - ptr[v]);
-  }
-  // gather layout: slot of each vertex
-  std::vector<uint32_t> pos(n);
-  if (o.gather_layout) {
-    std::vector<uint32_t> freq(n, 0), order(n);
-    for (int64_t e = 0; e < m; ++e) freq[nbr[e]]++;
-    for (int64_t v = 0; v < n; ++v) order[v] = (uint32_t)v;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t a, uint32_t b) { return freq[a] > freq[b]; });
-    for (int64_t k = 0; k < n; ++k) pos[order[k]] = (uint32_t)k;
-  } else {
-    for (int64_t v = 0; v < n; ++v) pos[v] = (uint32_t)v;
   }
   std::vector<uint32_t> rowpos(n);
   for (int64_t i = 0; i < n; ++i) rowpos[i] = pos[rows[i]];
@@ -112,88 +148,150 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     if (w) memcpy(&wv[rptr[i]], w + ptr[v], sizeof(double) * L);
   }
 
-  // work items in launch order: hub chunks, one-wavefront rows, tiles, zero rows
-  std::vector<int4> items, hsplit, tiles;
+  // Work items.  Per block, in launch order: hubs, one-wavefront rows (longest
+  // first), tiles, zero rows.  Two lists share the rows and tiles:
+  //  * the sweep list: a hub of at most 8 * chunk edges is one item of a
+  //    whole workgroup: 8 copies at positions 8q..8q+7, which every launch
+  //    gives to the 8 wavefronts of one workgroup in the same round (position
+  //    p goes to wavefront p mod W, W wavefronts per launch, and W is a
+  //    multiple of 8).  A longer hub is split into `chunk`-edge items whose
+  //    sums the finalize kernel adds (msplit / hpart);
+  //  * the batched list: each hub is split into `chunk`-edge items whose sums
+  //    the batched finalize kernel adds (hsplit / hpart).
+  const int W = g->grid * kSweepWaves;
+  std::vector<int4> items, bitems, hsplit, msplit, tiles;
+  const int64_t wg_max = (int64_t)kSweepWaves * o.chunk;  // longest list of a workgroup item
   std::vector<int32_t> tidx;
   std::vector<double> tw;
   std::vector<uint8_t> tmask;
   int64_t i = 0, chunks = 0;
-  for (size_t h = 0; h < bins[0].size(); ++h, ++i) {
-    int64_t L = rptr[i + 1] - rptr[i];
-    int64_t nch = (L + o.chunk - 1) / o.chunk;
-    int slot = (int)chunks;
-    hsplit.push_back(make_int4((int)i, slot, (int)nch, 0));
-    chunks += nch;
-    for (int64_t c = 0; c < nch; ++c) items.push_back(make_int4(kHeavy, (int)i, (int)c, slot));
-    P.e_heavy += L;
-  }
-  P.n_heavy_rows = (int64_t)bins[0].size();
-  {
-    const int64_t end = i + (int64_t)bins[1].size();
-    for (int64_t i0 = i; i0 < end; i0 += o.steps)
-      items.push_back(make_int4(kRows, (int)i0, (int)std::min(end, i0 + o.steps), 64));
-    P.n_medium = end - i;
-    P.e_medium = rptr[end] - rptr[i];
-    i = end;
-  }
-  {
-    const int64_t end = i + (int64_t)bins[2].size();
-    P.n_light = end - i;
-    P.e_light = rptr[end] - rptr[i];
-    while (i < end) {
-      const int64_t r0 = i;
-      int64_t edges = 0;
-      while (i < end && i - r0 < o.tile_rows) {
-        const int64_t L = rptr[i + 1] - rptr[i];
-        if (edges + L > kTileEdges) break;
-        edges += L;
-        ++i;
+  P.block_items.assign(1, 0);
+  for (int b = 0; b < B; ++b) {
+    std::vector<int4> rest;  // the block's items other than hubs, in order
+    const auto &hubs = bins[(size_t)b * 4 + 0];
+    const int64_t hub0 = i;
+    std::vector<int4> mega;  // chunk items of the hubs longer than wg_max
+    for (size_t h = 0; h < hubs.size(); ++h, ++i) {
+      int64_t L = rptr[i + 1] - rptr[i];
+      int64_t nch = (L + o.chunk - 1) / o.chunk;
+      int slot = (int)chunks;
+      hsplit.push_back(make_int4((int)i, slot, (int)nch, 0));
+      if (L > wg_max) msplit.push_back(make_int4((int)i, slot, (int)nch, 0));
+      chunks += nch;
+      for (int64_t c = 0; c < nch; ++c) {
+        bitems.push_back(make_int4(kHeavy, (int)i, (int)c, slot));
+        if (L > wg_max) mega.push_back(make_int4(kHeavy, (int)i, (int)c, slot));
       }
-      const int t = (int)tiles.size();
-      tiles.push_back(make_int4((int)r0, (int)(i - r0), (int)edges, 0));
-      items.push_back(make_int4(kTile, t, 0, 0));
-      tidx.resize((size_t)(t + 1) * kTileEdges, 0);
-      if (w) tw.resize((size_t)(t + 1) * kTileEdges, 0.0);
-      tmask.resize((size_t)(t + 1) * 64, 0);
-      int64_t j = 0;
-      for (int64_t r = r0; r < i; ++r) {
-        tmask[(size_t)t * 64 + (j >> 3)] |= (uint8_t)(1u << (j & 7));
-        for (uint32_t e = rptr[r]; e < rptr[r + 1]; ++e, ++j) {
-          const size_t at = (size_t)t * kTileEdges + (size_t)(j & 7) * 64 + (size_t)(j >> 3);
-          tidx[at] = idx[e];
-          if (w) tw[at] = wv[e];
+      P.e_heavy += L;
+    }
+    P.n_heavy_rows += (int64_t)hubs.size();
+    {
+      const int64_t end = i + (int64_t)bins[(size_t)b * 4 + 1].size();
+      for (int64_t i0 = i; i0 < end; i0 += o.steps)
+        rest.push_back(make_int4(kRows, (int)i0, (int)std::min(end, i0 + o.steps), 64));
+      P.n_medium += end - i;
+      P.e_medium += rptr[end] - rptr[i];
+      i = end;
+    }
+    {
+      const int64_t end = i + (int64_t)bins[(size_t)b * 4 + 2].size();
+      P.n_light += end - i;
+      P.e_light += rptr[end] - rptr[i];
+      while (i < end) {
+        const int64_t r0 = i;
+        int64_t edges = 0;
+        while (i < end && i - r0 < o.tile_rows) {
+          const int64_t L = rptr[i + 1] - rptr[i];
+          if (edges + L > kTileEdges) break;
+          edges += L;
+          ++i;
+        }
+        const int t = (int)tiles.size();
+        tiles.push_back(make_int4((int)r0, (int)(i - r0), (int)edges, 0));
+        rest.push_back(make_int4(kTile, t, 0, 0));
+        tidx.resize((size_t)(t + 1) * kTileEdges, 0);
+        if (w) tw.resize((size_t)(t + 1) * kTileEdges, 0.0);
+        tmask.resize((size_t)(t + 1) * 64, 0);
+        int64_t j = 0;
+        for (int64_t r = r0; r < i; ++r) {
+          tmask[(size_t)t * 64 + (j >> 3)] |= (uint8_t)(1u << (j & 7));
+          for (uint32_t e = rptr[r]; e < rptr[r + 1]; ++e, ++j) {
+            const size_t at = (size_t)t * kTileEdges + (size_t)(j & 7) * 64 + (size_t)(j >> 3);
+            tidx[at] = idx[e];
+            if (w) tw[at] = wv[e];
+          }
         }
       }
     }
+    {
+      const int64_t end = i + (int64_t)bins[(size_t)b * 4 + 3].size();
+      for (int64_t i0 = i; i0 < end; i0 += 256)
+        rest.push_back(make_int4(kZero, (int)i0, (int)std::min(end, i0 + 256), 0));
+      P.n_light += end - i;
+      i = end;
+    }
+    bitems.insert(bitems.end(), rest.begin(), rest.end());
+    // the sweep list of this block: hub groups at positions that are
+    // multiples of 8 (any launch assigns position p to wavefront p mod W, and
+    // W is a multiple of 8, so a group lands on the 8 wavefronts of one
+    // workgroup in one round), after at most 7 no-op items
+    std::vector<int4> blkitems;
+    if (!hubs.empty())
+      while ((items.size() + blkitems.size()) % kSweepWaves) blkitems.push_back(make_int4(kZero, 0, 0, 0));
+    for (size_t h = 0; h < hubs.size(); ++h) {
+      const int64_t r = hub0 + (int64_t)h;
+      if (rptr[r + 1] - rptr[r] <= wg_max)
+        for (int k = 0; k < kSweepWaves; ++k) blkitems.push_back(make_int4(kHubWG, (int)r, 0, 0));
+    }
+    blkitems.insert(blkitems.end(), mega.begin(), mega.end());
+    blkitems.insert(blkitems.end(), rest.begin(), rest.end());
+    items.insert(items.end(), blkitems.begin(), blkitems.end());
+    P.block_items.push_back((int)items.size());
   }
-  {
-    const int64_t end = i + (int64_t)bins[3].size();
-    for (int64_t i0 = i; i0 < end; i0 += 256)
-      items.push_back(make_int4(kZero, (int)i0, (int)std::min(end, i0 + 256), 0));
-    P.n_light += end - i;
-    i = end;
-  }
+  P.n_blocks = B;
+  for (int b = 0; b + 1 < B; ++b)  // the last block's launch holds the hubs
+    if (!bins[(size_t)b * 4].empty()) return pr_fail(PR_EDEVICE, "pr_graph_create: hub outside the last block");
   P.n_items = (int)items.size();
+  P.n_bitems = (int)bitems.size();
   P.n_tiles = (int)tiles.size();
-  P.n_heavy = (int)bins[0].size();
+  P.n_heavy = (int)P.n_heavy_rows;
   P.n_split = (int)hsplit.size();
+  P.n_msplit = (int)msplit.size();
   P.n_chunks = (int)chunks;
 
   // host-side check of what the kernels assume
-  for (const int4 &it : items) {
-    bool ok = false;
+  auto check = [&](const int4 &it) {
     if (it.x == kHeavy)
-      ok = it.y >= 0 && it.y < n && it.w >= 0 && it.w + it.z < chunks &&
-           (int64_t)it.z * o.chunk < (int64_t)(rptr[it.y + 1] - rptr[it.y]);
-    else if (it.x == kRows || it.x == kZero)
-      ok = it.y >= 0 && it.y < it.z && it.z <= n;
-    else if (it.x == kTile) {
+      return it.y >= 0 && it.y < n && it.w >= 0 && it.w + it.z < chunks &&
+             (int64_t)it.z * o.chunk < (int64_t)(rptr[it.y + 1] - rptr[it.y]);
+    if (it.x == kHubWG)
+      return it.y >= 0 && it.y < n && (int64_t)(rptr[it.y + 1] - rptr[it.y]) > o.chunk &&
+             (int64_t)(rptr[it.y + 1] - rptr[it.y]) <= wg_max;
+    if (it.x == kRows) return it.y >= 0 && it.y < it.z && it.z <= n;
+    if (it.x == kZero) return it.y >= 0 && it.y <= it.z && it.z <= n;
+    if (it.x == kTile) {
       const int4 d = tiles[it.y];
-      ok = d.x >= 0 && d.y >= 1 && d.y <= kTileRows && d.x + d.y <= n && d.z >= d.y && d.z <= kTileEdges &&
-           (int64_t)(rptr[d.x + d.y] - rptr[d.x]) == d.z;
+      return d.x >= 0 && d.y >= 1 && d.y <= kTileRows && d.x + d.y <= n && d.z >= d.y && d.z <= kTileEdges &&
+             (int64_t)(rptr[d.x + d.y] - rptr[d.x]) == d.z;
     }
-    if (!ok) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
-  }
+    return false;
+  };
+  for (const int4 &it : items)
+    if (!check(it)) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
+  for (const int4 &it : bitems)
+    if (it.x == kHubWG || !check(it)) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
+  // a hub item fills positions 8q..8q+7 (the 8 wavefronts of one workgroup,
+  // one round): every wavefront of that workgroup meets its barrier
+  if (W % kSweepWaves) return pr_fail(PR_EDEVICE, "pr_graph_create: wavefront count not a multiple of 8");
+  for (size_t p = 0; p < items.size(); ++p)
+    if (items[p].x == kHubWG) {
+      const size_t first = p - p % kSweepWaves;
+      if (first + kSweepWaves > items.size())
+        return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (hub item)");
+      for (int k = 0; k < kSweepWaves; ++k)
+        if (items[first + k].x != kHubWG || items[first + k].y != items[p].y)
+          return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (hub item)");
+    }
 
   int64_t before = g->device_bytes;
   int rc;
@@ -204,14 +302,17 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   if ((rc = upload(g, &P.idx, idx.data(), idx.size()))) return rc;
   if (w && (rc = upload(g, &P.w, wv.data(), wv.size()))) return rc;
   if ((rc = upload(g, &P.items, items.data(), items.size()))) return rc;
+  if ((rc = upload(g, &P.bitems, bitems.data(), bitems.size()))) return rc;
   if ((rc = upload(g, &P.hsplit, hsplit.data(), hsplit.size()))) return rc;
+  if ((rc = upload(g, &P.msplit, msplit.data(), msplit.size()))) return rc;
   if ((rc = upload(g, &P.tiles, tiles.data(), tiles.size()))) return rc;
   if ((rc = upload(g, &P.tidx, tidx.data(), tidx.size()))) return rc;
   if (w && (rc = upload(g, &P.tw, tw.data(), tw.size()))) return rc;
   if ((rc = upload(g, &P.tmask, tmask.data(), tmask.size()))) return rc;
   if ((rc = fpr_dev_alloc(g, (void **)&P.hpart, sizeof(double) * (chunks > 0 ? chunks : 1)))) return rc;
-  P.n_waves = g->grid * kSweepWaves;
-  if ((rc = fpr_dev_alloc(g, (void **)&P.wave_part, sizeof(double) * 3 * (size_t)P.n_waves))) return rc;
+  P.n_waves = W;
+  P.part_stride = B * g->grid;  // one partial per sweep workgroup and block
+  if ((rc = fpr_dev_alloc(g, (void **)&P.wave_part, sizeof(double) * 3 * (size_t)P.part_stride))) return rc;
   if ((rc = fpr_dev_alloc(g, (void **)&P.st, sizeof(SweepState)))) return rc;
   PR_HIP(hipMemset(P.st, 0, sizeof(SweepState)));
   P.bytes = g->device_bytes - before;
@@ -252,10 +353,11 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
   pr_plan_opts_default(&o);
   if (opts) o = *opts;
   if (o.chunk < 64 || o.chunk > (1 << 20) || o.tile_max_row < 0 || o.tile_max_row > kTileEdges ||
-      o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 || o.steps > 64)
+      o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 || o.steps > 64 || o.gs_blocks < 1 ||
+      o.gs_blocks > 64)
     return pr_fail(PR_EINVAL,
                    "pr_graph_create: need 64 <= chunk <= 2^20, 0 <= tile_max_row <= 512, "
-                   "1 <= tile_rows <= 128, 1 <= steps <= 64");
+                   "1 <= tile_rows <= 128, 1 <= steps <= 64, 1 <= gs_blocks <= 64");
   o.tile_max_row = std::min(o.tile_max_row, o.chunk);
   int dev_count = 0;
   hipError_t he = hipGetDeviceCount(&dev_count);

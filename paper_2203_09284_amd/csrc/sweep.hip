@@ -3,29 +3,31 @@
 //
 //  * Jacobi (Section 3, Algorithm 1): contributions are double-buffered; sweep
 //    k reads c_k and writes c_{k+1}, so every vertex sees the previous sweep.
-//  * Fused (Section 4, Algorithm 2; Eq. 9): one contribution array, updated in
-//    place right after each vertex's rank; work items run one per workgroup
-//    in dispatch order, so items that start later read the contributions
-//    written by items that finished earlier in the same sweep (the paper's
-//    parallel variant, Section 6.3, an asynchronous Gauss-Seidel iteration).
-//    Reads and writes of the shared array are relaxed atomics: a reader gets
-//    either the old or the new value, never a torn one.
+//  * Fused (Section 4, Algorithm 2; Eq. 9): Gauss-Seidel over blocks of
+//    vertices.  The plan cuts the vertices into blocks (hubs and high
+//    out-degree first) whose gather slots are contiguous; the sweep launches
+//    the kernel once per block, and a gather of a slot that belongs to an
+//    earlier block reads the contribution written in this sweep, every other
+//    gather the previous sweep's.  Kernel boundaries are the only points where
+//    all of a launch's writes are visible to every XCD, so the blocks, not
+//    individual vertices, are the Gauss-Seidel units; within a block the sweep
+//    is Jacobi, which keeps it deterministic.
 //
 // Per vertex u the update is Eq. 1 with the dangling mass D spread uniformly,
 //     x_u <- (1-d) p_u s + d (sum_{v->u} w c_v + D/n),   c_u <- x_u / W_u,
 // where s = 1, except in the fused mass-scaled mode where s is the previous
 // sweep's total mass (see the mode flag kFlagScaled).  The per-vertex change,
-// the new dangling mass and the new total mass are reduced in FP64 per work
-// item; a one-workgroup finalize kernel after each sweep sums the item
-// partials in a fixed order (deterministic), completes rows that were split
-// across workgroups, and sets the residual, the iteration count and the stop
-// flag, so the next sweep needs no host work.  The hot kernel has no fences
-// and no atomics besides the relaxed loads/stores of the fused form.
+// the new dangling mass and the new total mass are reduced in FP64 per
+// workgroup; a one-workgroup finalize kernel after each sweep sums the
+// workgroup partials in a fixed order (deterministic) and sets the residual,
+// the iteration count and the stop flag, so the next sweep needs no host
+// work.  The hot kernel has no fences
+// and no atomics.
 //
 // Work layout: a few workgroups per CU; each keeps the hottest slots of the
 // gathered array in LDS and its wavefronts take work items round-robin; an
-// item is a tile of short rows, a few long rows (a wavefront each), one chunk
-// of a hub's list, or a run of vertices without in-edges.
+// item is a tile of short rows, a long row (a wavefront), a hub (all
+// wavefronts of a workgroup), or a run of vertices without in-edges.
 //
 // FP32 storage (ranks and contributions) sums with Neumaier compensation per
 // lane and TwoSum when lanes combine; the rank update and every reduction are
@@ -42,29 +44,7 @@
 using namespace fpr;
 using namespace fpr::dev;
 
-// Memory scope of the relaxed atomic loads/stores of the shared contribution
-// array in the fused form.  Workgroup scope compiles to ordinary cached
-// loads/stores (no tearing for naturally aligned 4/8-byte values); a reader
-// in another workgroup may then see a value up to one sweep old, since kernel
-// boundaries make every write visible.  Agent scope (-DFPR_FUSED_SCOPE=
-// __HIP_MEMORY_SCOPE_AGENT) forces device-coherent accesses instead.
-#ifndef FPR_FUSED_SCOPE
-#define FPR_FUSED_SCOPE __HIP_MEMORY_SCOPE_WORKGROUP
-#endif
-
 namespace {
-
-template <bool FUSED, typename T>
-__device__ __forceinline__ T ld_c(const T *p) {
-  if constexpr (FUSED) return __hip_atomic_load(p, __ATOMIC_RELAXED, FPR_FUSED_SCOPE);
-  else return *p;
-}
-
-template <bool FUSED, typename T>
-__device__ __forceinline__ void st_c(T *p, T v) {
-  if constexpr (FUSED) __hip_atomic_store(p, v, __ATOMIC_RELAXED, FPR_FUSED_SCOPE);
-  else *p = v;
-}
 
 // ------------------------------------------------------------ arguments --
 
@@ -80,11 +60,11 @@ struct SweepArgs {
   const double *w;
   const int4 *items;
   const int4 *tiles;
+  const int4 *msplit;  // hubs split into chunk items: {row index, first slot, chunks, 0}
+  double *hpart;       // chunk sums
   const int32_t *tidx;
   const double *tw;
   const uint8_t *tmask;
-  const int4 *hsplit;
-  double *hpart;
   double *wave_part;
   SweepState *st;
   const double *inv_w;
@@ -96,11 +76,18 @@ struct SweepArgs {
   double d;
   double inv_n;
   int n_items;
-  int n_split;
-  int n_waves;
+  int n_msplit;
   int chunk;
+  int n_waves;
   int hot;  // gather slots staged in LDS (<= kHotSlots<T>)
   int flags;
+  // launch-specific: the work items [item_lo, item_hi) of this launch, where
+  // its wavefront partials go, and what the finalize kernel sums
+  int item_lo, item_hi;
+  int part_base;    // first partial slot written by this launch
+  int part_stride;  // SoA stride of the three partial rows
+  int n_part;       // partial slots the finalize kernel sums
+  int fresh_lo, fresh_hi;  // slots rewritten by earlier blocks of this sweep (fused form)
 };
 
 template <typename T>
@@ -113,13 +100,15 @@ struct Ctx {
   const double *inv_w;
   const double *p;
   T *x;
-  const T *cin;
-  T *cout;
+  const T *cin;  // contributions of the previous sweep
+  T *cout;       // contributions of this sweep
   double tele;   // (1-d) * mass scale
   double d;
   double dterm;  // D / n, 0 in leak mode
   double inv_n;
   int hot;
+  int fresh_lo;  // gather slots [fresh_lo, fresh_lo + fresh_n) are read from cout
+  int fresh_n;   // (earlier Gauss-Seidel blocks of this sweep)
   int flags;
 };
 
@@ -138,13 +127,10 @@ __device__ __forceinline__ Ctx<T> make_ctx(const SweepArgs<T> &a, const SweepSta
   C.inv_w = a.inv_w;
   C.p = a.p;
   C.x = a.x;
-  if (FUSED) {
-    C.cin = a.c0;
-    C.cout = a.c0;
-  } else {
-    C.cin = (it & 1) ? a.c1 : a.c0;
-    C.cout = (it & 1) ? a.c0 : a.c1;
-  }
+  C.cin = (it & 1) ? a.c1 : a.c0;
+  C.cout = (it & 1) ? a.c0 : a.c1;
+  C.fresh_lo = a.fresh_lo;
+  C.fresh_n = FUSED ? a.fresh_hi - a.fresh_lo : 0;
   C.d = a.d;
   C.inv_n = a.inv_n;
   C.hot = a.hot;
@@ -173,9 +159,7 @@ __device__ __forceinline__ void update_vertex(const Ctx<T> &C, T *hot, int i, do
 
 // The update of vertex u from its pulled sum s, with its operands loaded:
 // old value xo, 1/W_u (iw), teleport (or adjoint right-hand side) pu, and the
-// slot of u in the gather layout.  In the fused form the workgroup's LDS copy
-// of a hot slot is refreshed as well, so later wavefronts of the workgroup
-// read the new value.
+// slot of u in the gather layout.
 //   forward: x' = (1-d) p_u s + d (sum + D/n),  gathered value x' / W_u
 //   adjoint: x' = g_u + d (sum / W_u + [W_u = 0] S/n),  gathered value x'
 template <typename T, bool FUSED>
@@ -188,14 +172,19 @@ __device__ __forceinline__ void update_loaded(const Ctx<T> &C, T *hot, uint32_t 
   C.x[u] = xs;
   const double xd = (double)xs;
   if (adj || iw != 0.0) {
-    const T cv = adj ? xs : (T)(xd * iw);
-    st_c<FUSED>(C.cout + slot, cv);
-    if (FUSED && hot != nullptr && slot < (uint32_t)C.hot) hot[slot] = cv;
+    C.cout[slot] = adj ? xs : (T)(xd * iw);
   }
   if (iw == 0.0) red.dang += xd;
   const double dl = fabs(xd - xo);
   red.chg = (C.flags & kFlagLinf) ? fmax(red.chg, dl) : red.chg + dl;
   red.tot += xd;
+}
+
+// The array slot s is read from: this sweep's contributions for slots of
+// earlier Gauss-Seidel blocks (fused form), the previous sweep's otherwise.
+template <typename T, bool FUSED>
+__device__ __forceinline__ const T *src_of(const Ctx<T> &C, int32_t s) {
+  return FUSED && (uint32_t)(s - C.fresh_lo) < (uint32_t)C.fresh_n ? C.cout : C.cin;
 }
 
 // Gather of slot s (always a valid slot).  Both the LDS copy and the global
@@ -212,10 +201,10 @@ __device__ __forceinline__ T gather(const Ctx<T> &C, const T *hot, int32_t s) {
 #if FPR_GATHER_MASKED
   // global load only on the lanes whose slot is not in LDS
   T vg = vh;
-  if (!h) vg = ld_c<FUSED>(C.cin + s);
+  if (!h) vg = src_of<T, FUSED>(C, s)[s];
   return vg;
 #else
-  const T vg = ld_c<FUSED>(C.cin + (h ? 0 : s));
+  const T vg = src_of<T, FUSED>(C, s)[h ? 0 : s];
   return h ? vh : vg;
 #endif
 }
@@ -397,10 +386,11 @@ __device__ __forceinline__ void zero_rows(const Ctx<T> &C, T *hot, int i0, int i
   for (int r = i0 + lane; r < i1; r += 64) update_vertex<T, FUSED>(C, hot, r, 0.0, red);
 }
 
-// One chunk of a hub's list per wavefront; the chunk sum goes to its slot.
+// One `chunk`-edge piece of a very long hub list per wavefront; the piece sum
+// goes to its slot and the finalize kernel adds the pieces in order.
 template <typename T, bool FUSED, bool WEIGHTED>
-__device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double *hpart, int chunk,
-                                          int i, int c, int slot) {
+__device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double *hpart, int chunk, int i, int c,
+                                          int slot) {
   const int lane = threadIdx.x & 63;
   const uint32_t rb = C.rptr[i];
   const int L = (int)(C.rptr[i + 1] - rb);
@@ -430,70 +420,159 @@ __device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double 
   if (lane == 0) hpart[slot + c] = acc.value();
 }
 
-// Wavefront reduction of a Red; lane 0 writes the wavefront's partials (SoA).
-__device__ __forceinline__ void store_wave_partial(Red &red, double *part, int n_waves, int gw,
-                                                   bool linf) {
-  const double chg = linf ? wave_max(red.chg) : wave_sum(red.chg);
-  const double dang = wave_sum(red.dang);
-  const double tot = wave_sum(red.tot);
-  if ((threadIdx.x & 63) == 0) {
-    part[gw] = chg;
-    part[(size_t)n_waves + gw] = dang;
-    part[2 * (size_t)n_waves + gw] = tot;
+// A hub (list longer than the plan's chunk, at most 8 chunks) is an item of a
+// whole workgroup:
+// the plan gives it to all 8 wavefronts of one workgroup in the same round.
+// Wavefront k sums the 512-edge pieces k, k+8, k+16, ... of the list; the 8
+// sums meet in LDS and wavefront 0 adds them in wavefront order and updates
+// the row.  `par` alternates the LDS buffer between consecutive hub items.
+template <typename T, bool FUSED, bool WEIGHTED>
+__device__ __forceinline__ void hub_wg(const Ctx<T> &C, const T *hot, double (*s_hub)[kSweepWaves], int &par,
+                                       int i, Red &red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t rb = C.rptr[i];
+  const int L = (int)(C.rptr[i + 1] - rb);
+  uint32_t u = 0, slot = 0;
+  double xo = 0.0, iw = 0.0, pu = C.inv_n;
+  if (wave == 0 && lane == 0) {
+    u = C.rows[i];
+    slot = C.rowpos[i];
+    xo = (double)C.x[u];
+    iw = C.inv_w[u];
+    if (!(C.flags & kFlagUniformP)) pu = C.p[u];
   }
+  LaneSum<T> acc;
+  for (int j0 = wave * (kBatch * 64) + lane; j0 < L; j0 += kSweepWaves * kBatch * 64) {
+    int32_t sl[kBatch];
+    double wt[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int j = j0 + 64 * k;
+      sl[k] = j < L ? C.idx[rb + j] : 0;
+      if constexpr (WEIGHTED) wt[k] = j < L ? C.w[rb + j] : 0.0;
+    }
+    T v[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, sl[k]);
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      T x = j0 + 64 * k < L ? v[k] : (T)0;
+      if constexpr (WEIGHTED) x = (T)((double)x * wt[k]);
+      acc.add(x);
+    }
+  }
+  acc.group_reduce(64);
+  if (lane == 0) s_hub[par][wave] = acc.value();
+  __syncthreads();
+  if (wave == 0 && lane == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < kSweepWaves; ++k) tot += s_hub[par][k];
+    update_loaded<T, FUSED>(C, nullptr, u, slot, xo, iw, pu, tot, red);
+  }
+  par ^= 1;
 }
 
-// One workgroup per CU.  The workgroup first copies the hottest gather slots
-// (the first `hot` of the gather layout) into LDS, then each wavefront takes
-// work items gw, gw + W, gw + 2W, ... (W wavefronts in the launch), so the
-// items run roughly in order: hubs first, then rows by decreasing length.
-// Every wavefront accumulates its rows' change / dangling / total mass and
-// writes one partial; a fixed item-to-wavefront map keeps the sums
-// reproducible.
+// A few workgroups per CU.  The workgroup first copies the hottest gather
+// slots (the first `hot` of the gather layout) into LDS, then each wavefront
+// takes the work items at positions congruent to its index modulo W (W
+// wavefronts in the launch), so the items run roughly in order: hubs first,
+// then rows by decreasing length.
+// Every wavefront accumulates its rows' change / dangling / total mass; the
+// workgroup writes one partial of each; a fixed item-to-wavefront map keeps
+// the sums reproducible.
 #ifndef FPR_WAVES_PER_EU
 #define FPR_WAVES_PER_EU 6
 #endif
 
+// Copy of the hot slots [0, C.hot) into LDS with 16-byte loads, all issued
+// before the first LDS write (one memory latency per launch, not one per
+// slot).  A 16-byte group that straddles the fresh range falls back to one
+// load per slot.
+template <typename T, bool FUSED>
+__device__ __forceinline__ void load_hot(const Ctx<T> &C, T *hot) {
+  constexpr int V = 16 / (int)sizeof(T);
+  constexpr int kPer = (kHotSlots<T> / V + kSweepBlock - 1) / kSweepBlock;
+  const int nvec = C.hot / V;
+  uint4 buf[kPer];
+  bool mixed[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int q = (int)threadIdx.x + k * kSweepBlock;
+    mixed[k] = false;
+    buf[k] = make_uint4(0, 0, 0, 0);
+    if (q < nvec) {
+      const int s0 = q * V;
+      const T *src = src_of<T, FUSED>(C, s0);
+      mixed[k] = FUSED && src_of<T, FUSED>(C, s0 + V - 1) != src;
+      buf[k] = *reinterpret_cast<const uint4 *>(src + s0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int q = (int)threadIdx.x + k * kSweepBlock;
+    if (q < nvec) {
+      *reinterpret_cast<uint4 *>(hot + q * V) = buf[k];
+      if (mixed[k])
+        for (int j = 0; j < V; ++j) hot[q * V + j] = src_of<T, FUSED>(C, q * V + j)[q * V + j];
+    }
+  }
+  for (int s = nvec * V + (int)threadIdx.x; s < C.hot; s += kSweepBlock) hot[s] = src_of<T, FUSED>(C, s)[s];
+}
+
 template <typename T, bool FUSED, bool WEIGHTED>
 __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(FPR_WAVES_PER_EU)))
 void k_sweep(SweepArgs<T> a) {
-  __shared__ T hot[kHotSlots<T>];
+  __shared__ __align__(16) T hot[kHotSlots<T>];
   __shared__ double rowsum_all[kSweepWaves][kTileRows];
+  __shared__ double s_part[3][kSweepWaves];
+  __shared__ double s_hub[2][kSweepWaves];
   const SweepState *st = a.st;
   if (st->done) return;
   const Ctx<T> C = make_ctx<T, FUSED>(a, st);
-  for (int s = threadIdx.x; s < C.hot; s += kSweepBlock) hot[s] = ld_c<FUSED>(C.cin + s);
+  load_hot<T, FUSED>(C, hot);
   __syncthreads();
-  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kSweepWaves + (threadIdx.x >> 6)));
+  const int wave = threadIdx.x >> 6;
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kSweepWaves + wave));
   Red red;
-  double *rowsum = rowsum_all[threadIdx.x >> 6];
-  for (int item = gw; item < a.n_items; item += a.n_waves) {
+  int par = 0;
+  double *rowsum = rowsum_all[wave];
+  // position p goes to wavefront p mod W in every launch (the plan places
+  // each hub's 8 items on one workgroup that way)
+  int first = gw - a.item_lo % a.n_waves;
+  if (first < 0) first += a.n_waves;
+  for (int item = a.item_lo + first; item < a.item_hi; item += a.n_waves) {
     const int4 wi = a.items[item];
     if (wi.x == kTile) tile_rows<T, FUSED, WEIGHTED>(C, a, hot, rowsum, wi.y, red);
     else if (wi.x == kRows) row_group<T, FUSED, WEIGHTED>(C, hot, wi.y, wi.z, wi.w, red);
+    else if (wi.x == kHubWG) hub_wg<T, FUSED, WEIGHTED>(C, hot, s_hub, par, wi.y, red);
     else if (wi.x == kHeavy) hub_chunk<T, FUSED, WEIGHTED>(C, hot, a.hpart, a.chunk, wi.y, wi.z, wi.w);
     else zero_rows<T, FUSED>(C, hot, wi.y, wi.z, red);
   }
-  store_wave_partial(red, a.wave_part, a.n_waves, gw, (a.flags & kFlagLinf) != 0);
+  // one partial per workgroup: wavefront sums, then the waves in order
+  const bool linf = (a.flags & kFlagLinf) != 0;
+  const double chg = linf ? wave_max(red.chg) : wave_sum(red.chg);
+  const double dang = wave_sum(red.dang);
+  const double tot = wave_sum(red.tot);
+  if ((threadIdx.x & 63) == 0) {
+    s_part[0][wave] = chg;
+    s_part[1][wave] = dang;
+    s_part[2][wave] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int r = threadIdx.x;
+    double v = s_part[r][0];
+    for (int k = 1; k < kSweepWaves; ++k) v = (r == 0 && linf) ? fmax(v, s_part[r][k]) : v + s_part[r][k];
+    a.wave_part[(size_t)r * a.part_stride + a.part_base + blockIdx.x] = v;
+  }
 }
 
-constexpr int kFinBlock = 1024;
-
-// Completes the sweep in one workgroup: updates the hubs from their chunk sums
-// (in chunk order), sums the wavefront partials in a fixed order, and
-// publishes residual, dangling mass, total mass, iteration count and the stop
-// flag.
+// The hubs split into chunk items: each adds its chunk sums in chunk order and
+// is updated (one thread per hub, chunk loads batched).
 template <typename T, bool FUSED>
-__global__ __launch_bounds__(kFinBlock) void k_finalize(SweepArgs<T> a) {
-  __shared__ double s_red[3][kFinBlock / 64];
-  SweepState *st = a.st;
-  if (st->done) return;
-  const Ctx<T> C = make_ctx<T, FUSED>(a, st);
-  const double S_old = st->S;
-  const bool linf = (a.flags & kFlagLinf) != 0;
-  Red red;
-  for (int h = threadIdx.x; h < a.n_split; h += kFinBlock) {
-    const int4 hs = a.hsplit[h];
+__device__ __forceinline__ void finish_split_hubs(const Ctx<T> &C, const SweepArgs<T> &a, Red &red) {
+  for (int h = threadIdx.x; h < a.n_msplit; h += kFinBlock) {
+    const int4 hs = a.msplit[h];
     const uint32_t u = C.rows[hs.x];
     const uint32_t slot = C.rowpos[hs.x];
     const double xo = (double)C.x[u];
@@ -509,12 +588,39 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(SweepArgs<T> a) {
     }
     update_loaded<T, FUSED>(C, nullptr, u, slot, xo, iw, pu, tot, red);
   }
-  const int n = a.n_waves;
-  for (int i = threadIdx.x; i < n; i += kFinBlock) {
-    const double c0 = a.wave_part[i];
-    red.chg = linf ? fmax(red.chg, c0) : red.chg + c0;
-    red.dang += a.wave_part[(size_t)n + i];
-    red.tot += a.wave_part[2 * (size_t)n + i];
+}
+
+// Completes the sweep in one workgroup: updates the split hubs, sums the
+// workgroup partials in a fixed order and publishes residual, dangling mass, total mass, iteration
+// count and the stop flag.
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(kFinBlock) void k_finalize(SweepArgs<T> a) {
+  __shared__ double s_red[3][kFinBlock / 64];
+  SweepState *st = a.st;
+  if (st->done) return;
+  const Ctx<T> C = make_ctx<T, FUSED>(a, st);
+  const double S_old = st->S;
+  const bool linf = (a.flags & kFlagLinf) != 0;
+  Red red;
+  finish_split_hubs<T, FUSED>(C, a, red);
+  const int n = a.n_part;
+  const size_t ps = (size_t)a.part_stride;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kFinBlock) {
+    double c[8], dg[8], tt[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k * kFinBlock;
+      const bool ok = i < n;
+      c[k] = ok ? a.wave_part[i] : 0.0;
+      dg[k] = ok ? a.wave_part[ps + i] : 0.0;
+      tt[k] = ok ? a.wave_part[2 * ps + i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      red.chg = linf ? fmax(red.chg, c[k]) : red.chg + c[k];
+      red.dang += dg[k];
+      red.tot += tt[k];
+    }
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double chg = linf ? wave_max(red.chg) : wave_sum(red.chg);
@@ -710,11 +816,13 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   a.w = P.w;
   a.items = P.items;
   a.tiles = P.tiles;
+  a.msplit = P.msplit;
+  a.hpart = P.hpart;
+  a.n_msplit = P.n_msplit;
+  a.chunk = P.chunk;
   a.tidx = P.tidx;
   a.tw = P.tw;
   a.tmask = P.tmask;
-  a.hsplit = P.hsplit;
-  a.hpart = P.hpart;
   a.wave_part = P.wave_part;
   a.st = P.st;
   a.inv_w = g->inv_w;
@@ -726,37 +834,67 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
   a.n_items = P.n_items;
-  a.n_split = P.n_split;
   a.n_waves = P.n_waves;
-  a.chunk = P.chunk;
   {
     int64_t hot = g->popts.hot_slots < 0 ? kHotSlots<T> : std::min<int64_t>(g->popts.hot_slots, kHotSlots<T>);
     a.hot = (int)std::min<int64_t>(hot, g->n);
   }
   a.flags = flags | (p ? 0 : kFlagUniformP);
+  a.item_lo = 0;
+  a.item_hi = P.n_items;
+  a.part_base = 0;
+  a.part_stride = P.part_stride;
+  a.n_part = P.n_waves / kSweepWaves;
+  a.fresh_lo = 0;
+  a.fresh_hi = 0;
   return a;
 }
 
+// One sweep: the sweep kernel, then the finalize kernel.  The fused form with
+// several Gauss-Seidel blocks launches the sweep kernel once per block, so
+// each block reads what the blocks before it wrote in this sweep.  `mark`,
+// when given, is recorded right before the finalize kernel.
 template <typename T, bool FUSED, bool WEIGHTED>
-void launch_one(const SweepArgs<T> &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep<T, FUSED, WEIGHTED>), dim3(a.n_waves / kSweepWaves), dim3(kSweepBlock), 0,
-                     s, a);
+void launch_one(const DevPlan &P, const SweepArgs<T> &a0, hipStream_t s, hipEvent_t mark) {
+  const dim3 grid(a0.n_waves / kSweepWaves), block(kSweepBlock);
+  if (!FUSED || P.n_blocks <= 1) {
+    hipLaunchKernelGGL((k_sweep<T, FUSED, WEIGHTED>), grid, block, 0, s, a0);
+    if (mark) (void)hipEventRecord(mark, s);
+    hipLaunchKernelGGL((k_finalize<T, FUSED>), dim3(1), dim3(kFinBlock), 0, s, a0);
+    return;
+  }
+  const int B = P.n_blocks;
+  SweepArgs<T> a = a0;
+  a.fresh_lo = P.block_slots[0];
+  for (int b = 0; b < B; ++b) {
+    a.item_lo = P.block_items[b];
+    a.item_hi = P.block_items[b + 1];
+    a.part_base = b * (P.n_waves / kSweepWaves);
+    a.fresh_hi = P.block_slots[b];
+    hipLaunchKernelGGL((k_sweep<T, FUSED, WEIGHTED>), grid, block, 0, s, a);
+  }
+  if (mark) (void)hipEventRecord(mark, s);
+  a.n_part = B * (P.n_waves / kSweepWaves);
   hipLaunchKernelGGL((k_finalize<T, FUSED>), dim3(1), dim3(kFinBlock), 0, s, a);
+}
+
+template <typename T>
+void launch_marked(pr_graph *g, const SweepArgs<T> &a, bool fused, bool weighted, hipStream_t s,
+                   hipEvent_t mark) {
+  const DevPlan &P = g->fwd;  // the fused form runs on the forward plan only
+  if (fused) {
+    if (weighted) launch_one<T, true, true>(P, a, s, mark);
+    else launch_one<T, true, false>(P, a, s, mark);
+  } else {
+    if (weighted) launch_one<T, false, true>(P, a, s, mark);
+    else launch_one<T, false, false>(P, a, s, mark);
+  }
 }
 
 template <typename T>
 void launch_sweeps(pr_graph *g, const SweepArgs<T> &a, bool fused, bool weighted, int count,
                    hipStream_t s) {
-  (void)g;
-  for (int k = 0; k < count; ++k) {
-    if (fused) {
-      if (weighted) launch_one<T, true, true>(a, s);
-      else launch_one<T, true, false>(a, s);
-    } else {
-      if (weighted) launch_one<T, false, true>(a, s);
-      else launch_one<T, false, false>(a, s);
-    }
-  }
+  for (int k = 0; k < count; ++k) launch_marked<T>(g, a, fused, weighted, s, nullptr);
 }
 
 // Cached hipGraph executables of `count` sweeps for one exact argument set.
@@ -985,35 +1123,36 @@ extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const p
   return (r < target) ? PR_OK : PR_NOT_CONVERGED;
 }
 
-extern "C" int pr_iterate(pr_graph *g, double d, const pr_opts *opts, const double *p, double *x,
-                          int sweeps, double *resid, double *elapsed_ms, void *stream) {
-  pr_clear_error();
-  pr_opts o;
-  pr_opts_default(&o);
-  if (opts) o = *opts;
-  o.precision = PR_FP64;
-  int rc = validate_common(g, d, o);
-  if (rc) return rc;
-  if (!x) return pr_fail(PR_EINVAL, "x is NULL");
-  if (sweeps < 0) return pr_fail(PR_EINVAL, "sweeps=%d must be >= 0", sweeps);
-  StreamJoin join(g, stream);
-  if ((rc = ensure_contrib<double>(g))) return rc;
+namespace {
+
+// `sweeps` sweeps of precision T from the FP64 vector x (read, cast, written back).
+template <typename T>
+int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, double *x, int sweeps,
+                 double *resid, double *elapsed_ms) {
+  int rc;
+  T *xs = nullptr;
+  if constexpr (sizeof(T) == 8) {
+    xs = x;
+  } else {
+    if (!g->x32 && (rc = fpr_dev_alloc(g, (void **)&g->x32, sizeof(float) * (size_t)g->n))) return rc;
+    xs = g->x32;
+  }
+  if ((rc = ensure_contrib<T>(g))) return rc;
   DevPlan &P = g->fwd;
-  if ((rc = launch_init<double>(g, P, p, x, x, -1.0, std::max(1, sweeps)))) return rc;
+  if ((rc = launch_init<T>(g, P, p, x, xs, -1.0, std::max(1, sweeps)))) return rc;
   const int flags = flags_of(o);
-  SweepArgs<double> a = make_args<double>(g, P, p, x, d, flags, nullptr);
+  SweepArgs<T> a = make_args<T>(g, P, p, xs, d, flags, nullptr);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (elapsed_ms) {
     PR_HIP(hipEventCreate(&e0));
     PR_HIP(hipEventCreate(&e1));
     PR_HIP(hipEventRecord(e0, g->work));
   }
-  if (sweeps > 0 && (rc = run_sweeps<double>(g, a, o.mode == PR_FUSED, o.use_hip_graph != 0, sweeps)))
-    return rc;
+  if (sweeps > 0 && (rc = run_sweeps<T>(g, a, o.mode == PR_FUSED, o.use_hip_graph != 0, sweeps))) return rc;
   if (elapsed_ms) PR_HIP(hipEventRecord(e1, g->work));
-  if (flags & kFlagScaled)
-    hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const double *)x, x,
-                       g->n, (const SweepState *)P.st, 1);
+  if (sizeof(T) != 8 || (flags & kFlagScaled))
+    hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const T *)xs, x, g->n,
+                       (const SweepState *)P.st, (flags & kFlagScaled) ? 1 : 0);
   PR_HIP(hipGetLastError());
   if ((rc = poll_state(g, P))) return rc;
   if (resid) *resid = sweeps > 0 ? g->host_st->resid : INFINITY;
@@ -1025,6 +1164,83 @@ extern "C" int pr_iterate(pr_graph *g, double d, const pr_opts *opts, const doub
     (void)hipEventDestroy(e1);
   }
   return PR_OK;
+}
+
+}  // namespace
+
+extern "C" int pr_iterate(pr_graph *g, double d, const pr_opts *opts, const double *p, double *x,
+                          int sweeps, double *resid, double *elapsed_ms, void *stream) {
+  pr_clear_error();
+  pr_opts o;
+  pr_opts_default(&o);
+  if (opts) o = *opts;
+  int rc = validate_common(g, d, o);
+  if (rc) return rc;
+  if (!x) return pr_fail(PR_EINVAL, "x is NULL");
+  if (sweeps < 0) return pr_fail(PR_EINVAL, "sweeps=%d must be >= 0", sweeps);
+  StreamJoin join(g, stream);
+  if (o.precision == PR_FP32) return iterate_impl<float>(g, d, o, p, x, sweeps, resid, elapsed_ms);
+  return iterate_impl<double>(g, d, o, p, x, sweeps, resid, elapsed_ms);
+}
+
+namespace {
+
+template <typename T>
+int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps, double *sweep_ms,
+                 double *finalize_ms) {
+  int rc;
+  T *xs = nullptr;
+  if constexpr (sizeof(T) == 8) {
+    xs = x;
+  } else {
+    if (!g->x32 && (rc = fpr_dev_alloc(g, (void **)&g->x32, sizeof(float) * (size_t)g->n))) return rc;
+    xs = g->x32;
+  }
+  if ((rc = ensure_contrib<T>(g))) return rc;
+  DevPlan &P = g->fwd;
+  if ((rc = launch_init<T>(g, P, nullptr, x, xs, -1.0, sweeps))) return rc;
+  SweepArgs<T> a = make_args<T>(g, P, nullptr, xs, d, flags_of(o), nullptr);
+  std::vector<hipEvent_t> ev(3 * (size_t)sweeps, nullptr);
+  for (auto &e : ev) PR_HIP(hipEventCreate(&e));
+  for (int k = 0; k < sweeps; ++k) {
+    PR_HIP(hipEventRecord(ev[3 * k], g->work));
+    launch_marked<T>(g, a, o.mode == PR_FUSED, g->weighted, g->work, ev[3 * k + 1]);
+    PR_HIP(hipEventRecord(ev[3 * k + 2], g->work));
+  }
+  PR_HIP(hipGetLastError());
+  if (sizeof(T) != 8 || (a.flags & kFlagScaled))
+    hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const T *)xs, x, g->n,
+                       (const SweepState *)P.st, (a.flags & kFlagScaled) ? 1 : 0);
+  PR_HIP(hipStreamSynchronize(g->work));
+  double ts = 0.0, tf = 0.0;
+  for (int k = 0; k < sweeps; ++k) {
+    float a0 = 0.0f, a1 = 0.0f;
+    PR_HIP(hipEventElapsedTime(&a0, ev[3 * k], ev[3 * k + 1]));
+    PR_HIP(hipEventElapsedTime(&a1, ev[3 * k + 1], ev[3 * k + 2]));
+    ts += a0;
+    tf += a1;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  *sweep_ms = ts / sweeps;
+  *finalize_ms = tf / sweeps;
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" int pr_profile_sweeps(pr_graph *g, double d, const pr_opts *opts, double *x, int sweeps,
+                                 double *sweep_ms, double *finalize_ms, void *stream) {
+  pr_clear_error();
+  pr_opts o;
+  pr_opts_default(&o);
+  if (opts) o = *opts;
+  int rc = validate_common(g, d, o);
+  if (rc) return rc;
+  if (!x || !sweep_ms || !finalize_ms) return pr_fail(PR_EINVAL, "x/sweep_ms/finalize_ms are NULL");
+  if (sweeps < 1 || sweeps > 4096) return pr_fail(PR_EINVAL, "sweeps=%d outside [1, 4096]", sweeps);
+  StreamJoin join(g, stream);
+  if (o.precision == PR_FP32) return profile_impl<float>(g, d, o, x, sweeps, sweep_ms, finalize_ms);
+  return profile_impl<double>(g, d, o, x, sweeps, sweep_ms, finalize_ms);
 }
 
 extern "C" int pr_certificate(pr_graph *g, double d, const double *p, const double *x,

@@ -180,10 +180,10 @@ class Graph:
     def iterate(self, x: torch.Tensor, sweeps: int, d: float = 0.85, mode: str = "jacobi",
                 p: torch.Tensor | None = None, dangling: str = "uniform", norm: str = "l1",
                 fused_scaled: bool = True, use_hip_graph: bool = False, timed: bool = False,
-                stream=None):
-        """pr_iterate: exactly `sweeps` FP64 sweeps from x, in place.  Returns the last
-        residual, or (residual, device milliseconds of the sweeps) when timed."""
-        o = self._opts(mode, "fp64", dangling, norm, True, fused_scaled, None, use_hip_graph, None,
+                precision: str = "fp64", stream=None):
+        """pr_iterate: exactly `sweeps` sweeps from the FP64 vector x, in place.  Returns
+        the last residual, or (residual, device milliseconds of the sweeps) when timed."""
+        o = self._opts(mode, precision, dangling, norm, True, fused_scaled, None, use_hip_graph, None,
                        None, None)
         res = ctypes.c_double(0.0)
         ms = ctypes.c_double(0.0)
@@ -193,6 +193,19 @@ class Graph:
                                 _stream_ptr(stream))
         L.check(rc)
         return (res.value, ms.value) if timed else res.value
+
+    def profile_sweeps(self, sweeps: int, d: float = 0.85, mode: str = "jacobi", precision: str = "fp64",
+                       fused_scaled: bool = True, stream=None):
+        """pr_profile_sweeps from x = 1/n: average device milliseconds per launch of
+        the sweep kernel and of its finalize kernel, (sweep_ms, finalize_ms)."""
+        o = self._opts(mode, precision, "uniform", "l1", True, fused_scaled, None, False, None, None, None)
+        x = torch.full((self.n,), 1.0 / self.n, dtype=torch.float64, device=self.device)
+        a = ctypes.c_double(0.0)
+        b = ctypes.c_double(0.0)
+        rc = L.lib().pr_profile_sweeps(self._h, d, ctypes.byref(o), _dev_ptr(x, torch.float64, self.n, "x"),
+                                       int(sweeps), ctypes.byref(a), ctypes.byref(b), _stream_ptr(stream))
+        L.check(rc)
+        return a.value, b.value
 
     def certificate(self, x: torch.Tensor, d: float = 0.85, p: torch.Tensor | None = None,
                     stream=None) -> float:

@@ -45,10 +45,12 @@ def cases():
 
 
 CASES = cases()
-# plans that force every bin, many heavy chunks and ragged blocks on small graphs
-PLANS = [None, dict(chunk=64, tile_max_row=9, tile_rows=5, steps=3, hot_slots=100),
-         dict(chunk=256, tile_max_row=0, steps=1, hot_slots=0, gather_layout=0),
-         dict(chunk=96, tile_max_row=90, tile_rows=128, steps=2, hot_slots=7)]
+# plans that force every bin, many heavy chunks, ragged tiles and several
+# Gauss-Seidel block counts (the fused form launches one sweep per block) on
+# small graphs
+PLANS = [None, dict(chunk=64, tile_max_row=9, tile_rows=5, steps=3, hot_slots=100, gs_blocks=3),
+         dict(chunk=256, tile_max_row=0, steps=1, hot_slots=0, gather_layout=0, gs_blocks=1),
+         dict(chunk=96, tile_max_row=90, tile_rows=128, steps=2, hot_slots=7, gs_blocks=7)]
 
 
 def _ref(n, src, dst, w, p, tol=1e-15):
@@ -253,6 +255,30 @@ def test_fused_across_schedules():
         g.close()
 
 
+def test_gauss_seidel_blocks_cut_sweeps():
+    """Block Gauss-Seidel over out-degree-ordered blocks needs fewer sweeps than
+    Jacobi (Stein-Rosenberg for the regular splitting; soft check), and every
+    block count reaches the same fixed point."""
+    fpr = _fpr()
+    s, t = gg.rmat(14, 16, seed=2)
+    n = 1 << 14
+    _, xr = _ref(n, s, t, None, None)
+    say("gs blocks")
+    g = fpr.Graph(n, s, t)
+    _, it_j, _, _ = g.solve(d=D, tol=1e-10, mode="jacobi")
+    g.close()
+    for B in (1, 2, 4, 16, 64):
+        g = fpr.Graph(n, s, t, plan=dict(gs_blocks=B))
+        x, it, res, ok = g.solve(d=D, tol=1e-10, mode="fused")
+        say("  blocks=%d sweeps=%d (jacobi %d)" % (B, it, it_j))
+        assert ok and it <= it_j
+        if B >= 4:
+            assert it < it_j
+        x, it, res, ok = g.solve(d=D, tol=1e-13, mode="fused")
+        assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
+        g.close()
+
+
 def test_trace_and_warm_start():
     fpr = _fpr()
     s, t = gg.rmat(12, 16, seed=7)
@@ -296,3 +322,6 @@ def test_invalid_arguments():
     with pytest.raises(ValueError):
         g.solve(p=torch.zeros(3, dtype=torch.float64, device="cuda"))
     g.close()
+    for plan in (dict(gs_blocks=0), dict(gs_blocks=65), dict(chunk=32), dict(tile_rows=129)):
+        with pytest.raises(FusedPRError):
+            fpr.Graph(10, s, t, plan=plan)
