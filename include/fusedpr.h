@@ -116,7 +116,8 @@ typedef struct pr_plan_opts {
   int chunk;             /* lists longer than this (hubs) are summed by several wavefronts:
                             up to 8 * chunk edges by the 8 wavefronts of one workgroup, longer
                             ones in chunk-edge pieces, one wavefront each, added by the
-                            finalize kernel (default 1024, range [64, 2^20]) */
+                            finalize kernel (0 = default: about the edges per wavefront of
+                            a sweep launch, a power of two in [1024, 16384]; else [64, 2^20]) */
   int tile_max_row;      /* lists of 1..tile_max_row edges are packed into 512-edge tiles
                             (default 512, at most 512; lowered to chunk if larger); longer
                             ones get a wavefront each */
@@ -124,15 +125,18 @@ typedef struct pr_plan_opts {
   int steps;             /* one-wavefront rows per work item (default 1) */
   int hot_slots;         /* gather slots staged in LDS per sweep workgroup (-1 = as many as fit,
                             0 = none) */
-  int gather_layout;     /* 1 (default): store the gathered array sorted by gather count,
-                            so the hottest vertices come first; 0: vertex-id order */
+  int gather_layout;     /* order of the gathered array: 1 (default) sorted by gather count, the
+                            hottest vertices first; 0 vertex-id order; 2 the most gathered
+                            vertices (as many as the LDS copy holds in FP32) first, the rest in
+                            vertex-id order, which keeps the locality of an ordered input */
   int with_adjoint;      /* also plan the out-edge (transposed) pull for pr_adjoint */
-  int gs_blocks;         /* Gauss-Seidel blocks of the fused form (1..64, default 2): the
+  int gs_blocks;         /* Gauss-Seidel blocks of the fused form (0 = default: 2, or 1 for
+                            graphs under 64 edges per sweep wavefront; else 1..64): the
                             vertices, in decreasing out-degree, are cut into this many blocks
-                            of equal in-edge count (chunked rows join the last block) and
-                            swept one launch each, so every block reads the contributions the
-                            blocks before it wrote in the same sweep (Eq. 9 over the blocks).
-                            The Jacobi form ignores it. */
+                            of equal in-edge count (hubs join the last block) and swept one
+                            launch each, so every block reads the contributions the blocks
+                            before it wrote in the same sweep (Eq. 9 over the blocks).  The
+                            Jacobi form ignores it. */
 } pr_plan_opts;
 
 void pr_plan_opts_default(pr_plan_opts *o);

@@ -38,6 +38,7 @@ constexpr int kFinBlock = 1024;  // threads of the one-workgroup finalize kernel
 constexpr int kBatch = 8;                     // loads in flight per lane and batch
 constexpr int kPrefetch = 4;                  // row rounds whose list bounds are loaded up front
 constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather slots, per workgroup
+constexpr int kHotLayout = kHotBytes / 4;     // slots kept in gather-count order by gather_layout 2
 constexpr int kTileEdges = 512;               // edges of a tile: 8 consecutive per lane
 constexpr int kTileRows = 128;                // rows of a tile at most (row sums staged in LDS)
 
@@ -101,7 +102,9 @@ struct DevPlan {
   int n_waves = 0;  // wavefronts of one sweep launch
   int part_stride = 0;
   int n_blocks = 1;               // Gauss-Seidel blocks of the fused form
-  std::vector<int> block_items;   // [n_blocks + 1] first work item of each block
+  std::vector<int> block_items;   // [n_blocks + 1] first position of each block's sweep list
+  int *block_pos = nullptr;       // the same on the device
+  int *wave_cnt = nullptr;        // [n_blocks * n_waves] list length of each wavefront per block
   std::vector<int> block_slots;   // [n_blocks + 1] first gather slot of each block's non-hub
                                   // vertices (the hubs' slots come before block 0's)
   int64_t n_light = 0, n_medium = 0, n_heavy_rows = 0;  // rows in tiles, one wavefront each, chunked

@@ -32,6 +32,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <queue>
 #include <vector>
 
 #include "internal.h"
@@ -40,14 +41,14 @@ using namespace fpr;
 
 extern "C" void pr_plan_opts_default(pr_plan_opts *o) {
   if (!o) return;
-  o->chunk = 1024;
+  o->chunk = 0;
   o->tile_max_row = kTileEdges;
   o->tile_rows = kTileRows;
   o->steps = 1;
   o->hot_slots = -1;
   o->gather_layout = 1;
   o->with_adjoint = 0;
-  o->gs_blocks = 2;
+  o->gs_blocks = 0;
 }
 
 int fpr_dev_alloc(pr_graph *g, void **p, size_t bytes) {
@@ -107,15 +108,28 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     }
   }
   // Gather layout: the hubs first, then the other vertices block by block;
-  // inside each group by decreasing gather count (gather_layout = 1) or by
-  // vertex id (0).  block_slots[b] = first slot of block b's non-hub vertices,
-  // so the slots block b+1 reads fresh are [block_slots[0], block_slots[b+1]).
+  // inside each group by decreasing gather count (gather_layout = 1), by
+  // vertex id (0), or (2) the group's vertices among the kHotLayout most
+  // gathered ones first, by decreasing gather count, then the rest by vertex
+  // id (keeps the locality of an ordered input for the gathers that miss the
+  // LDS copy).  block_slots[b] = first slot of block b's non-hub vertices, so
+  // the slots block b+1 reads fresh are [block_slots[0], block_slots[b+1]).
   std::vector<uint32_t> pos(n);
   {
-    std::vector<uint32_t> lay(n);
-    for (int64_t k = 0; k < n; ++k) lay[k] = o.gather_layout ? order[k] : (uint32_t)k;
+    std::vector<uint32_t> rank(n);
+    for (int64_t k = 0; k < n; ++k) rank[order[k]] = (uint32_t)k;
     auto group = [&](uint32_t v) { return bin_of(v) == 0 ? -1 : (int)blk[v]; };
-    std::stable_sort(lay.begin(), lay.end(), [&](uint32_t a, uint32_t b) { return group(a) < group(b); });
+    auto key = [&](uint32_t v) -> uint64_t {  // order inside a group
+      if (o.gather_layout == 1) return rank[v];
+      if (o.gather_layout == 2 && rank[v] < (uint32_t)kHotLayout) return rank[v];
+      return (uint64_t)kHotLayout + v;
+    };
+    std::vector<uint32_t> lay(n);
+    for (int64_t k = 0; k < n; ++k) lay[k] = (uint32_t)k;
+    std::sort(lay.begin(), lay.end(), [&](uint32_t a, uint32_t b) {
+      const int ga = group(a), gb = group(b);
+      return ga != gb ? ga < gb : key(a) < key(b);
+    });
     for (int64_t k = 0; k < n; ++k) pos[lay[k]] = (uint32_t)k;
     P.block_slots.assign(B + 1, (int)n);
     for (int64_t k = n - 1; k >= 0; --k)
@@ -151,15 +165,14 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   // Work items.  Per block, in launch order: hubs, one-wavefront rows (longest
   // first), tiles, zero rows.  Two lists share the rows and tiles:
   //  * the sweep list: a hub of at most 8 * chunk edges is one item of a
-  //    whole workgroup: 8 copies at positions 8q..8q+7, which every launch
-  //    gives to the 8 wavefronts of one workgroup in the same round (position
-  //    p goes to wavefront p mod W, W wavefronts per launch, and W is a
-  //    multiple of 8).  A longer hub is split into `chunk`-edge items whose
-  //    sums the finalize kernel adds (msplit / hpart);
+  //    whole workgroup (all 8 of its wavefronts), a longer hub is split into
+  //    `chunk`-edge items whose sums the finalize kernel adds (msplit /
+  //    hpart); the items are dealt to wavefronts per block (below);
   //  * the batched list: each hub is split into `chunk`-edge items whose sums
   //    the batched finalize kernel adds (hsplit / hpart).
   const int W = g->grid * kSweepWaves;
   std::vector<int4> items, bitems, hsplit, msplit, tiles;
+  std::vector<int> wave_cnt;
   const int64_t wg_max = (int64_t)kSweepWaves * o.chunk;  // longest list of a workgroup item
   std::vector<int32_t> tidx;
   std::vector<double> tw;
@@ -231,21 +244,81 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
       i = end;
     }
     bitems.insert(bitems.end(), rest.begin(), rest.end());
-    // the sweep list of this block: hub groups at positions that are
-    // multiples of 8 (any launch assigns position p to wavefront p mod W, and
-    // W is a multiple of 8, so a group lands on the 8 wavefronts of one
-    // workgroup in one round), after at most 7 no-op items
-    std::vector<int4> blkitems;
-    if (!hubs.empty())
-      while ((items.size() + blkitems.size()) % kSweepWaves) blkitems.push_back(make_int4(kZero, 0, 0, 0));
-    for (size_t h = 0; h < hubs.size(); ++h) {
-      const int64_t r = hub0 + (int64_t)h;
-      if (rptr[r + 1] - rptr[r] <= wg_max)
-        for (int k = 0; k < kSweepWaves; ++k) blkitems.push_back(make_int4(kHubWG, (int)r, 0, 0));
+    // The sweep list of this block: work items are dealt to the W
+    // wavefronts of a launch by longest-processing-time first, with a cost
+    // model in 512-edge gather rounds.  Hubs go first, each to all 8
+    // wavefronts of the least loaded workgroup (so every wavefront of that
+    // workgroup meets the hub's barrier at the same list index); then every
+    // other item, longest first, to the least loaded wavefront.  Wavefront w's
+    // k-th item sits at position base + k * W + w; wave_cnt[b * W + w] is the
+    // length of its list (positions past it are never read).
+    {
+      auto rounds = [&](int64_t L, int64_t per) { return (double)((L + per - 1) / per); };
+      auto cost = [&](const int4 &it) -> double {
+        switch (it.x) {
+          case kTile: return 1.25;
+          case kRows: {
+            double c = 0.0;
+            for (int r = it.y; r < it.z; ++r) c += rounds(rptr[r + 1] - rptr[r], 512) + 0.25;
+            return c;
+          }
+          case kHeavy: return rounds(std::min<int64_t>(o.chunk, rptr[it.y + 1] - rptr[it.y] - (int64_t)it.z * o.chunk), 512);
+          case kZero: return 0.25 + (it.z - it.y) / 512.0;
+          default: return 1.0;
+        }
+      };
+      const int G = W / kSweepWaves;
+      std::vector<double> load(W, 0.0);
+      std::vector<std::vector<int4>> lists(W);
+      // hubs, heaviest first, to whole workgroups
+      std::vector<int64_t> wgh;
+      for (size_t h = 0; h < hubs.size(); ++h)
+        if (rptr[hub0 + h + 1] - rptr[hub0 + h] <= wg_max) wgh.push_back(hub0 + (int64_t)h);
+      std::stable_sort(wgh.begin(), wgh.end(), [&](int64_t a2, int64_t b2) {
+        return rptr[a2 + 1] - rptr[a2] > rptr[b2 + 1] - rptr[b2];
+      });
+      {
+        using E = std::pair<double, int>;
+        std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+        for (int q = 0; q < G; ++q) heap.push(E(0.0, q));
+        for (int64_t r : wgh) {
+          E e = heap.top();
+          heap.pop();
+          const double c = rounds(rptr[r + 1] - rptr[r], (int64_t)kSweepWaves * 512) + 0.5;
+          for (int k = 0; k < kSweepWaves; ++k) {
+            lists[e.second * kSweepWaves + k].push_back(make_int4(kHubWG, (int)r, 0, 0));
+            load[e.second * kSweepWaves + k] += c;
+          }
+          heap.push(E(e.first + c, e.second));
+        }
+      }
+      std::vector<int4> other(mega);
+      other.insert(other.end(), rest.begin(), rest.end());
+      std::vector<double> oc(other.size());
+      for (size_t k = 0; k < other.size(); ++k) oc[k] = cost(other[k]);
+      std::vector<size_t> ord(other.size());
+      for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+      std::stable_sort(ord.begin(), ord.end(), [&](size_t a2, size_t b2) { return oc[a2] > oc[b2]; });
+      {
+        using E = std::pair<double, int>;
+        std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+        for (int w2 = 0; w2 < W; ++w2) heap.push(E(load[w2], w2));
+        for (size_t k : ord) {
+          E e = heap.top();
+          heap.pop();
+          lists[e.second].push_back(other[k]);
+          heap.push(E(e.first + oc[k], e.second));
+        }
+      }
+      size_t kmax = 0;
+      for (auto &l : lists) kmax = std::max(kmax, l.size());
+      const size_t base = items.size();
+      items.resize(base + kmax * (size_t)W, make_int4(kZero, 0, 0, 0));
+      for (int w2 = 0; w2 < W; ++w2) {
+        for (size_t k = 0; k < lists[w2].size(); ++k) items[base + k * (size_t)W + w2] = lists[w2][k];
+        wave_cnt.push_back((int)lists[w2].size());
+      }
     }
-    blkitems.insert(blkitems.end(), mega.begin(), mega.end());
-    blkitems.insert(blkitems.end(), rest.begin(), rest.end());
-    items.insert(items.end(), blkitems.begin(), blkitems.end());
     P.block_items.push_back((int)items.size());
   }
   P.n_blocks = B;
@@ -280,18 +353,20 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     if (!check(it)) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
   for (const int4 &it : bitems)
     if (it.x == kHubWG || !check(it)) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
-  // a hub item fills positions 8q..8q+7 (the 8 wavefronts of one workgroup,
-  // one round): every wavefront of that workgroup meets its barrier
-  if (W % kSweepWaves) return pr_fail(PR_EDEVICE, "pr_graph_create: wavefront count not a multiple of 8");
-  for (size_t p = 0; p < items.size(); ++p)
-    if (items[p].x == kHubWG) {
-      const size_t first = p - p % kSweepWaves;
-      if (first + kSweepWaves > items.size())
-        return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (hub item)");
-      for (int k = 0; k < kSweepWaves; ++k)
-        if (items[first + k].x != kHubWG || items[first + k].y != items[p].y)
-          return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (hub item)");
-    }
+  // every wavefront of a workgroup meets each of its hub items at the same
+  // list index
+  for (int b = 0; b < B; ++b)
+    for (int w2 = 0; w2 < W; ++w2)
+      for (int k = 0; k < wave_cnt[(size_t)b * W + w2]; ++k) {
+        const int4 &it = items[(size_t)P.block_items[b] + (size_t)k * W + w2];
+        if (it.x != kHubWG) continue;
+        const int w0 = w2 - w2 % kSweepWaves;
+        for (int j = 0; j < kSweepWaves; ++j) {
+          const int4 &o2 = items[(size_t)P.block_items[b] + (size_t)k * W + w0 + j];
+          if (k >= wave_cnt[(size_t)b * W + w0 + j] || o2.x != kHubWG || o2.y != it.y)
+            return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (hub item)");
+        }
+      }
 
   int64_t before = g->device_bytes;
   int rc;
@@ -303,6 +378,11 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   if (w && (rc = upload(g, &P.w, wv.data(), wv.size()))) return rc;
   if ((rc = upload(g, &P.items, items.data(), items.size()))) return rc;
   if ((rc = upload(g, &P.bitems, bitems.data(), bitems.size()))) return rc;
+  if ((rc = upload(g, &P.wave_cnt, wave_cnt.data(), wave_cnt.size()))) return rc;
+  {
+    std::vector<int> bpos(P.block_items.begin(), P.block_items.end());
+    if ((rc = upload(g, &P.block_pos, bpos.data(), bpos.size()))) return rc;
+  }
   if ((rc = upload(g, &P.hsplit, hsplit.data(), hsplit.size()))) return rc;
   if ((rc = upload(g, &P.msplit, msplit.data(), msplit.size()))) return rc;
   if ((rc = upload(g, &P.tiles, tiles.data(), tiles.size()))) return rc;
@@ -352,13 +432,12 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
   pr_plan_opts o;
   pr_plan_opts_default(&o);
   if (opts) o = *opts;
-  if (o.chunk < 64 || o.chunk > (1 << 20) || o.tile_max_row < 0 || o.tile_max_row > kTileEdges ||
-      o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 || o.steps > 64 || o.gs_blocks < 1 ||
-      o.gs_blocks > 64)
+  if ((o.chunk != 0 && (o.chunk < 64 || o.chunk > (1 << 20))) || o.tile_max_row < 0 || o.tile_max_row > kTileEdges ||
+      o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 || o.steps > 64 || o.gs_blocks < 0 ||
+      o.gs_blocks > 64 || o.gather_layout < 0 || o.gather_layout > 2)
     return pr_fail(PR_EINVAL,
-                   "pr_graph_create: need 64 <= chunk <= 2^20, 0 <= tile_max_row <= 512, "
-                   "1 <= tile_rows <= 128, 1 <= steps <= 64, 1 <= gs_blocks <= 64");
-  o.tile_max_row = std::min(o.tile_max_row, o.chunk);
+                   "pr_graph_create: need chunk = 0 or 64 <= chunk <= 2^20, 0 <= tile_max_row <= 512, "
+                   "1 <= tile_rows <= 128, 1 <= steps <= 64, 0 <= gs_blocks <= 64, gather_layout 0..2");
   int dev_count = 0;
   hipError_t he = hipGetDeviceCount(&dev_count);
   if (he != hipSuccess || dev_count < 1)
@@ -377,6 +456,22 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
   }
   g->n_cu = prop.multiProcessorCount;
   g->grid = fpr_grid_for(g);
+  if (o.chunk == 0) {
+    // hubs start at about the average edge share of one sweep wavefront
+    // (a power of two in [1024, 16384]): a longer list on one wavefront would
+    // be the launch's critical path
+    const int64_t W = (int64_t)g->grid * kSweepWaves;
+    int64_t c = 1024;
+    while (c < 16384 && 2 * c <= csr->m / W) c *= 2;
+    o.chunk = (int)c;
+  }
+  o.tile_max_row = std::min(o.tile_max_row, o.chunk);
+  if (o.gs_blocks == 0) {
+    // a second launch per sweep pays off once a sweep is long against the
+    // cost of a launch: about 64 edges per wavefront
+    o.gs_blocks = csr->m >= 64 * (int64_t)g->grid * kSweepWaves ? 2 : 1;
+  }
+  g->popts = o;
   rc = [&]() -> int {
     // 1 / W_v, W_v summed over out-edges in out order
     const int64_t n = g->n;

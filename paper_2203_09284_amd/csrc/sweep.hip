@@ -81,9 +81,11 @@ struct SweepArgs {
   int n_waves;
   int hot;  // gather slots staged in LDS (<= kHotSlots<T>)
   int flags;
-  // launch-specific: the work items [item_lo, item_hi) of this launch, where
-  // its wavefront partials go, and what the finalize kernel sums
-  int item_lo, item_hi;
+  // launch-specific: the blocks [blk_lo, blk_hi) of this launch, where its
+  // workgroup partials go, and what the finalize kernel sums
+  const int *block_pos;  // first list position of each block
+  const int *wave_cnt;   // [block][wavefront] list lengths
+  int blk_lo, blk_hi;
   int part_base;    // first partial slot written by this launch
   int part_stride;  // SoA stride of the three partial rows
   int n_part;       // partial slots the finalize kernel sums
@@ -474,9 +476,8 @@ __device__ __forceinline__ void hub_wg(const Ctx<T> &C, const T *hot, double (*s
 
 // A few workgroups per CU.  The workgroup first copies the hottest gather
 // slots (the first `hot` of the gather layout) into LDS, then each wavefront
-// takes the work items at positions congruent to its index modulo W (W
-// wavefronts in the launch), so the items run roughly in order: hubs first,
-// then rows by decreasing length.
+// works through its own list of items in each block of the launch (the plan
+// deals the items to wavefronts, longest first, to balance them).
 // Every wavefront accumulates its rows' change / dangling / total mass; the
 // workgroup writes one partial of each; a fixed item-to-wavefront map keeps
 // the sums reproducible.
@@ -536,17 +537,17 @@ void k_sweep(SweepArgs<T> a) {
   Red red;
   int par = 0;
   double *rowsum = rowsum_all[wave];
-  // position p goes to wavefront p mod W in every launch (the plan places
-  // each hub's 8 items on one workgroup that way)
-  int first = gw - a.item_lo % a.n_waves;
-  if (first < 0) first += a.n_waves;
-  for (int item = a.item_lo + first; item < a.item_hi; item += a.n_waves) {
-    const int4 wi = a.items[item];
-    if (wi.x == kTile) tile_rows<T, FUSED, WEIGHTED>(C, a, hot, rowsum, wi.y, red);
-    else if (wi.x == kRows) row_group<T, FUSED, WEIGHTED>(C, hot, wi.y, wi.z, wi.w, red);
-    else if (wi.x == kHubWG) hub_wg<T, FUSED, WEIGHTED>(C, hot, s_hub, par, wi.y, red);
-    else if (wi.x == kHeavy) hub_chunk<T, FUSED, WEIGHTED>(C, hot, a.hpart, a.chunk, wi.y, wi.z, wi.w);
-    else zero_rows<T, FUSED>(C, hot, wi.y, wi.z, red);
+  for (int b = a.blk_lo; b < a.blk_hi; ++b) {
+    const int base = a.block_pos[b];
+    const int cnt = a.wave_cnt[(size_t)b * a.n_waves + gw];
+    for (int k = 0; k < cnt; ++k) {
+      const int4 wi = a.items[base + k * a.n_waves + gw];
+      if (wi.x == kTile) tile_rows<T, FUSED, WEIGHTED>(C, a, hot, rowsum, wi.y, red);
+      else if (wi.x == kRows) row_group<T, FUSED, WEIGHTED>(C, hot, wi.y, wi.z, wi.w, red);
+      else if (wi.x == kHubWG) hub_wg<T, FUSED, WEIGHTED>(C, hot, s_hub, par, wi.y, red);
+      else if (wi.x == kHeavy) hub_chunk<T, FUSED, WEIGHTED>(C, hot, a.hpart, a.chunk, wi.y, wi.z, wi.w);
+      else zero_rows<T, FUSED>(C, hot, wi.y, wi.z, red);
+    }
   }
   // one partial per workgroup: wavefront sums, then the waves in order
   const bool linf = (a.flags & kFlagLinf) != 0;
@@ -840,8 +841,10 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
     a.hot = (int)std::min<int64_t>(hot, g->n);
   }
   a.flags = flags | (p ? 0 : kFlagUniformP);
-  a.item_lo = 0;
-  a.item_hi = P.n_items;
+  a.block_pos = P.block_pos;
+  a.wave_cnt = P.wave_cnt;
+  a.blk_lo = 0;
+  a.blk_hi = P.n_blocks;
   a.part_base = 0;
   a.part_stride = P.part_stride;
   a.n_part = P.n_waves / kSweepWaves;
@@ -867,8 +870,8 @@ void launch_one(const DevPlan &P, const SweepArgs<T> &a0, hipStream_t s, hipEven
   SweepArgs<T> a = a0;
   a.fresh_lo = P.block_slots[0];
   for (int b = 0; b < B; ++b) {
-    a.item_lo = P.block_items[b];
-    a.item_hi = P.block_items[b + 1];
+    a.blk_lo = b;
+    a.blk_hi = b + 1;
     a.part_base = b * (P.n_waves / kSweepWaves);
     a.fresh_hi = P.block_slots[b];
     hipLaunchKernelGGL((k_sweep<T, FUSED, WEIGHTED>), grid, block, 0, s, a);

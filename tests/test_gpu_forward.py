@@ -50,7 +50,7 @@ CASES = cases()
 # small graphs
 PLANS = [None, dict(chunk=64, tile_max_row=9, tile_rows=5, steps=3, hot_slots=100, gs_blocks=3),
          dict(chunk=256, tile_max_row=0, steps=1, hot_slots=0, gather_layout=0, gs_blocks=1),
-         dict(chunk=96, tile_max_row=90, tile_rows=128, steps=2, hot_slots=7, gs_blocks=7)]
+         dict(chunk=96, tile_max_row=90, tile_rows=128, steps=2, hot_slots=7, gs_blocks=7, gather_layout=2)]
 
 
 def _ref(n, src, dst, w, p, tol=1e-15):
@@ -322,6 +322,6 @@ def test_invalid_arguments():
     with pytest.raises(ValueError):
         g.solve(p=torch.zeros(3, dtype=torch.float64, device="cuda"))
     g.close()
-    for plan in (dict(gs_blocks=0), dict(gs_blocks=65), dict(chunk=32), dict(tile_rows=129)):
+    for plan in (dict(gs_blocks=-1), dict(gs_blocks=65), dict(chunk=32), dict(tile_rows=129), dict(gather_layout=3)):
         with pytest.raises(FusedPRError):
             fpr.Graph(10, s, t, plan=plan)
