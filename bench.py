@@ -95,8 +95,9 @@ def kernel_source_sha():
 
 
 def traffic_record(key):
-    """HBM bytes per launch from the committed rocprofv3 counter runs
-    (profiles/traffic.json), valid only while the kernel sources are unchanged."""
+    """HBM bytes per sweep (the sweep kernel's launches of one sweep) from the
+    committed rocprofv3 counter runs (profiles/traffic.json), valid only while
+    the kernel sources are unchanged."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -106,7 +107,7 @@ def traffic_record(key):
         return None
     if not rec or rec.get("source_sha") != kernel_source_sha():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_sweep")
 
 
 def timed(torch, fn, steps, warmup):
@@ -158,10 +159,13 @@ def solve_legs(torch, g, m, tol, steps, warmup, names, x_ref=None):
     return forms
 
 
-def roofline(achieved_gbs, traffic, kernel, bytes_launch, us_launch):
+def roofline(achieved_gbs, traffic, kernel, bytes_sweep, us_sweep, launches):
+    """`achieved` and `traffic` are per sweep: the sweep kernel's launches of one
+    sweep (one per Gauss-Seidel block in the fused form), timed together."""
     return {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
-            "bytes_per_launch": bytes_launch, "us_per_launch": round(us_launch, 2)}
+            "alg_bytes_per_sweep": bytes_sweep, "us_per_sweep": round(us_sweep, 2),
+            "launches_per_sweep": launches}
 
 
 # ----------------------------------------------------------------- legs --
@@ -241,7 +245,8 @@ def leg_rmat24(torch, fpr, steps, warmup):
     out = dict(workload="rmat24", n=n, m=m, tol=1e-8, fp32_tol=1e-7,
                forms={k: rounded(v) for k, v in forms.items()},
                speedup_fused_fp32_vs_jacobi_fp64=sig(forms["jacobi-fp64"]["ms"] / forms["fused-fp32"]["ms"]),
-               roofline=roofline(ach, traffic_record("fused_fp32_rmat24"), "k_sweep<float, fused>", b32, k32),
+               roofline=roofline(ach, traffic_record("fused_fp32_rmat24"), "k_sweep<float, fused>", b32, k32,
+                                 g.stats()["gs_blocks"]),
                finalize_us=round(f32, 2), jacobi_fp64_sweep_kernel_us=round(k64, 2))
     g.close()
     return out
@@ -274,10 +279,11 @@ def profile_driver(args):
 
 def pmc_summary(args):
     """Turn two rocprofv3 --pmc runs of the --profile driver (FETCH_SIZE, then
-    WRITE_SIZE; counter_collection CSVs) into the bytes per launch of the sweep
-    kernel.  Each counter is scaled by bytes / counter-reading of the reference
-    copy kernel of the same run (torch.mul over COPY_BYTES, read + write).
-    Writes the record into profiles/traffic.json under --pmc-key."""
+    WRITE_SIZE; counter_collection CSVs) into the bytes one sweep moves through
+    the sweep kernel (all of its launches in that sweep: one per Gauss-Seidel
+    block in the fused form).  Each counter is scaled by bytes / reading of the
+    reference copy kernel of the same run (torch.mul over COPY_BYTES, read +
+    write).  Writes the record into profiles/traffic.json under KEY."""
     import csv
     key, fetch_csv, write_csv, driver_log = args.pmc_summary
     drv = json.loads([ln for ln in open(driver_log) if ln.startswith('{"profile"')][-1])
@@ -294,17 +300,18 @@ def pmc_summary(args):
                 copy.append(v)
         if not sweep or not copy:
             raise SystemExit("%s: no sweep or reference copy dispatches for %s" % (path, counter))
-        return float(np.mean(sweep)), float(np.median(copy)), len(sweep)
+        return float(np.sum(sweep)) / drv["sweeps"], float(np.median(copy)), len(sweep)
     f_sweep, f_copy, n_f = read(fetch_csv, "FETCH_SIZE")
     w_sweep, w_copy, n_w = read(write_csv, "WRITE_SIZE")
     cb = drv["copy_bytes"]
     rd = f_sweep * cb / f_copy
     wr = w_sweep * cb / w_copy
-    rec = {"bytes_per_launch": int(round(rd + wr)), "read_bytes": int(round(rd)), "write_bytes": int(round(wr)),
+    rec = {"bytes_per_sweep": int(round(rd + wr)), "read_bytes": int(round(rd)), "write_bytes": int(round(wr)),
            "fetch_scale": sig(cb / f_copy), "write_scale": sig(cb / w_copy),
-           "fetch_raw_bytes_per_launch": int(round(f_sweep)), "write_raw_bytes_per_launch": int(round(w_sweep)),
-           "launches": [n_f, n_w], "b_alg": drv["b_alg"], "amplification": sig((rd + wr) / drv["b_alg"], 4),
-           "n": drv["n"], "m": drv["m"], "source_sha": drv["source_sha"]}
+           "fetch_raw_bytes_per_sweep": int(round(f_sweep)), "write_raw_bytes_per_sweep": int(round(w_sweep)),
+           "launches_per_sweep": n_f // drv["sweeps"], "sweeps": drv["sweeps"], "b_alg": drv["b_alg"],
+           "amplification": sig((rd + wr) / drv["b_alg"], 4), "n": drv["n"], "m": drv["m"],
+           "source_sha": drv["source_sha"]}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(path)) if os.path.exists(path) else {}
     allrec[key] = rec
@@ -426,7 +433,7 @@ def main():
         "config": {"workload": "rmat20", "graph": w_desc("rmat20"), "n": n, "m": m, "d": D, "tol": tol,
                    "form": "fused-fp64", "step": "one solve from 1/n to L1<tol"},
         "roofline": roofline(achieved, traffic_record("fused_fp64_rmat20"), "k_sweep<double, fused>",
-                             bytes_sweep, k_fused),
+                             bytes_sweep, k_fused, st["gs_blocks"]),
         "cpu_baseline": cpu,
         "forms": {k: rounded(f) for k, f in forms.items()},
         "kernel_us": {k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},

@@ -152,7 +152,9 @@ typedef struct pr_graph_stats {
   int64_t n_items;                    /* wavefront work items per sweep */
   int64_t n_dangling;
   int64_t device_bytes;               /* graph + plan bytes held on the device */
-  int grid;                           /* workgroups of one sweep launch (one per CU) */
+  int grid;                           /* workgroups of one sweep launch */
+  int gs_blocks;                      /* Gauss-Seidel blocks (sweep launches of the fused form) */
+  int chunk;                          /* hub threshold in edges, as resolved */
 } pr_graph_stats;
 
 int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *out);

@@ -38,7 +38,8 @@ class PrGraphStats(ctypes.Structure):
                 ("n_light", ctypes.c_int64), ("n_medium", ctypes.c_int64), ("n_heavy", ctypes.c_int64),
                 ("e_light", ctypes.c_int64), ("e_medium", ctypes.c_int64), ("e_heavy", ctypes.c_int64),
                 ("n_items", ctypes.c_int64), ("n_dangling", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("grid", ctypes.c_int)]
+                ("device_bytes", ctypes.c_int64), ("grid", ctypes.c_int), ("gs_blocks", ctypes.c_int),
+                ("chunk", ctypes.c_int)]
 
 
 class PrOpts(ctypes.Structure):

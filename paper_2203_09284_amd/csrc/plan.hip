@@ -531,5 +531,7 @@ extern "C" int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *s) {
   s->n_dangling = g->n_dangling;
   s->device_bytes = g->device_bytes;
   s->grid = g->grid;
+  s->gs_blocks = g->fwd.n_blocks;
+  s->chunk = g->fwd.chunk;
   return PR_OK;
 }

@@ -46,6 +46,29 @@ using namespace fpr::dev;
 
 namespace {
 
+// Streaming accesses (graph arrays read once per sweep, per-vertex operands)
+// can be issued non-temporal so they do not displace the gathered
+// contributions from the caches: FPR_NT=1 for the reads and the rank store,
+// FPR_NT=2 also for the contribution store.
+#ifndef FPR_NT
+#define FPR_NT 0
+#endif
+template <typename V>
+__device__ __forceinline__ V sld(const V *p) {
+  if constexpr (FPR_NT >= 1) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename V>
+__device__ __forceinline__ void sst_x(V *p, V v) {
+  if constexpr (FPR_NT >= 1) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <typename V>
+__device__ __forceinline__ void sst_c(V *p, V v) {
+  if constexpr (FPR_NT >= 2) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // ------------------------------------------------------------ arguments --
 
 template <typename T>
@@ -154,9 +177,9 @@ __device__ __forceinline__ void update_loaded(const Ctx<T> &C, T *hot, uint32_t 
 
 template <typename T, bool FUSED>
 __device__ __forceinline__ void update_vertex(const Ctx<T> &C, T *hot, int i, double s, Red &red) {
-  const uint32_t u = C.rows[i];
-  const double pu = (C.flags & kFlagUniformP) ? C.inv_n : C.p[u];
-  update_loaded<T, FUSED>(C, hot, u, C.rowpos[i], (double)C.x[u], C.inv_w[u], pu, s, red);
+  const uint32_t u = sld(C.rows + i);
+  const double pu = (C.flags & kFlagUniformP) ? C.inv_n : sld(C.p + u);
+  update_loaded<T, FUSED>(C, hot, u, sld(C.rowpos + i), (double)sld(C.x + u), sld(C.inv_w + u), pu, s, red);
 }
 
 // The update of vertex u from its pulled sum s, with its operands loaded:
@@ -171,10 +194,10 @@ __device__ __forceinline__ void update_loaded(const Ctx<T> &C, T *hot, uint32_t 
   const double xn = adj ? pu + C.d * (iw * s + (iw == 0.0 ? C.dterm : 0.0))
                         : C.tele * pu + C.d * (s + C.dterm);
   const T xs = (T)xn;
-  C.x[u] = xs;
+  sst_x(C.x + u, xs);
   const double xd = (double)xs;
   if (adj || iw != 0.0) {
-    C.cout[slot] = adj ? xs : (T)(xd * iw);
+    sst_c(C.cout + slot, adj ? xs : (T)(xd * iw));
   }
   if (iw == 0.0) red.dang += xd;
   const double dl = fabs(xd - xo);
@@ -235,8 +258,8 @@ __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i
       eb[k] = 0;
       len[k] = 0;
       if (r < i1) {
-        eb[k] = C.rptr[r];
-        len[k] = (int)(C.rptr[r + 1] - eb[k]);
+        eb[k] = sld(C.rptr + (r));
+        len[k] = (int)(sld(C.rptr + (r + 1)) - eb[k]);
       }
     }
 #pragma unroll
@@ -249,11 +272,11 @@ __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i
       uint32_t u = 0, slot = 0;
       double xo = 0.0, iw = 0.0, pu = C.inv_n;
       if (owner) {
-        u = C.rows[r];
-        slot = C.rowpos[r];
-        xo = (double)C.x[u];
-        iw = C.inv_w[u];
-        if (!(C.flags & kFlagUniformP)) pu = C.p[u];
+        u = sld(C.rows + (r));
+        slot = sld(C.rowpos + (r));
+        xo = (double)sld(C.x + (u));
+        iw = sld(C.inv_w + (u));
+        if (!(C.flags & kFlagUniformP)) pu = sld(C.p + (u));
       }
       const uint32_t e0 = eb[k];
       const int L = len[k];
@@ -264,8 +287,8 @@ __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
           const int j = j0 + b * lpr;
-          s[b] = j < L ? C.idx[e0 + j] : 0;
-          if constexpr (WEIGHTED) wt[b] = j < L ? C.w[e0 + j] : 0.0;
+          s[b] = j < L ? sld(C.idx + (e0 + j)) : 0;
+          if constexpr (WEIGHTED) wt[b] = j < L ? sld(C.w + (e0 + j)) : 0.0;
         }
         T v[kBatch];
 #pragma unroll
@@ -305,24 +328,24 @@ __device__ __forceinline__ void tile_rows(const Ctx<T> &C, const SweepArgs<T> &a
   for (int k = 0; k < 2; ++k) {
     const int r = lane + 64 * k;
     if (r < nr) {
-      u[k] = C.rows[r0 + r];
-      slot[k] = C.rowpos[r0 + r];
-      xo[k] = (double)C.x[u[k]];
-      iw[k] = C.inv_w[u[k]];
-      if (!(C.flags & kFlagUniformP)) pu[k] = C.p[u[k]];
+      u[k] = sld(C.rows + (r0 + r));
+      slot[k] = sld(C.rowpos + (r0 + r));
+      xo[k] = (double)sld(C.x + u[k]);
+      iw[k] = sld(C.inv_w + u[k]);
+      if (!(C.flags & kFlagUniformP)) pu[k] = sld(C.p + u[k]);
     }
   }
   const size_t base = (size_t)t * kTileEdges;
   int32_t s[kBatch];
 #pragma unroll
-  for (int k = 0; k < kBatch; ++k) s[k] = a.tidx[base + k * 64 + lane];
-  const uint32_t fl = a.tmask[(size_t)t * 64 + lane];
+  for (int k = 0; k < kBatch; ++k) s[k] = sld(a.tidx + (base + k * 64 + lane));
+  const uint32_t fl = sld(a.tmask + ((size_t)t * 64 + lane));
   T v[kBatch];
 #pragma unroll
   for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, s[k]);
 #pragma unroll
   for (int k = 0; k < kBatch; ++k) {
-    if constexpr (WEIGHTED) v[k] = (T)((double)v[k] * a.tw[base + k * 64 + lane]);  // padding weight 0
+    if constexpr (WEIGHTED) v[k] = (T)((double)v[k] * sld(a.tw + (base + k * 64 + lane)));  // padding weight 0
     else v[k] = lane * kBatch + k < ne ? v[k] : (T)0;
   }
   // row index (within the tile) of this lane's first row start
@@ -394,8 +417,8 @@ template <typename T, bool FUSED, bool WEIGHTED>
 __device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double *hpart, int chunk, int i, int c,
                                           int slot) {
   const int lane = threadIdx.x & 63;
-  const uint32_t rb = C.rptr[i];
-  const int L = (int)(C.rptr[i + 1] - rb);
+  const uint32_t rb = sld(C.rptr + (i));
+  const int L = (int)(sld(C.rptr + (i + 1)) - rb);
   const uint32_t eb = rb + (uint32_t)c * (uint32_t)chunk;
   const int ne = min(chunk, L - c * chunk);
   LaneSum<T> acc;
@@ -405,8 +428,8 @@ __device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double 
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
       const int j = j0 + 64 * k;
-      s[k] = j < ne ? C.idx[eb + j] : 0;
-      if constexpr (WEIGHTED) wt[k] = j < ne ? C.w[eb + j] : 0.0;
+      s[k] = j < ne ? sld(C.idx + (eb + j)) : 0;
+      if constexpr (WEIGHTED) wt[k] = j < ne ? sld(C.w + (eb + j)) : 0.0;
     }
     T v[kBatch];
 #pragma unroll
@@ -432,16 +455,16 @@ template <typename T, bool FUSED, bool WEIGHTED>
 __device__ __forceinline__ void hub_wg(const Ctx<T> &C, const T *hot, double (*s_hub)[kSweepWaves], int &par,
                                        int i, Red &red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t rb = C.rptr[i];
-  const int L = (int)(C.rptr[i + 1] - rb);
+  const uint32_t rb = sld(C.rptr + (i));
+  const int L = (int)(sld(C.rptr + (i + 1)) - rb);
   uint32_t u = 0, slot = 0;
   double xo = 0.0, iw = 0.0, pu = C.inv_n;
   if (wave == 0 && lane == 0) {
-    u = C.rows[i];
-    slot = C.rowpos[i];
-    xo = (double)C.x[u];
-    iw = C.inv_w[u];
-    if (!(C.flags & kFlagUniformP)) pu = C.p[u];
+    u = sld(C.rows + (i));
+    slot = sld(C.rowpos + (i));
+    xo = (double)sld(C.x + (u));
+    iw = sld(C.inv_w + (u));
+    if (!(C.flags & kFlagUniformP)) pu = sld(C.p + (u));
   }
   LaneSum<T> acc;
   for (int j0 = wave * (kBatch * 64) + lane; j0 < L; j0 += kSweepWaves * kBatch * 64) {
@@ -450,8 +473,8 @@ __device__ __forceinline__ void hub_wg(const Ctx<T> &C, const T *hot, double (*s
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
       const int j = j0 + 64 * k;
-      sl[k] = j < L ? C.idx[rb + j] : 0;
-      if constexpr (WEIGHTED) wt[k] = j < L ? C.w[rb + j] : 0.0;
+      sl[k] = j < L ? sld(C.idx + (rb + j)) : 0;
+      if constexpr (WEIGHTED) wt[k] = j < L ? sld(C.w + (rb + j)) : 0.0;
     }
     T v[kBatch];
 #pragma unroll
