@@ -7,6 +7,56 @@
 namespace fpr {
 namespace dev {
 
+// ------------------------------------------------------- cross-lane moves --
+//
+// DPP moves (a VALU operand modifier, no LDS round trip, unlike __shfl_*,
+// which becomes ds_bpermute).  Lanes without a source, and rows outside the
+// row mask, read 0.  Controls: row_shr:n shifts within rows of 16 lanes,
+// row_bcast:15 / :31 broadcast lane 15 of each row (lane 31) to the next rows,
+// wave_shr:1 shifts the whole wavefront by one lane.
+enum : int {
+  kDppRowShr1 = 0x111,
+  kDppRowShr2 = 0x112,
+  kDppRowShr4 = 0x114,
+  kDppRowShr8 = 0x118,
+  kDppWaveShr1 = 0x138,
+  kDppRowBcast15 = 0x142,
+  kDppRowBcast31 = 0x143
+};
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, true);
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL, ROW_MASK>(__float_as_int(v)));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL, ROW_MASK>((int)b);
+  const int hi = dpp_i<CTRL, ROW_MASK>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Inclusive prefix sum of an int over the 64 lanes.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x += dpp_i<kDppRowShr1>(x);
+  x += dpp_i<kDppRowShr2>(x);
+  x += dpp_i<kDppRowShr4>(x);
+  x += dpp_i<kDppRowShr8>(x);
+  x += dpp_i<kDppRowBcast15, 0xa>(x);
+  x += dpp_i<kDppRowBcast31, 0xc>(x);
+  return x;
+}
+
 // ------------------------------------------------------------ arithmetic --
 
 // Per-lane sum: plain FP64, or FP32 with Neumaier compensation.
@@ -27,8 +77,26 @@ struct LaneSum<double> {
   __device__ __forceinline__ void add_before(const LaneSum &earlier) { s = earlier.s + s; }
   // this = this + later
   __device__ __forceinline__ void combine_with(const LaneSum &later) { s = s + later.s; }
-  // butterfly over the lpr-lane group (lpr a power of two, uniform in the wavefront)
+  template <int CTRL, int ROW_MASK = 0xf>
+  __device__ __forceinline__ LaneSum dpp() const {
+    LaneSum r;
+    r.s = dpp_d<CTRL, ROW_MASK>(s);
+    return r;
+  }
+  // sum over the lpr-lane group (lpr a power of two, uniform in the
+  // wavefront): the whole wavefront by a DPP scan read at lane 63, smaller
+  // groups by a butterfly
   __device__ __forceinline__ void group_reduce(int lpr) {
+    if (lpr == 64) {
+      s += dpp_d<kDppRowShr1>(s);
+      s += dpp_d<kDppRowShr2>(s);
+      s += dpp_d<kDppRowShr4>(s);
+      s += dpp_d<kDppRowShr8>(s);
+      s += dpp_d<kDppRowBcast15, 0xa>(s);
+      s += dpp_d<kDppRowBcast31, 0xc>(s);
+      s = readlane_d(s, 63);
+      return;
+    }
     for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   }
 };
@@ -65,7 +133,31 @@ struct LaneSum<float> {
     c = c + c2 + err;
     s = t;
   }
+  template <int CTRL, int ROW_MASK = 0xf>
+  __device__ __forceinline__ LaneSum dpp() const {
+    LaneSum r;
+    r.s = dpp_f<CTRL, ROW_MASK>(s);
+    r.c = dpp_f<CTRL, ROW_MASK>(c);
+    return r;
+  }
+  template <int CTRL, int ROW_MASK = 0xf>
+  __device__ __forceinline__ void scan_step() {
+    LaneSum e = dpp<CTRL, ROW_MASK>();
+    e.combine(s, c);
+    *this = e;
+  }
   __device__ __forceinline__ void group_reduce(int lpr) {
+    if (lpr == 64) {
+      scan_step<kDppRowShr1>();
+      scan_step<kDppRowShr2>();
+      scan_step<kDppRowShr4>();
+      scan_step<kDppRowShr8>();
+      scan_step<kDppRowBcast15, 0xa>();
+      scan_step<kDppRowBcast31, 0xc>();
+      s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), 63));
+      c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c), 63));
+      return;
+    }
     for (int off = lpr >> 1; off > 0; off >>= 1) {
       float s2 = __shfl_xor(s, off, 64);
       float c2 = __shfl_xor(c, off, 64);
@@ -73,6 +165,27 @@ struct LaneSum<float> {
     }
   }
 };
+
+// Segmented inclusive scan over the 64 lanes: lane l ends with the sum of
+// lanes k..l, k the last lane <= l whose flag is set (lane 0 if none).
+template <typename T, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_scan_step(LaneSum<T> &v, int &f) {
+  LaneSum<T> p = v.template dpp<CTRL, ROW_MASK>();
+  const int pf = dpp_i<CTRL, ROW_MASK>(f);
+  p.combine_with(v);
+  if (!f) v = p;
+  f |= pf;
+}
+template <typename T>
+__device__ __forceinline__ void seg_scan(LaneSum<T> &v, bool flag) {
+  int f = flag ? 1 : 0;
+  seg_scan_step<T, kDppRowShr1, 0xf>(v, f);
+  seg_scan_step<T, kDppRowShr2, 0xf>(v, f);
+  seg_scan_step<T, kDppRowShr4, 0xf>(v, f);
+  seg_scan_step<T, kDppRowShr8, 0xf>(v, f);
+  seg_scan_step<T, kDppRowBcast15, 0xa>(v, f);
+  seg_scan_step<T, kDppRowBcast31, 0xc>(v, f);
+}
 
 // Reductions carried per thread through a work item.
 struct Red {

@@ -221,7 +221,8 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
         }
         const int t = (int)tiles.size();
         tiles.push_back(make_int4((int)r0, (int)(i - r0), (int)edges, 0));
-        rest.push_back(make_int4(kTile, t, 0, 0));
+        // the tile's first row, rows and edges travel in the item (one load less)
+        rest.push_back(make_int4(kTile, t, (int)r0, (int)(((i - r0) << 16) | edges)));
         tidx.resize((size_t)(t + 1) * kTileEdges, 0);
         if (w) tw.resize((size_t)(t + 1) * kTileEdges, 0.0);
         tmask.resize((size_t)(t + 1) * 64, 0);
@@ -344,7 +345,8 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     if (it.x == kZero) return it.y >= 0 && it.y <= it.z && it.z <= n;
     if (it.x == kTile) {
       const int4 d = tiles[it.y];
-      return d.x >= 0 && d.y >= 1 && d.y <= kTileRows && d.x + d.y <= n && d.z >= d.y && d.z <= kTileEdges &&
+      return d.x == it.z && d.y == (it.w >> 16) && d.z == (it.w & 0xffff) &&
+             d.x >= 0 && d.y >= 1 && d.y <= kTileRows && d.x + d.y <= n && d.z >= d.y && d.z <= kTileEdges &&
              (int64_t)(rptr[d.x + d.y] - rptr[d.x]) == d.z;
     }
     return false;

@@ -216,22 +216,21 @@ __device__ __forceinline__ const T *src_of(const Ctx<T> &C, int32_t s) {
 // array are read unconditionally, at slot 0 of the side that is not used, and
 // the value is selected: this keeps the gathers of a batch independent (no
 // branch, no address-space select that would turn them into flat loads).
-#ifndef FPR_GATHER_MASKED
-#define FPR_GATHER_MASKED 1
-#endif
+//
+// The global side is read through an address-space-1 (global) pointer: a
+// generic pointer would let the compiler fold the two loads into one flat
+// load of a selected address, which serialises on both wait counters.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
 template <typename T, bool FUSED>
 __device__ __forceinline__ T gather(const Ctx<T> &C, const T *hot, int32_t s) {
   const bool h = s < C.hot;
   const T vh = hot[h ? s : 0];
-#if FPR_GATHER_MASKED
   // global load only on the lanes whose slot is not in LDS
   T vg = vh;
-  if (!h) vg = src_of<T, FUSED>(C, s)[s];
+  if (!h) vg = ((gptr<T>)src_of<T, FUSED>(C, s))[s];
   return vg;
-#else
-  const T vg = src_of<T, FUSED>(C, s)[h ? 0 : s];
-  return h ? vh : vg;
-#endif
 }
 
 // ---------------------------------------------------- work item kinds --
@@ -306,7 +305,8 @@ __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i
   }
 }
 
-// A tile of consecutive rows (<= kTileRows rows, <= kTileEdges edges).  Lane
+// A tile of consecutive rows r0.. (nr <= kTileRows rows, ne <= kTileEdges
+// edges, all given by the work item).  Lane
 // l loads edges 8l..8l+7 (lane-transposed storage: each load instruction reads
 // 256 contiguous bytes), gathers them, and sums runs between row starts.  A
 // row that starts in lane a and ends in lane b > a is completed by a
@@ -317,10 +317,8 @@ __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i
 // before the gathers.
 template <typename T, bool FUSED, bool WEIGHTED>
 __device__ __forceinline__ void tile_rows(const Ctx<T> &C, const SweepArgs<T> &a, T *hot,
-                                          double *rowsum, int t, Red &red) {
+                                          double *rowsum, int t, int r0, int nr, int ne, Red &red) {
   const int lane = threadIdx.x & 63;
-  const int4 d = a.tiles[t];
-  const int r0 = d.x, nr = d.y, ne = d.z;
   // rank-update operands of rows r0 + lane and r0 + 64 + lane
   uint32_t u[2] = {0, 0}, slot[2] = {0, 0};
   double xo[2] = {0.0, 0.0}, iw[2] = {0.0, 0.0}, pu[2] = {C.inv_n, C.inv_n};
@@ -350,13 +348,7 @@ __device__ __forceinline__ void tile_rows(const Ctx<T> &C, const SweepArgs<T> &a
   }
   // row index (within the tile) of this lane's first row start
   const int pc = __popc(fl);
-  int incl = pc;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int o = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += o;
-  }
-  const int rowbase = incl - pc;
+  const int rowbase = wave_incl_scan(pc) - pc;
   // lane-local runs: head = before the first start, complete rows, tail = after the last start
   LaneSum<T> cur, head;
   bool seen = false;
@@ -372,20 +364,11 @@ __device__ __forceinline__ void tile_rows(const Ctx<T> &C, const SweepArgs<T> &a
     cur.add(v[k]);
   }
   if (!seen) head = cur;
-  // segmented inclusive scan over lanes of (flag, value)
+  // segmented inclusive scan over lanes of (flag, value), then each lane's
+  // predecessor (lane 0 reads zero)
   LaneSum<T> sc = cur;
-  bool f = seen;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    LaneSum<T> prev = sc.shfl_up(off);
-    const bool pf = __shfl_up((int)f, off, 64) != 0;
-    if (lane >= off) {
-      if (!f) sc.add_before(prev);
-      f = f || pf;
-    }
-  }
-  LaneSum<T> carry = sc.shfl_up(1);
-  if (lane == 0) carry = LaneSum<T>();
+  seg_scan<T>(sc, seen);
+  LaneSum<T> carry = sc.template dpp<kDppWaveShr1>();
   if (seen && lane > 0) {
     carry.combine_with(head);
     rowsum[rowbase - 1] = carry.value();
@@ -505,7 +488,7 @@ __device__ __forceinline__ void hub_wg(const Ctx<T> &C, const T *hot, double (*s
 // workgroup writes one partial of each; a fixed item-to-wavefront map keeps
 // the sums reproducible.
 #ifndef FPR_WAVES_PER_EU
-#define FPR_WAVES_PER_EU 6
+#define FPR_WAVES_PER_EU 4
 #endif
 
 // Copy of the hot slots [0, C.hot) into LDS with 16-byte loads, all issued
@@ -563,9 +546,12 @@ void k_sweep(SweepArgs<T> a) {
   for (int b = a.blk_lo; b < a.blk_hi; ++b) {
     const int base = a.block_pos[b];
     const int cnt = a.wave_cnt[(size_t)b * a.n_waves + gw];
+    // the next item's record is loaded while the current one runs
+    int4 next = cnt > 0 ? a.items[base + gw] : make_int4(kZero, 0, 0, 0);
     for (int k = 0; k < cnt; ++k) {
-      const int4 wi = a.items[base + k * a.n_waves + gw];
-      if (wi.x == kTile) tile_rows<T, FUSED, WEIGHTED>(C, a, hot, rowsum, wi.y, red);
+      const int4 wi = next;
+      if (k + 1 < cnt) next = a.items[base + (k + 1) * a.n_waves + gw];
+      if (wi.x == kTile) tile_rows<T, FUSED, WEIGHTED>(C, a, hot, rowsum, wi.y, wi.z, wi.w >> 16, wi.w & 0xffff, red);
       else if (wi.x == kRows) row_group<T, FUSED, WEIGHTED>(C, hot, wi.y, wi.z, wi.w, red);
       else if (wi.x == kHubWG) hub_wg<T, FUSED, WEIGHTED>(C, hot, s_hub, par, wi.y, red);
       else if (wi.x == kHeavy) hub_chunk<T, FUSED, WEIGHTED>(C, hot, a.hpart, a.chunk, wi.y, wi.z, wi.w);
