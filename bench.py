@@ -11,8 +11,9 @@ are resident in HBM before timing.
 
 The same JSON line carries, on the same GPU:
   forms       plain FP64 Jacobi, fused FP64 (mass-scaled and unscaled), FP32
-              Jacobi/fused with FP64 refinement to 1e-8, each with its error
-              against the oracle's fixed point;
+              Jacobi/fused with FP64 refinement to 1e-8, and the edge-centric
+              contributionList form of Algorithm 1 (scatter, then contiguous
+              row sums), each with its error against the oracle's fixed point;
   batched     k = 64 one-hot personalized solves (FP32, per-column tol 1e-6)
               against 64 sequential plain FP64 single-seed solves;
   er10k       directed Erdos-Renyi n=10,000, m=80,000, plain FP64, tol 1e-10;
@@ -230,12 +231,12 @@ def leg_rmat24(torch, fpr, steps, warmup):
     n = w["n"]
     log("generated rmat24 in %.1fs" % (time.perf_counter() - t0))
     t0 = time.perf_counter()
-    g = fpr.Graph(n, w["src"], w["dst"])
+    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1))
     del w
     m = g.m
     log("rmat24 on device: m'=%d setup %.1fs" % (m, time.perf_counter() - t0))
     forms = solve_legs(torch, g, m, 1e-8, steps, warmup, ["jacobi-fp64", "fused-fp32", "jacobi-fp32",
-                                                          "fused-fp64"])
+                                                          "fused-fp64", "edge_list-fp32"])
     k32, f32 = sweep_kernel_us(g, "fused", "fp32", sweeps=20)
     k64, _ = sweep_kernel_us(g, "jacobi", "fp64", sweeps=20)
     b32 = b_alg(n, m, 4)
@@ -260,8 +261,8 @@ def profile_driver(args):
     import paper_2203_09284_amd as fpr
     torch.cuda.set_device(0)
     w = workload(args.workload)
-    g = fpr.Graph(w["n"], w["src"], w["dst"])
     mode, prec = args.profile.split("-")[:2]
+    g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1 if mode == "edge_list" else 0))
     x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
     g.iterate(x, args.profile_sweeps, d=D, mode=mode, precision=prec, use_hip_graph=False)
     torch.cuda.synchronize()
@@ -329,7 +330,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only (no extra legs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rmat24", action="store_true")
-    ap.add_argument("--profile", default=None, help="jacobi-fp64|fused-fp64|jacobi-fp32|fused-fp32")
+    ap.add_argument("--profile", default=None, help="{jacobi,fused,edge_list}-{fp64,fp32}")
     ap.add_argument("--profile-sweeps", type=int, default=20)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("KEY", "FETCH_CSV", "WRITE_CSV", "DRIVER_LOG"))
@@ -357,7 +358,7 @@ def main():
     n, tol = w["n"], w["tol"]
     log("generated rmat20: n=%d raw m=%d in %.1fs" % (n, len(w["src"]), time.perf_counter() - t0))
     t0 = time.perf_counter()
-    g = fpr.Graph(n, w["src"], w["dst"])
+    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1))
     setup_s = time.perf_counter() - t0
     st = g.stats()
     m = g.m
@@ -366,10 +367,10 @@ def main():
     x_ref, _, _ = oracle.pagerank_ec(og, D, tol=1e-13, max_iter=1000, threads=cores)
 
     forms = solve_legs(torch, g, m, tol, args.steps, args.warmup,
-                       ["jacobi-fp64", "fused-fp64", "fused-fp64-unscaled", "jacobi-fp32", "fused-fp32"],
-                       x_ref)
+                       ["jacobi-fp64", "fused-fp64", "fused-fp64-unscaled", "jacobi-fp32", "fused-fp32",
+                        "edge_list-fp64"], x_ref)
     kern = {name: sweep_kernel_us(g, *name.split("-")) for name in
-            ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32")}
+            ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32", "edge_list-fp64")}
     for name, (ks, kf) in kern.items():
         log("%-12s sweep kernel %.1f us + finalize %.1f us per launch" % (name, ks, kf))
     k_fused = kern["fused-fp64"][0]

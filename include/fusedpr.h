@@ -137,6 +137,9 @@ typedef struct pr_plan_opts {
                             launch each, so every block reads the contributions the blocks
                             before it wrote in the same sweep (Eq. 9 over the blocks).  The
                             Jacobi form ignores it. */
+  int with_cl;           /* also build the edge-centric contributionList layout (Section 3:
+                            contributionList + offsetList) for PR_EDGE_LIST: 8 B (16 B
+                            weighted) per edge more on the device (default 0) */
 } pr_plan_opts;
 
 void pr_plan_opts_default(pr_plan_opts *o);
@@ -162,13 +165,17 @@ int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *out);
 /* ------------------------------------------------------------------------
  * Solver options.
  * ---------------------------------------------------------------------- */
-enum pr_mode { PR_JACOBI = 0, PR_FUSED = 1 };
+enum pr_mode { PR_JACOBI = 0, PR_FUSED = 1, PR_EDGE_LIST = 2 };
 enum pr_precision { PR_FP64 = 0, PR_FP32 = 1 };
 enum pr_dangling { PR_DANGLING_UNIFORM = 0, PR_DANGLING_LEAK = 1 };
 enum pr_norm { PR_NORM_L1 = 0, PR_NORM_LINF = 1 };
 
 typedef struct pr_opts {
-  int mode;             /* PR_JACOBI (Algorithm 1) or PR_FUSED (Algorithm 2, block Gauss-Seidel) */
+  int mode;             /* PR_JACOBI (Algorithm 1 as a pull), PR_FUSED (Algorithm 2, block
+                            Gauss-Seidel) or PR_EDGE_LIST (Algorithm 1 with the paper's
+                            edge-ordered contributionList: a scatter through offsetList, then
+                            contiguous row sums; needs a graph planned with with_cl; same
+                            values, same summation order, same results as PR_JACOBI) */
   int precision;        /* PR_FP64, or PR_FP32: ranks and contributions stored and summed
                            in FP32 with compensated sums; residual and dangling mass in FP64 */
   int dangling;         /* PR_DANGLING_UNIFORM, or PR_DANGLING_LEAK (the paper's literal

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfusedpr.so")
 
 PR_OK, PR_NOT_CONVERGED, PR_EINVAL, PR_ENOMEM, PR_EDEVICE = 0, 1, -1, -2, -3
-PR_JACOBI, PR_FUSED = 0, 1
+PR_JACOBI, PR_FUSED, PR_EDGE_LIST = 0, 1, 2
 PR_FP64, PR_FP32 = 0, 1
 PR_DANGLING_UNIFORM, PR_DANGLING_LEAK = 0, 1
 PR_NORM_L1, PR_NORM_LINF = 0, 1
@@ -30,7 +30,8 @@ class PrCsr(ctypes.Structure):
 class PrPlanOpts(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int), ("tile_max_row", ctypes.c_int), ("tile_rows", ctypes.c_int),
                 ("steps", ctypes.c_int), ("hot_slots", ctypes.c_int),
-                ("gather_layout", ctypes.c_int), ("with_adjoint", ctypes.c_int), ("gs_blocks", ctypes.c_int)]
+                ("gather_layout", ctypes.c_int), ("with_adjoint", ctypes.c_int), ("gs_blocks", ctypes.c_int),
+                ("with_cl", ctypes.c_int)]
 
 
 class PrGraphStats(ctypes.Structure):

@@ -51,6 +51,7 @@ enum SweepFlags : int {
   kFlagScaled = 4,    // teleport scaled by the previous sweep's total mass
   kFlagUniformP = 8,  // p == 1/n (p pointer unused)
   kFlagAdjoint = 16,  // transposed iteration: lam' = g + d (W^-1 sum w lam + [W = 0] sum(lam) / n)
+  kFlagList = 32,     // edge-centric list form: no n-length contribution array
 };
 
 // Device-resident state of an iteration; one per graph and pull direction.
@@ -105,6 +106,14 @@ struct DevPlan {
   std::vector<int> block_items;   // [n_blocks + 1] first position of each block's sweep list
   int *block_pos = nullptr;       // the same on the device
   int *wave_cnt = nullptr;        // [n_blocks * n_waves] list length of each wavefront per block
+  // contributionList layout (plan option with_cl): list position of every
+  // edge = its position in tidx (tile rows) or cl_rows + its idx position
+  int32_t *cl_src = nullptr;      // [m] source of each out-edge (out-CSR order)
+  int32_t *cl_pos = nullptr;      // [m] its list position
+  double *cl_w = nullptr;         // [m] its weight (weighted graphs)
+  int64_t cl_size = 0;            // list positions (tiles * 512 + m)
+  uint32_t cl_rows = 0;           // first position of the idx region
+  std::vector<int64_t> inpos;     // host, during planning: in-CSR edge -> list position
   std::vector<int> block_slots;   // [n_blocks + 1] first gather slot of each block's non-hub
                                   // vertices (the hubs' slots come before block 0's)
   int64_t n_light = 0, n_medium = 0, n_heavy_rows = 0;  // rows in tiles, one wavefront each, chunked
@@ -135,6 +144,8 @@ struct pr_graph {
   double *c64[2] = {nullptr, nullptr};
   float *c32[2] = {nullptr, nullptr};
   float *x32 = nullptr;
+  double *cl64 = nullptr;       // contributionList buffers of the edge-centric form
+  float *cl32 = nullptr;
   double *xtmp = nullptr;
   double *trace_dev = nullptr;
   int trace_cap = 0;

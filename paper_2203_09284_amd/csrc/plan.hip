@@ -49,6 +49,7 @@ extern "C" void pr_plan_opts_default(pr_plan_opts *o) {
   o->gather_layout = 1;
   o->with_adjoint = 0;
   o->gs_blocks = 0;
+  o->with_cl = 0;
 }
 
 int fpr_dev_alloc(pr_graph *g, void **p, size_t bytes) {
@@ -75,7 +76,7 @@ static int upload(pr_graph *g, T **dst, const T *src, size_t count) {
 
 // Build one binned pull plan from a CSR (ptr[n+1], nbr[m], w[m] nullable).
 static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, const int32_t *nbr,
-                      const double *w, const pr_plan_opts &o) {
+                      const double *w, const pr_plan_opts &o, bool want_cl) {
   P.n = n;
   P.m = ptr[n];
   P.chunk = o.chunk;
@@ -162,6 +163,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     if (w) memcpy(&wv[rptr[i]], w + ptr[v], sizeof(double) * L);
   }
 
+  if (want_cl) P.inpos.assign((size_t)m, -1);
   // Work items.  Per block, in launch order: hubs, one-wavefront rows (longest
   // first), tiles, zero rows.  Two lists share the rows and tiles:
   //  * the sweep list: a hub of at most 8 * chunk edges is one item of a
@@ -233,6 +235,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
             const size_t at = (size_t)t * kTileEdges + (size_t)(j & 7) * 64 + (size_t)(j >> 3);
             tidx[at] = idx[e];
             if (w) tw[at] = wv[e];
+            if (want_cl) P.inpos[(size_t)(ptr[rows[r]] + (e - rptr[r]))] = (int64_t)at;
           }
         }
       }
@@ -321,6 +324,18 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
       }
     }
     P.block_items.push_back((int)items.size());
+  }
+  if (want_cl) {
+    // contributionList positions: tile edges keep their tidx position, the
+    // other lists follow the tiles at their idx position
+    P.cl_rows = (uint32_t)(tiles.size() * (size_t)kTileEdges);
+    P.cl_size = (int64_t)P.cl_rows + m;
+    if (P.cl_size >= INT32_MAX) return pr_fail(PR_EINVAL, "pr_graph_create: contributionList too large");
+    for (int64_t r = 0; r < n; ++r) {
+      const uint32_t v = rows[r];
+      for (int64_t k = 0; k < (int64_t)(ptr[v + 1] - ptr[v]); ++k)
+        if (P.inpos[(size_t)(ptr[v] + k)] < 0) P.inpos[(size_t)(ptr[v] + k)] = (int64_t)P.cl_rows + rptr[r] + k;
+    }
   }
   P.n_blocks = B;
   for (int b = 0; b + 1 < B; ++b)  // the last block's launch holds the hubs
@@ -491,9 +506,29 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
       if (W == 0.0) g->n_dangling++;
     }
     if ((rc2 = upload(g, &g->inv_w, inv_w.data(), inv_w.size()))) return rc2;
-    if ((rc2 = build_plan(g, g->fwd, n, csr->in_ptr, csr->in_src, csr->in_w, o))) return rc2;
+    if ((rc2 = build_plan(g, g->fwd, n, csr->in_ptr, csr->in_src, csr->in_w, o, o.with_cl != 0))) return rc2;
+    if (o.with_cl) {
+      // out-edge order: source, list position and weight of every edge
+      const int64_t m = csr->m;
+      std::vector<int32_t> src((size_t)m), pos((size_t)m);
+      std::vector<double> wv(csr->in_w ? (size_t)m : 0);
+      for (int64_t v = 0; v < n; ++v)
+        for (int64_t e = csr->out_ptr[v]; e < csr->out_ptr[v + 1]; ++e) {
+          const int64_t ie = csr->out_to_in[e];
+          const int64_t p = g->fwd.inpos[(size_t)ie];
+          if (ie < 0 || ie >= m || p < 0 || p >= g->fwd.cl_size)
+            return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (list position)");
+          src[(size_t)e] = (int32_t)v;
+          pos[(size_t)e] = (int32_t)p;
+          if (csr->in_w) wv[(size_t)e] = csr->in_w[ie];
+        }
+      std::vector<int64_t>().swap(g->fwd.inpos);
+      if ((rc2 = upload(g, &g->fwd.cl_src, src.data(), src.size()))) return rc2;
+      if ((rc2 = upload(g, &g->fwd.cl_pos, pos.data(), pos.size()))) return rc2;
+      if (csr->in_w && (rc2 = upload(g, &g->fwd.cl_w, wv.data(), wv.size()))) return rc2;
+    }
     if (o.with_adjoint) {
-      if ((rc2 = build_plan(g, g->adj, n, csr->out_ptr, csr->out_dst, csr->out_w, o))) return rc2;
+      if ((rc2 = build_plan(g, g->adj, n, csr->out_ptr, csr->out_dst, csr->out_w, o, false))) return rc2;
       std::vector<uint32_t> op(n + 1);
       for (int64_t v = 0; v <= n; ++v) op[v] = (uint32_t)csr->out_ptr[v];
       if ((rc2 = upload(g, &g->out_ptr, op.data(), op.size()))) return rc2;

@@ -69,7 +69,20 @@ __device__ __forceinline__ void sst_c(V *p, V v) {
   else *p = v;
 }
 
+// Weighted edge value: the product rounded on its own (never fused into the
+// following add), so every form that sums it gets the same bits.
+template <typename T>
+__device__ __forceinline__ T wmul(T v, double w) {
+#pragma clang fp contract(off)
+  return (T)((double)v * w);
+}
+
 // ------------------------------------------------------------ arguments --
+
+// How a sweep reads the value of an in-edge: gathered from the contribution
+// array (plain, or times the edge weight), or read from the edge-ordered
+// contributionList that a scatter kernel filled (weights already applied).
+enum SweepMode : int { kModePlain = 0, kModeWeighted = 1, kModeList = 2 };
 
 template <typename T>
 constexpr int kHotSlots = kHotBytes / (int)sizeof(T);
@@ -95,6 +108,8 @@ struct SweepArgs {
   T *x;
   T *c0;
   T *c1;
+  const T *cl;
+  uint32_t cl_rows;
   double *trace;
   double d;
   double inv_n;
@@ -125,6 +140,8 @@ struct Ctx {
   const double *inv_w;
   const double *p;
   T *x;
+  const T *cl;        // contributionList (list mode), in the plan's edge positions
+  uint32_t cl_rows;   // position of the first list edge (after the tiles)
   const T *cin;  // contributions of the previous sweep
   T *cout;       // contributions of this sweep
   double tele;   // (1-d) * mass scale
@@ -152,6 +169,8 @@ __device__ __forceinline__ Ctx<T> make_ctx(const SweepArgs<T> &a, const SweepSta
   C.inv_w = a.inv_w;
   C.p = a.p;
   C.x = a.x;
+  C.cl = a.cl;
+  C.cl_rows = a.cl_rows;
   C.cin = (it & 1) ? a.c1 : a.c0;
   C.cout = (it & 1) ? a.c0 : a.c1;
   C.fresh_lo = a.fresh_lo;
@@ -196,7 +215,7 @@ __device__ __forceinline__ void update_loaded(const Ctx<T> &C, T *hot, uint32_t 
   const T xs = (T)xn;
   sst_x(C.x + u, xs);
   const double xd = (double)xs;
-  if (adj || iw != 0.0) {
+  if ((adj || iw != 0.0) && !(C.flags & kFlagList)) {
     sst_c(C.cout + slot, adj ? xs : (T)(xd * iw));
   }
   if (iw == 0.0) red.dang += xd;
@@ -241,9 +260,10 @@ __device__ __forceinline__ T gather(const Ctx<T> &C, const T *hot, int32_t s) {
 // The list bounds of up to kPrefetch rounds are loaded before the first round,
 // and each round issues its rank-update loads before its gathers, so a round
 // costs about two dependent memory latencies.
-template <typename T, bool FUSED, bool WEIGHTED>
+template <typename T, bool FUSED, int MODE>
 __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i1, int lpr,
                                           Red &red) {
+  constexpr bool WEIGHTED = MODE == kModeWeighted, CL = MODE == kModeList;
   const int lane = threadIdx.x & 63;
   const int q = lane & (lpr - 1);
   const int g = lane / lpr;
@@ -283,19 +303,27 @@ __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i
       for (int j0 = q; j0 < L; j0 += kBatch * lpr) {
         int32_t s[kBatch];
         double wt[kBatch];
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-          const int j = j0 + b * lpr;
-          s[b] = j < L ? sld(C.idx + (e0 + j)) : 0;
-          if constexpr (WEIGHTED) wt[b] = j < L ? sld(C.w + (e0 + j)) : 0.0;
-        }
         T v[kBatch];
+        if constexpr (CL) {
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) v[b] = gather<T, FUSED>(C, hot, s[b]);
+          for (int b = 0; b < kBatch; ++b) {
+            const int j = j0 + b * lpr;
+            v[b] = j < L ? sld(C.cl + (C.cl_rows + e0 + j)) : (T)0;
+          }
+        } else {
+#pragma unroll
+          for (int b = 0; b < kBatch; ++b) {
+            const int j = j0 + b * lpr;
+            s[b] = j < L ? sld(C.idx + (e0 + j)) : 0;
+            if constexpr (WEIGHTED) wt[b] = j < L ? sld(C.w + (e0 + j)) : 0.0;
+          }
+#pragma unroll
+          for (int b = 0; b < kBatch; ++b) v[b] = gather<T, FUSED>(C, hot, s[b]);
+        }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
           T x = j0 + b * lpr < L ? v[b] : (T)0;
-          if constexpr (WEIGHTED) x = (T)((double)x * wt[b]);
+          if constexpr (WEIGHTED) x = wmul(x, wt[b]);
           acc.add(x);
         }
       }
@@ -315,9 +343,10 @@ __device__ __forceinline__ void row_group(const Ctx<T> &C, T *hot, int i0, int i
 // at lanes that hold a row start.  Completed row sums go to the wavefront's
 // LDS slice; then lane r updates rows r and r + 64 with operands it loaded
 // before the gathers.
-template <typename T, bool FUSED, bool WEIGHTED>
+template <typename T, bool FUSED, int MODE>
 __device__ __forceinline__ void tile_rows(const Ctx<T> &C, const SweepArgs<T> &a, T *hot,
                                           double *rowsum, int t, int r0, int nr, int ne, Red &red) {
+  constexpr bool WEIGHTED = MODE == kModeWeighted, CL = MODE == kModeList;
   const int lane = threadIdx.x & 63;
   // rank-update operands of rows r0 + lane and r0 + 64 + lane
   uint32_t u[2] = {0, 0}, slot[2] = {0, 0};
@@ -334,16 +363,21 @@ __device__ __forceinline__ void tile_rows(const Ctx<T> &C, const SweepArgs<T> &a
     }
   }
   const size_t base = (size_t)t * kTileEdges;
-  int32_t s[kBatch];
-#pragma unroll
-  for (int k = 0; k < kBatch; ++k) s[k] = sld(a.tidx + (base + k * 64 + lane));
   const uint32_t fl = sld(a.tmask + ((size_t)t * 64 + lane));
   T v[kBatch];
+  if constexpr (CL) {
 #pragma unroll
-  for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, s[k]);
+    for (int k = 0; k < kBatch; ++k) v[k] = sld(C.cl + (base + k * 64 + lane));
+  } else {
+    int32_t s[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) s[k] = sld(a.tidx + (base + k * 64 + lane));
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, s[k]);
+  }
 #pragma unroll
   for (int k = 0; k < kBatch; ++k) {
-    if constexpr (WEIGHTED) v[k] = (T)((double)v[k] * sld(a.tw + (base + k * 64 + lane)));  // padding weight 0
+    if constexpr (WEIGHTED) v[k] = wmul(v[k], sld(a.tw + (base + k * 64 + lane)));  // padding weight 0
     else v[k] = lane * kBatch + k < ne ? v[k] : (T)0;
   }
   // row index (within the tile) of this lane's first row start
@@ -396,9 +430,10 @@ __device__ __forceinline__ void zero_rows(const Ctx<T> &C, T *hot, int i0, int i
 
 // One `chunk`-edge piece of a very long hub list per wavefront; the piece sum
 // goes to its slot and the finalize kernel adds the pieces in order.
-template <typename T, bool FUSED, bool WEIGHTED>
+template <typename T, bool FUSED, int MODE>
 __device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double *hpart, int chunk, int i, int c,
                                           int slot) {
+  constexpr bool WEIGHTED = MODE == kModeWeighted, CL = MODE == kModeList;
   const int lane = threadIdx.x & 63;
   const uint32_t rb = sld(C.rptr + (i));
   const int L = (int)(sld(C.rptr + (i + 1)) - rb);
@@ -408,19 +443,27 @@ __device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double 
   for (int j0 = lane; j0 < ne; j0 += kBatch * 64) {
     int32_t s[kBatch];
     double wt[kBatch];
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const int j = j0 + 64 * k;
-      s[k] = j < ne ? sld(C.idx + (eb + j)) : 0;
-      if constexpr (WEIGHTED) wt[k] = j < ne ? sld(C.w + (eb + j)) : 0.0;
-    }
     T v[kBatch];
+    if constexpr (CL) {
 #pragma unroll
-    for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, s[k]);
+      for (int k = 0; k < kBatch; ++k) {
+        const int j = j0 + 64 * k;
+        v[k] = j < ne ? sld(C.cl + (C.cl_rows + eb + j)) : (T)0;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int j = j0 + 64 * k;
+        s[k] = j < ne ? sld(C.idx + (eb + j)) : 0;
+        if constexpr (WEIGHTED) wt[k] = j < ne ? sld(C.w + (eb + j)) : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, s[k]);
+    }
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
       T x = j0 + 64 * k < ne ? v[k] : (T)0;
-      if constexpr (WEIGHTED) x = (T)((double)x * wt[k]);
+      if constexpr (WEIGHTED) x = wmul(x, wt[k]);
       acc.add(x);
     }
   }
@@ -434,9 +477,10 @@ __device__ __forceinline__ void hub_chunk(const Ctx<T> &C, const T *hot, double 
 // Wavefront k sums the 512-edge pieces k, k+8, k+16, ... of the list; the 8
 // sums meet in LDS and wavefront 0 adds them in wavefront order and updates
 // the row.  `par` alternates the LDS buffer between consecutive hub items.
-template <typename T, bool FUSED, bool WEIGHTED>
+template <typename T, bool FUSED, int MODE>
 __device__ __forceinline__ void hub_wg(const Ctx<T> &C, const T *hot, double (*s_hub)[kSweepWaves], int &par,
                                        int i, Red &red) {
+  constexpr bool WEIGHTED = MODE == kModeWeighted, CL = MODE == kModeList;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t rb = sld(C.rptr + (i));
   const int L = (int)(sld(C.rptr + (i + 1)) - rb);
@@ -453,19 +497,27 @@ __device__ __forceinline__ void hub_wg(const Ctx<T> &C, const T *hot, double (*s
   for (int j0 = wave * (kBatch * 64) + lane; j0 < L; j0 += kSweepWaves * kBatch * 64) {
     int32_t sl[kBatch];
     double wt[kBatch];
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-      const int j = j0 + 64 * k;
-      sl[k] = j < L ? sld(C.idx + (rb + j)) : 0;
-      if constexpr (WEIGHTED) wt[k] = j < L ? sld(C.w + (rb + j)) : 0.0;
-    }
     T v[kBatch];
+    if constexpr (CL) {
 #pragma unroll
-    for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, sl[k]);
+      for (int k = 0; k < kBatch; ++k) {
+        const int j = j0 + 64 * k;
+        v[k] = j < L ? sld(C.cl + (C.cl_rows + rb + j)) : (T)0;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int j = j0 + 64 * k;
+        sl[k] = j < L ? sld(C.idx + (rb + j)) : 0;
+        if constexpr (WEIGHTED) wt[k] = j < L ? sld(C.w + (rb + j)) : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) v[k] = gather<T, FUSED>(C, hot, sl[k]);
+    }
 #pragma unroll
     for (int k = 0; k < kBatch; ++k) {
       T x = j0 + 64 * k < L ? v[k] : (T)0;
-      if constexpr (WEIGHTED) x = (T)((double)x * wt[k]);
+      if constexpr (WEIGHTED) x = wmul(x, wt[k]);
       acc.add(x);
     }
   }
@@ -526,9 +578,10 @@ __device__ __forceinline__ void load_hot(const Ctx<T> &C, T *hot) {
   for (int s = nvec * V + (int)threadIdx.x; s < C.hot; s += kSweepBlock) hot[s] = src_of<T, FUSED>(C, s)[s];
 }
 
-template <typename T, bool FUSED, bool WEIGHTED>
+template <typename T, bool FUSED, int MODE>
 __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(FPR_WAVES_PER_EU)))
 void k_sweep(SweepArgs<T> a) {
+  constexpr bool WEIGHTED = MODE == kModeWeighted, CL = MODE == kModeList;
   __shared__ __align__(16) T hot[kHotSlots<T>];
   __shared__ double rowsum_all[kSweepWaves][kTileRows];
   __shared__ double s_part[3][kSweepWaves];
@@ -536,7 +589,7 @@ void k_sweep(SweepArgs<T> a) {
   const SweepState *st = a.st;
   if (st->done) return;
   const Ctx<T> C = make_ctx<T, FUSED>(a, st);
-  load_hot<T, FUSED>(C, hot);
+  if constexpr (!CL) load_hot<T, FUSED>(C, hot);
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kSweepWaves + wave));
@@ -551,10 +604,10 @@ void k_sweep(SweepArgs<T> a) {
     for (int k = 0; k < cnt; ++k) {
       const int4 wi = next;
       if (k + 1 < cnt) next = a.items[base + (k + 1) * a.n_waves + gw];
-      if (wi.x == kTile) tile_rows<T, FUSED, WEIGHTED>(C, a, hot, rowsum, wi.y, wi.z, wi.w >> 16, wi.w & 0xffff, red);
-      else if (wi.x == kRows) row_group<T, FUSED, WEIGHTED>(C, hot, wi.y, wi.z, wi.w, red);
-      else if (wi.x == kHubWG) hub_wg<T, FUSED, WEIGHTED>(C, hot, s_hub, par, wi.y, red);
-      else if (wi.x == kHeavy) hub_chunk<T, FUSED, WEIGHTED>(C, hot, a.hpart, a.chunk, wi.y, wi.z, wi.w);
+      if (wi.x == kTile) tile_rows<T, FUSED, MODE>(C, a, hot, rowsum, wi.y, wi.z, wi.w >> 16, wi.w & 0xffff, red);
+      else if (wi.x == kRows) row_group<T, FUSED, MODE>(C, hot, wi.y, wi.z, wi.w, red);
+      else if (wi.x == kHubWG) hub_wg<T, FUSED, MODE>(C, hot, s_hub, par, wi.y, red);
+      else if (wi.x == kHeavy) hub_chunk<T, FUSED, MODE>(C, hot, a.hpart, a.chunk, wi.y, wi.z, wi.w);
       else zero_rows<T, FUSED>(C, hot, wi.y, wi.z, red);
     }
   }
@@ -574,6 +627,36 @@ void k_sweep(SweepArgs<T> a) {
     double v = s_part[r][0];
     for (int k = 1; k < kSweepWaves; ++k) v = (r == 0 && linf) ? fmax(v, s_part[r][k]) : v + s_part[r][k];
     a.wave_part[(size_t)r * a.part_stride + a.part_base + blockIdx.x] = v;
+  }
+}
+
+// Phase 1 of the edge-centric form (Algorithm 1): every out-edge v -> u gets
+// v's contribution x_v / W_v (times the edge weight) in its contributionList
+// position, the position of that edge in the sweep's edge layout.  The value
+// is computed exactly as the pull computes the gathered one, so both forms
+// sum the same numbers in the same order.
+template <typename T>
+struct ScatterArgs {
+  const int32_t *src;  // [m] source of each out-edge
+  const int32_t *pos;  // [m] its list position
+  const double *w;     // [m] its weight (weighted graphs)
+  const double *inv_w;
+  const T *x;
+  T *cl;
+  int64_t m;
+  const SweepState *st;
+};
+constexpr int kScatterGrid = 2048;
+
+template <typename T, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_scatter(ScatterArgs<T> a) {
+  if (a.st->done) return;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < a.m; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t v = sld(a.src + e);
+    const double xd = (double)a.x[v];
+    T c = (T)(xd * a.inv_w[v]);
+    if constexpr (WEIGHTED) c = wmul(c, sld(a.w + e));
+    a.cl[sld(a.pos + e)] = c;
   }
 }
 
@@ -783,6 +866,27 @@ int ensure_contrib(pr_graph *g) {
   return PR_OK;
 }
 
+template <typename T>
+T *cl_buf(pr_graph *g) {
+  if constexpr (sizeof(T) == 8) return g->cl64;
+  else return g->cl32;
+}
+
+// The contributionList of the edge-centric form, zeroed once (tile padding
+// positions are never written and must read zero).
+template <typename T>
+int ensure_cl(pr_graph *g) {
+  T **slot;
+  if constexpr (sizeof(T) == 8) slot = &g->cl64;
+  else slot = &g->cl32;
+  if (*slot) return PR_OK;
+  const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(1, g->fwd.cl_size);
+  int rc = fpr_dev_alloc(g, (void **)slot, bytes);
+  if (rc) return rc;
+  PR_HIP(hipMemsetAsync(*slot, 0, bytes, g->work));
+  return PR_OK;
+}
+
 int ensure_trace(pr_graph *g, int max_iter) {
   if (g->trace_cap >= max_iter) return PR_OK;
   int rc = fpr_dev_alloc(g, (void **)&g->trace_dev, sizeof(double) * (size_t)max_iter);
@@ -840,6 +944,8 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   a.x = x;
   a.c0 = c0 ? c0 : contrib<T>(g, 0);
   a.c1 = c1 ? c1 : contrib<T>(g, 1);
+  a.cl = cl_buf<T>(g);
+  a.cl_rows = P.cl_rows;
   a.trace = trace;
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
@@ -866,11 +972,11 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
 // several Gauss-Seidel blocks launches the sweep kernel once per block, so
 // each block reads what the blocks before it wrote in this sweep.  `mark`,
 // when given, is recorded right before the finalize kernel.
-template <typename T, bool FUSED, bool WEIGHTED>
+template <typename T, bool FUSED, int MODE>
 void launch_one(const DevPlan &P, const SweepArgs<T> &a0, hipStream_t s, hipEvent_t mark) {
   const dim3 grid(a0.n_waves / kSweepWaves), block(kSweepBlock);
   if (!FUSED || P.n_blocks <= 1) {
-    hipLaunchKernelGGL((k_sweep<T, FUSED, WEIGHTED>), grid, block, 0, s, a0);
+    hipLaunchKernelGGL((k_sweep<T, FUSED, MODE>), grid, block, 0, s, a0);
     if (mark) (void)hipEventRecord(mark, s);
     hipLaunchKernelGGL((k_finalize<T, FUSED>), dim3(1), dim3(kFinBlock), 0, s, a0);
     return;
@@ -883,7 +989,7 @@ void launch_one(const DevPlan &P, const SweepArgs<T> &a0, hipStream_t s, hipEven
     a.blk_hi = b + 1;
     a.part_base = b * (P.n_waves / kSweepWaves);
     a.fresh_hi = P.block_slots[b];
-    hipLaunchKernelGGL((k_sweep<T, FUSED, WEIGHTED>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_sweep<T, FUSED, MODE>), grid, block, 0, s, a);
   }
   if (mark) (void)hipEventRecord(mark, s);
   a.n_part = B * (P.n_waves / kSweepWaves);
@@ -891,22 +997,37 @@ void launch_one(const DevPlan &P, const SweepArgs<T> &a0, hipStream_t s, hipEven
 }
 
 template <typename T>
-void launch_marked(pr_graph *g, const SweepArgs<T> &a, bool fused, bool weighted, hipStream_t s,
+void launch_marked(pr_graph *g, const SweepArgs<T> &a, int form, bool weighted, hipStream_t s,
                    hipEvent_t mark) {
-  const DevPlan &P = g->fwd;  // the fused form runs on the forward plan only
-  if (fused) {
-    if (weighted) launch_one<T, true, true>(P, a, s, mark);
-    else launch_one<T, true, false>(P, a, s, mark);
+  const DevPlan &P = g->fwd;  // the fused and list forms run on the forward plan only
+  if (form == PR_EDGE_LIST) {
+    // Algorithm 1 as the paper lays it out: scatter the contributions into the
+    // edge-ordered list, then sum each row's contiguous slice
+    ScatterArgs<T> sa;
+    sa.src = P.cl_src;
+    sa.pos = P.cl_pos;
+    sa.w = P.cl_w;
+    sa.inv_w = g->inv_w;
+    sa.x = a.x;
+    sa.cl = const_cast<T *>(a.cl);
+    sa.m = P.m;
+    sa.st = a.st;
+    if (weighted) hipLaunchKernelGGL((k_scatter<T, true>), dim3(kScatterGrid), dim3(kBlock), 0, s, sa);
+    else hipLaunchKernelGGL((k_scatter<T, false>), dim3(kScatterGrid), dim3(kBlock), 0, s, sa);
+    launch_one<T, false, kModeList>(P, a, s, mark);
+  } else if (form == PR_FUSED) {
+    if (weighted) launch_one<T, true, kModeWeighted>(P, a, s, mark);
+    else launch_one<T, true, kModePlain>(P, a, s, mark);
   } else {
-    if (weighted) launch_one<T, false, true>(P, a, s, mark);
-    else launch_one<T, false, false>(P, a, s, mark);
+    if (weighted) launch_one<T, false, kModeWeighted>(P, a, s, mark);
+    else launch_one<T, false, kModePlain>(P, a, s, mark);
   }
 }
 
 template <typename T>
-void launch_sweeps(pr_graph *g, const SweepArgs<T> &a, bool fused, bool weighted, int count,
+void launch_sweeps(pr_graph *g, const SweepArgs<T> &a, int form, bool weighted, int count,
                    hipStream_t s) {
-  for (int k = 0; k < count; ++k) launch_marked<T>(g, a, fused, weighted, s, nullptr);
+  for (int k = 0; k < count; ++k) launch_marked<T>(g, a, form, weighted, s, nullptr);
 }
 
 // Cached hipGraph executables of `count` sweeps for one exact argument set.
@@ -918,15 +1039,15 @@ struct GraphEntry {
 static std::vector<GraphEntry> g_graph_cache;
 
 template <typename T>
-int run_sweeps(pr_graph *g, const SweepArgs<T> &a, bool fused, bool use_graph, int count) {
+int run_sweeps(pr_graph *g, const SweepArgs<T> &a, int form, bool use_graph, int count) {
   if (!use_graph) {
-    launch_sweeps(g, a, fused, g->weighted, count, g->work);
+    launch_sweeps(g, a, form, g->weighted, count, g->work);
     PR_HIP(hipGetLastError());
     return PR_OK;
   }
   std::vector<unsigned char> key(sizeof(a) + 3 * sizeof(int));
   memcpy(key.data(), &a, sizeof(a));
-  int extra[3] = {fused ? 1 : 0, count, (int)sizeof(T)};
+  int extra[3] = {form, count, (int)sizeof(T)};
   memcpy(key.data() + sizeof(a), extra, sizeof(extra));
   for (auto &e : g_graph_cache) {
     if (e.key_graph == g && e.key == key) {
@@ -940,7 +1061,7 @@ int run_sweeps(pr_graph *g, const SweepArgs<T> &a, bool fused, bool use_graph, i
   }
   hipGraph_t graph;
   PR_HIP(hipStreamBeginCapture(g->work, hipStreamCaptureModeThreadLocal));
-  launch_sweeps(g, a, fused, g->weighted, count, g->work);
+  launch_sweeps(g, a, form, g->weighted, count, g->work);
   hipError_t le = hipGetLastError();
   hipError_t ce = hipStreamEndCapture(g->work, &graph);
   if (le != hipSuccess) return pr_fail(PR_EDEVICE, "sweep launch during capture: %s", hipGetErrorString(le));
@@ -964,10 +1085,11 @@ int poll_state(pr_graph *g, DevPlan &P) {
 // stall: stop polling once the residual fails to halve between polls (FP32 floor).
 template <typename T>
 int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o, const double *p,
-                const double *x_in, T *x, int flags, bool fused, double *trace, bool stall,
+                const double *x_in, T *x, int flags, int form, double *trace, bool stall,
                 int *iters, double *resid) {
   int rc;
   if ((rc = ensure_contrib<T>(g))) return rc;
+  if (form == PR_EDGE_LIST && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
   if ((rc = launch_init<T>(g, P, p, x_in, x, tol, max_iter))) return rc;
   SweepArgs<T> a = make_args<T>(g, P, p, x, d, flags, trace);
@@ -976,7 +1098,7 @@ int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &
   int done_sweeps = 0;
   for (;;) {
     const int cnt = std::min(G, max_iter - done_sweeps);
-    if ((rc = run_sweeps<T>(g, a, fused, o.use_hip_graph != 0, cnt))) return rc;
+    if ((rc = run_sweeps<T>(g, a, form, o.use_hip_graph != 0, cnt))) return rc;
     if ((rc = poll_state(g, P))) return rc;
     done_sweeps = g->host_st->iter;
     if (g->host_st->done || done_sweeps >= max_iter) break;
@@ -993,7 +1115,10 @@ int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &
 int validate_common(pr_graph *g, double d, const pr_opts &o) {
   if (!g) return pr_fail(PR_EINVAL, "graph is NULL");
   if (!(d > 0.0 && d < 1.0)) return pr_fail(PR_EINVAL, "d=%g is not in (0, 1)", d);
-  if (o.mode != PR_JACOBI && o.mode != PR_FUSED) return pr_fail(PR_EINVAL, "bad mode %d", o.mode);
+  if (o.mode != PR_JACOBI && o.mode != PR_FUSED && o.mode != PR_EDGE_LIST)
+    return pr_fail(PR_EINVAL, "bad mode %d", o.mode);
+  if (o.mode == PR_EDGE_LIST && !g->fwd.cl_pos)
+    return pr_fail(PR_EINVAL, "the edge-list form needs a graph planned with with_cl = 1");
   if (o.precision != PR_FP64 && o.precision != PR_FP32)
     return pr_fail(PR_EINVAL, "bad precision %d", o.precision);
   if (o.dangling != PR_DANGLING_UNIFORM && o.dangling != PR_DANGLING_LEAK)
@@ -1014,6 +1139,7 @@ int flags_of(const pr_opts &o) {
   if (o.dangling == PR_DANGLING_LEAK) f |= kFlagLeak;
   if (o.norm == PR_NORM_LINF) f |= kFlagLinf;
   if (o.mode == PR_FUSED && o.fused_scaled) f |= kFlagScaled;
+  if (o.mode == PR_EDGE_LIST) f |= kFlagList;
   return f;
 }
 
@@ -1047,7 +1173,7 @@ void fpr_sweep_release(pr_graph *g) {
 
 int fpr_grid_for(pr_graph *g) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<double, false, false>, kSweepBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<double, false, kModePlain>, kSweepBlock, 0) !=
           hipSuccess ||
       nb < 1)
     nb = 1;
@@ -1089,14 +1215,14 @@ extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const p
     trace = g->trace_dev;
   }
   const int flags = flags_of(o);
-  const bool fused = o.mode == PR_FUSED;
+  const int form = o.mode;
   const bool scaled = (flags & kFlagScaled) != 0;
   int it = 0;
   double r = INFINITY;
   double target = tol;
   if (o.precision == PR_FP64) {
     if ((rc = solve_stage<double>(g, d, tol, max_iter, o, p, o.warm_start ? x : nullptr, x, flags,
-                                  fused, trace, false, &it, &r)))
+                                  form, trace, false, &it, &r)))
       return rc;
     if (scaled) {
       hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const double *)x,
@@ -1107,7 +1233,7 @@ extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const p
     const double tol32 = o.fp32_tol > 0.0 ? o.fp32_tol : std::max(tol, 1e-7);
     const double rtol = o.refine_tol < 0.0 ? tol : o.refine_tol;
     if ((rc = solve_stage<float>(g, d, tol32, max_iter, o, p, o.warm_start ? x : nullptr, g->x32,
-                                 flags, fused, trace, rtol > 0.0, &it, &r)))
+                                 flags, form, trace, rtol > 0.0, &it, &r)))
       return rc;
     target = rtol > 0.0 ? rtol : tol32;
     hipLaunchKernelGGL(k_to64<float>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
@@ -1115,7 +1241,7 @@ extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const p
     if (rtol > 0.0 && it < max_iter) {
       int it2 = 0;
       double r2 = INFINITY;
-      if ((rc = solve_stage<double>(g, d, rtol, max_iter - it, o, p, x, x, flags, fused,
+      if ((rc = solve_stage<double>(g, d, rtol, max_iter - it, o, p, x, x, flags, form,
                                     trace ? trace + it : nullptr, false, &it2, &r2)))
         return rc;
       if (scaled)
@@ -1150,6 +1276,7 @@ int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, doubl
     xs = g->x32;
   }
   if ((rc = ensure_contrib<T>(g))) return rc;
+  if (o.mode == PR_EDGE_LIST && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
   if ((rc = launch_init<T>(g, P, p, x, xs, -1.0, std::max(1, sweeps)))) return rc;
   const int flags = flags_of(o);
@@ -1160,7 +1287,7 @@ int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, doubl
     PR_HIP(hipEventCreate(&e1));
     PR_HIP(hipEventRecord(e0, g->work));
   }
-  if (sweeps > 0 && (rc = run_sweeps<T>(g, a, o.mode == PR_FUSED, o.use_hip_graph != 0, sweeps))) return rc;
+  if (sweeps > 0 && (rc = run_sweeps<T>(g, a, o.mode, o.use_hip_graph != 0, sweeps))) return rc;
   if (elapsed_ms) PR_HIP(hipEventRecord(e1, g->work));
   if (sizeof(T) != 8 || (flags & kFlagScaled))
     hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const T *)xs, x, g->n,
@@ -1209,6 +1336,7 @@ int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps,
     xs = g->x32;
   }
   if ((rc = ensure_contrib<T>(g))) return rc;
+  if (o.mode == PR_EDGE_LIST && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
   if ((rc = launch_init<T>(g, P, nullptr, x, xs, -1.0, sweeps))) return rc;
   SweepArgs<T> a = make_args<T>(g, P, nullptr, xs, d, flags_of(o), nullptr);
@@ -1216,7 +1344,7 @@ int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps,
   for (auto &e : ev) PR_HIP(hipEventCreate(&e));
   for (int k = 0; k < sweeps; ++k) {
     PR_HIP(hipEventRecord(ev[3 * k], g->work));
-    launch_marked<T>(g, a, o.mode == PR_FUSED, g->weighted, g->work, ev[3 * k + 1]);
+    launch_marked<T>(g, a, o.mode, g->weighted, g->work, ev[3 * k + 1]);
     PR_HIP(hipEventRecord(ev[3 * k + 2], g->work));
   }
   PR_HIP(hipGetLastError());

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib as L
 
-MODES = {"jacobi": L.PR_JACOBI, "fused": L.PR_FUSED}
+MODES = {"jacobi": L.PR_JACOBI, "fused": L.PR_FUSED, "edge_list": L.PR_EDGE_LIST}
 PRECISIONS = {"fp64": L.PR_FP64, "fp32": L.PR_FP32}
 DANGLING = {"uniform": L.PR_DANGLING_UNIFORM, "leak": L.PR_DANGLING_LEAK}
 NORMS = {"l1": L.PR_NORM_L1, "linf": L.PR_NORM_LINF}

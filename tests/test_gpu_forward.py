@@ -255,6 +255,43 @@ def test_fused_across_schedules():
         g.close()
 
 
+@pytest.mark.parametrize("plan", range(len(PLANS)))
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_edge_list_form_equals_jacobi_bits(case, plan):
+    """Algorithm 1 with the edge-ordered contributionList (scatter, then
+    contiguous row sums) adds the same values in the same order as the pull,
+    so its iterates are bit-identical to the Jacobi form's."""
+    name, n, src, dst, w, p = CASES[case]
+    say("case %s plan %d edge list" % (name, plan))
+    fpr = _fpr()
+    _, xr = _ref(n, src, dst, w, p)
+    g = fpr.Graph(n, src, dst, w, plan=dict(PLANS[plan] or {}, with_cl=1))
+    for prec in ("fp64", "fp32"):
+        xa, ia, ra, oka = g.solve(d=D, tol=1e-12, max_iter=3000, mode="jacobi", precision=prec, p=_p_dev(p))
+        xb, ib, rb, okb = g.solve(d=D, tol=1e-12, max_iter=3000, mode="edge_list", precision=prec, p=_p_dev(p))
+        assert oka and okb and ia == ib and ra == rb, (prec, ia, ib, ra, rb)
+        assert torch.equal(xa, xb), prec
+        assert l1(xb.cpu().numpy(), xr) <= 1e-9
+    # a fixed number of sweeps through pr_iterate, both precisions
+    for prec in ("fp64", "fp32"):
+        x0 = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+        x1 = x0.clone()
+        g.iterate(x0, 5, d=D, mode="jacobi", precision=prec, p=_p_dev(p))
+        g.iterate(x1, 5, d=D, mode="edge_list", precision=prec, p=_p_dev(p))
+        assert torch.equal(x0, x1), prec
+    g.close()
+
+
+def test_edge_list_form_needs_its_plan():
+    fpr = _fpr()
+    from paper_2203_09284_amd._lib import FusedPRError
+    s, t = gg.cycle(10)
+    g = fpr.Graph(10, s, t)
+    with pytest.raises(FusedPRError):
+        g.solve(mode="edge_list")
+    g.close()
+
+
 def test_gauss_seidel_blocks_cut_sweeps():
     """Block Gauss-Seidel over out-degree-ordered blocks needs fewer sweeps than
     Jacobi (Stein-Rosenberg for the regular splitting; soft check), and every
