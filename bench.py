@@ -18,6 +18,7 @@ The same JSON line carries, on the same GPU:
               against 64 sequential plain FP64 single-seed solves;
   er10k       directed Erdos-Renyi n=10,000, m=80,000, plain FP64, tol 1e-10;
   adjoint     weighted R-MAT scale 18: forward solve + adjoint + gradients;
+  road8m      a road-network-shaped street grid (8.4 M vertices, degree ~2.8);
   rmat24      R-MAT scale 24 in BFS order: FP32 fused + FP64 refinement
               against plain FP64 Jacobi, with the FP32 sweep's roofline;
   roofline    of the dominant kernel (the fused FP64 sweep at scale 20);
@@ -27,7 +28,9 @@ The same JSON line carries, on the same GPU:
     python bench.py --profile FORM [--workload rmat20|rmat24]   (kernel-only driver
         for rocprofv3: sweeps of one form, then a reference copy kernel)
     python bench.py --pmc-summary KEY FETCH_CSV WRITE_CSV DRIVER_LOG  (counter runs of
-        that driver -> HBM bytes per sweep launch, into profiles/traffic.json)
+        that driver -> HBM bytes per sweep, into profiles/traffic.json)
+    python bench.py --study [WORKLOAD ...]   (convergence study: thresholds 1e-6..1e-15,
+        L1 and max-norm stop rules, fused vs Jacobi distance, residual traces)
 """
 from __future__ import annotations
 
@@ -73,6 +76,10 @@ def workload(name):
     elif name == "rmat24":
         w = gg.rmat24_bfs()
         w.update(tol=1e-8, desc="R-MAT scale 24, edge factor 16, a=.57 b=c=.19, seed 5, BFS order")
+    elif name == "road8m":
+        w = gg.road8m()
+        w.update(tol=1e-8, desc="2896 x 2896 street grid, segments kept 0.75, one-way 0.1, seed 6, "
+                                "row-major ids")
     elif name == "rmat18w":
         w = gg.rmat18_weighted()
         w.update(tol=1e-12, desc="weighted R-MAT scale 18, weights U[0.5,1.5], seed 4")
@@ -225,6 +232,27 @@ def leg_adjoint(torch, fpr, oracle, steps, warmup, threads):
     return rounded(out)
 
 
+def leg_road(torch, fpr, steps, warmup):
+    """Road-network-shaped graph (low degree, no hubs, long diameter): the
+    regime where the paper reports its smallest gains."""
+    w = workload("road8m")
+    g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1))
+    n, m = g.n, g.m
+    forms = solve_legs(torch, g, m, 1e-8, steps, warmup,
+                       ["jacobi-fp64", "fused-fp64", "jacobi-fp32", "fused-fp32", "edge_list-fp64"])
+    kern = {name: sweep_kernel_us(g, *name.split("-"), sweeps=20) for name in ("jacobi-fp64", "fused-fp64")}
+    st = g.stats()
+    out = dict(workload="road8m", graph=w["desc"], n=n, m=m, tol=1e-8, gs_blocks=st["gs_blocks"],
+               forms={k: rounded(v) for k, v in forms.items()},
+               kernel_us={k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
+               alg_gbs_jacobi_fp64=sig(b_alg(n, m, 8) / (kern["jacobi-fp64"][0] * 1e-6) / 1e9))
+    log("road8m: jacobi %.3f ms (%d), fused %.3f ms (%d), sweep %.1f us" %
+        (forms["jacobi-fp64"]["ms"], forms["jacobi-fp64"]["sweeps"], forms["fused-fp64"]["ms"],
+         forms["fused-fp64"]["sweeps"], kern["jacobi-fp64"][0]))
+    g.close()
+    return out
+
+
 def leg_rmat24(torch, fpr, steps, warmup):
     t0 = time.perf_counter()
     w = workload("rmat24")
@@ -276,6 +304,48 @@ def profile_driver(args):
                       "b_alg": b_alg(g.n, g.m, 8 if prec == "fp64" else 4),
                       "source_sha": kernel_source_sha()}), flush=True)
     g.close()
+
+
+def study(args):
+    """Convergence study (the paper's threshold sweep, Section 6.3, on the
+    synthetic stand-ins): for thresholds 1e-6 .. 1e-15, sweeps and time of the
+    Jacobi pull under the L1 and max-norm stop rules (Eq. 3 uses the max-norm),
+    of the fused form and of the edge-list form (L1), the L1 distance between
+    the fused and the Jacobi results at the same threshold (the paper compares
+    FusEd against the edge-centric baseline this way), the certificate bound of
+    each, and the per-sweep residuals of the 1e-15 solves."""
+    import torch
+    import paper_2203_09284_amd as fpr
+    torch.cuda.set_device(0)
+    out = {"study": "convergence", "d": D, "workloads": {}}
+    for name in args.study:
+        w = workload(name)
+        g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1))
+        rows = []
+        for e in range(6, 16):
+            tol = 10.0 ** (-e)
+            row = {"tol": tol}
+            xs = {}
+            for form, mode, norm in (("jacobi", "jacobi", "l1"), ("jacobi_linf", "jacobi", "linf"),
+                                     ("fused", "fused", "l1"), ("edge_list", "edge_list", "l1")):
+                kw = dict(d=D, tol=tol, max_iter=2000, mode=mode, norm=norm)
+                t_ms, (x, it, r, ok) = timed(torch, lambda: g.solve(**kw), 3, 1)
+                row[form] = {"sweeps": it, "ms": sig(t_ms), "converged": bool(ok),
+                             "certificate_bound": sig(g.certificate(x, d=D) / (1 - D))}
+                xs[form] = x.clone()
+            row["l1_fused_vs_jacobi"] = sig(float((xs["fused"] - xs["jacobi"]).abs().sum()))
+            row["l1_edge_list_vs_jacobi"] = float((xs["edge_list"] - xs["jacobi"]).abs().sum())
+            rows.append(row)
+            log("%s tol %.0e: jacobi %d (linf %d), fused %d, edge_list %d sweeps; |fused - jacobi|_1 %.2e" %
+                (name, tol, row["jacobi"]["sweeps"], row["jacobi_linf"]["sweeps"], row["fused"]["sweeps"],
+                 row["edge_list"]["sweeps"], row["l1_fused_vs_jacobi"]))
+        traces = {}
+        for mode in ("jacobi", "fused"):
+            _, it, _, _, tr = g.solve(d=D, tol=1e-15, max_iter=2000, mode=mode, trace=True)
+            traces[mode] = [sig(float(v), 4) for v in tr]
+        out["workloads"][name] = {"n": g.n, "m": g.m, "rows": rows, "residual_trace_1e-15": traces}
+        g.close()
+    print(json.dumps(out), flush=True)
 
 
 def pmc_summary(args):
@@ -334,7 +404,13 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=20)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("KEY", "FETCH_CSV", "WRITE_CSV", "DRIVER_LOG"))
+    ap.add_argument("--study", nargs="*", default=None, metavar="WORKLOAD",
+                    help="convergence study over thresholds 1e-6..1e-15 (default: er10k rmat20)")
     args = ap.parse_args()
+    if args.study is not None:
+        args.study = args.study or ["er10k", "rmat20"]
+        study(args)
+        return
     if args.pmc_summary:
         pmc_summary(args)
         return
@@ -379,7 +455,8 @@ def main():
     if not args.quick:
         for name, fn in (("batched", lambda: leg_batched(torch, fpr, g, n, m, args.steps)),
                          ("er10k", lambda: leg_er10k(torch, fpr, oracle, args.steps, args.warmup)),
-                         ("adjoint", lambda: leg_adjoint(torch, fpr, oracle, args.steps, args.warmup, cores))):
+                         ("adjoint", lambda: leg_adjoint(torch, fpr, oracle, args.steps, args.warmup, cores)),
+                         ("road8m", lambda: leg_road(torch, fpr, max(3, args.steps // 4), 1))):
             try:
                 extra[name] = fn()
             except Exception as e:  # reported, not fatal: the headline stands on its own

@@ -219,6 +219,38 @@ def rmat24_bfs():
 
 # ------------------------------------------------- small shaped graphs ---
 
+def road_grid(side: int, seed: int, keep: float = 0.75, one_way: float = 0.1):
+    """Road-network-shaped graph: a side x side street grid, vertex r * side + c
+    (row-major ids, so grid neighbours are near in id).  Each grid segment is
+    kept with probability `keep`; a kept segment is one-way with probability
+    `one_way` (direction chosen by a fair coin), else two-way.  Low degree (about
+    2.8 out-edges per vertex), no hubs, diameter about 2 * side.  Stream 1
+    draws three uniforms per candidate segment, right segments first, then down
+    segments, in vertex order."""
+    n = side * side
+    r, c = np.divmod(np.arange(n, dtype=np.int64), side)
+    right = np.nonzero(c + 1 < side)[0]
+    down = np.nonzero(r + 1 < side)[0]
+    a = np.concatenate([right, down])
+    b = np.concatenate([right + 1, down + side])
+    u = uniforms(seed, STREAM_EDGES, 3 * len(a))
+    kept = u[0::3] < keep
+    oneway = u[1::3] < one_way
+    fwd = u[2::3] < 0.5
+    a, b, oneway, fwd = a[kept], b[kept], oneway[kept], fwd[kept]
+    both = ~oneway
+    src = np.concatenate([a[both], b[both], np.where(fwd[oneway], a[oneway], b[oneway])])
+    dst = np.concatenate([b[both], a[both], np.where(fwd[oneway], b[oneway], a[oneway])])
+    return src.astype(np.int32), dst.astype(np.int32)
+
+
+def road8m():
+    """The road-network stand-in of the benchmark: a 2896 x 2896 grid (8.4 M
+    vertices), seed 6."""
+    src, dst = road_grid(2896, seed=6)
+    return dict(name="road8m", n=2896 * 2896, src=src, dst=dst)
+
+
 def cycle(n: int):
     s = np.arange(n, dtype=np.int32)
     return s, ((s + 1) % n).astype(np.int32)

@@ -41,6 +41,8 @@ def cases():
     out.append(("rmat14", 1 << 14, s, t, None, None))
     d = gg.er_10k()
     out.append(("er10k", d["n"], d["src"], d["dst"], None, None))
+    s, t = gg.road_grid(48, seed=16)
+    out.append(("road48", 48 * 48, s, t, None, None))
     return out
 
 

@@ -7,6 +7,8 @@ benchmark times (default plans, hipGraph sweeps):
   rmat18w    weighted R-MAT scale 18, adjoint of the sum over 1,024 targets
   rmat24     R-MAT scale 24 in BFS order, FP32 fused + FP64 refinement
              (sampled rows, certificate; the oracle cannot build this CSR quickly)
+  road8m     road-network-shaped 2896 x 2896 street grid, FP64 Jacobi / fused /
+             edge-list and FP32 fused, tol 1e-12 against the oracle
 """
 import numpy as np
 import pytest
@@ -160,4 +162,22 @@ def test_rmat24_bfs_fp32_fused_refined():
         contrib = float(np.sum(xh[lst] / out_deg[lst])) if len(lst) else 0.0
         fr = (1 - D) / n + D * (contrib + D_mass / n)
         assert abs(fr - xh[r]) <= 1e-5 * xh[r]
+    g.close()
+
+
+@pytest.mark.timeout(900)
+def test_road8m_forms():
+    fpr = _fpr()
+    w = gg.road8m()
+    n = w["n"]
+    og = oracle.csr(n, w["src"], w["dst"])
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=2000, threads=THREADS)
+    say("road8m")
+    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1))
+    for mode in ("jacobi", "fused", "edge_list"):
+        x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=2000, mode=mode)
+        say("  %s sweeps=%d" % (mode, it))
+        assert ok and l1(x.cpu().numpy(), xr) <= 1e-9, mode
+    x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=2000, mode="fused", precision="fp32")
+    assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
     g.close()

@@ -108,3 +108,29 @@ def test_sample_distinct_and_weights():
     assert w.min() >= 0.5 and w.max() < 1.5
     seeds = gg.ppr_seeds(1 << 20)
     assert len(set(seeds.tolist())) == 64
+
+
+def test_road_grid_shape():
+    side = 40
+    s, t = gg.road_grid(side, seed=6)
+    n = side * side
+    assert s.dtype == np.int32 and len(s) == len(t)
+    # every edge joins grid neighbours
+    rs, cs = np.divmod(s, side)
+    rt, ct = np.divmod(t, side)
+    assert np.all(np.abs(rs - rt) + np.abs(cs - ct) == 1)
+    # no repeated edge, out-degree at most 4
+    key = s.astype(np.int64) * n + t
+    assert len(np.unique(key)) == len(key)
+    assert np.bincount(s, minlength=n).max() <= 4
+    # segments: 2 * side * (side - 1) candidates; kept ~0.75, one-way ~0.1 of kept
+    und = np.unique(np.minimum(s, t).astype(np.int64) * n + np.maximum(s, t))
+    cand = 2 * side * (side - 1)
+    assert abs(len(und) / cand - 0.75) < 0.03
+    one_way = 2 * len(und) - len(s)
+    assert abs(one_way / len(und) - 0.1) < 0.03
+    # deterministic; another seed differs
+    s2, t2 = gg.road_grid(side, seed=6)
+    assert np.array_equal(s, s2) and np.array_equal(t, t2)
+    s3, _ = gg.road_grid(side, seed=7)
+    assert not (len(s3) == len(s) and np.array_equal(s3, s))
