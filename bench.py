@@ -281,6 +281,29 @@ def leg_rmat24(torch, fpr, steps, warmup):
     return out
 
 
+def host_scaling(oracle, og, tol, cores):
+    """The paper's host comparison (Section 6.3, its thread-scaling figure) on
+    this box: edge-centric Algorithm 1 (Seq-EC / Par-EC) against the fused loop
+    (Seq-FusEd / Par-FusEd, mass-scaled, in place and asynchronous across
+    threads), FP64, same graph and stop rule, for 1..cores threads."""
+    out = []
+    counts = [k for k in (1, 2, 4, 8, 12, 16, 20) if k <= cores]
+    for th in counts:
+        t0 = time.perf_counter()
+        _, it_ec, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=1000, threads=th)
+        t_ec = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        if th == 1:
+            _, it_f, _ = oracle.pagerank_fused(og, D, tol=tol, max_iter=1000, scaled=True)
+        else:
+            _, it_f, _ = oracle.pagerank_fused_par(og, D, tol=tol, max_iter=1000, scaled=True, threads=th)
+        t_f = time.perf_counter() - t0
+        out.append(dict(threads=th, ec_s=sig(t_ec, 4), ec_sweeps=it_ec, fused_s=sig(t_f, 4), fused_sweeps=it_f,
+                        fused_speedup_vs_ec=sig(t_ec / t_f, 4)))
+        log("host %2d threads: EC %.3f s (%d sweeps), FusEd %.3f s (%d sweeps)" % (th, t_ec, it_ec, t_f, it_f))
+    return out
+
+
 def profile_driver(args):
     """Kernel-only run for rocprofv3: `sweeps` sweeps of one form, launched one
     by one, then five reference copies of COPY_BYTES (read + write) through
@@ -481,6 +504,8 @@ def main():
                           "contributionList and offsetList, FP64, median of 3 runs of %.2f s on %d threads; "
                           "1 thread: %.2f s" % (tol, it_cpu, cpu_s, cores, one_s),
                    single_thread_gteps=sig(og.m * it1 / one_s / 1e9))
+        if not args.quick:
+            cpu["thread_scaling"] = host_scaling(oracle, og, tol, cores)
         log("cpu oracle: %.3f GTEPS on %d threads, %.3f on 1" % (cpu["value"], cores, cpu["single_thread_gteps"]))
     g.close()
     del og, w

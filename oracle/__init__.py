@@ -64,6 +64,9 @@ def _lib():
     lib.orc_fused_iterate.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint,
                                       cint, cint, vp, vp, vp]
     lib.orc_fused_iterate.restype = cint
+    lib.orc_fused_par_iterate.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint, cint, cint,
+                                          vp, vp]
+    lib.orc_fused_par_iterate.restype = cint
     lib.orc_apply_F.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, dbl, cint, vp, vp]
     lib.orc_apply_F.restype = cint
     lib.orc_apply_F_rows.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, vp, i64, vp, vp]
@@ -191,6 +194,26 @@ def pagerank_fused(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int 
         raise MemoryError("orc_fused_iterate")
     if trace:
         return x, it, float(res[0]), tr[:it]
+    return x, it, float(res[0])
+
+
+def pagerank_fused_par(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int = 1000, p=None,
+                       x0=None, dangling: str = "uniform", scaled: bool = True, threads: int = 1):
+    """The paper's parallel fused variant (Section 6.3) on `threads` host
+    threads, in place and asynchronous across threads; host timing only.
+    Returns (x, sweeps, residual)."""
+    x = np.full(g.n, 1.0 / g.n) if x0 is None else np.array(x0, np.float64, copy=True)
+    if x0 is None and p is not None:
+        x = np.array(p, np.float64, copy=True)
+    p = None if p is None else np.ascontiguousarray(p, np.float64)
+    res = np.zeros(1)
+    it = _lib().orc_fused_par_iterate(g.n, _p(g.in_ptr), _p(g.out_ptr), _p(g.out_w), _p(g.offset),
+                                      _p(g.out_deg), _p(p), d, tol, max_iter, DANGLING[dangling],
+                                      int(scaled), int(threads), _p(x), _p(res))
+    if it == -2:
+        raise ValueError("the mass-scaled variant needs uniform dangling")
+    if it < 0:
+        raise MemoryError("orc_fused_par_iterate")
     return x, it, float(res[0])
 
 

@@ -28,6 +28,7 @@
  *   orc_ec_iterate   Algorithm 1 (edge-centric Jacobi): phase 1 scatters
  *                    x_v / W_v into CL through offsetList, phase 2 sums each
  *                    vertex's contiguous CL slice and applies the update.
+ *   orc_fused_par_iterate the parallel variant (Section 6.3), host timing only.
  *   orc_fused_iterate Algorithm 2 (loop-fused): CL primed once, then one loop
  *                    that pulls, updates, and immediately scatters the new
  *                    contribution, in ascending vertex order (Seq-FusEd,
@@ -350,6 +351,86 @@ int orc_fused_iterate(int64_t n, const int64_t *in_ptr, const int32_t *in_src, c
       r = (norm == ORC_NORM_LINF) ? linf : l1;
     }
     if (trace) trace[it - 1] = r;
+    if (r < tol) break;
+  }
+  if (scaled) {
+    double S = 0.0;
+    for (int64_t v = 0; v < n; ++v) S += x[v];
+    for (int64_t v = 0; v < n; ++v) x[v] /= S;
+  }
+  *res = r;
+  free(CL); free(W);
+  return it;
+}
+
+/*
+ * Par-FusEd: the paper's parallel loop-fused variant (Section 6.3), for host
+ * timing only (never a parity reference).  The vertices are split statically
+ * over `threads` OpenMP threads; each thread runs the loop of Algorithm 2 over
+ * its range in ascending order, in place on the shared contributionList, so a
+ * thread reads whatever value another thread last wrote (relaxed atomic loads
+ * and stores: a value is old or new, never torn).  The dangling mass is taken
+ * at the start of each sweep; `scaled` selects the mass-scaled form described
+ * above.  With one thread and scaled = 1 it computes what orc_fused_iterate
+ * computes with scaled = 1.  L1 residual only.
+ */
+int orc_fused_par_iterate(int64_t n, const int64_t *in_ptr, const int64_t *out_ptr,
+                          const double *out_w, const int64_t *offset, const int32_t *out_deg,
+                          const double *p, double d, double tol, int max_iter, int dangling,
+                          int scaled, int threads, double *x, double *res) {
+  const int uniform = (dangling == ORC_DANGLING_UNIFORM);
+  if (scaled && !uniform) return -2;
+  int64_t mu = in_ptr[n];
+  double *CL = (double *)malloc(sizeof(double) * (size_t)(mu > 0 ? mu : 1));
+  double *W = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!CL || !W) { free(CL); free(W); return -1; }
+  out_weight_sums(n, out_ptr, out_w, out_deg, W);
+  const double inv_n = 1.0 / (double)n;
+  for (int64_t v = 0; v < n; ++v) {
+    if (W[v] == 0.0) continue;
+    double contribution = x[v] / W[v];
+    for (int64_t e = out_ptr[v]; e < out_ptr[v + 1]; ++e)
+      CL[offset[e]] = out_w ? contribution * out_w[e] : contribution;
+  }
+  int it = 0;
+  double r = INFINITY;
+  while (it < max_iter) {
+    const double D = uniform ? dangling_mass(n, x, W) : 0.0;
+    double S = 1.0;
+    if (scaled) {
+      S = 0.0;
+      for (int64_t v = 0; v < n; ++v) S += x[v];
+    }
+    double l1 = 0.0;
+#pragma omp parallel for schedule(static) num_threads(threads) reduction(+ : l1)
+    for (int64_t u = 0; u < n; ++u) {
+      const double prev = x[u];
+      double sum = 0.0;
+      for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) {
+        double c;
+        __atomic_load(&CL[e], &c, __ATOMIC_RELAXED);
+        sum += c;
+      }
+      const double pu = p ? p[u] : inv_n;
+      const double xn = (1.0 - d) * pu * S + d * (sum + D * inv_n);
+      if (W[u] != 0.0) {
+        const double contribution = xn / W[u];
+        for (int64_t e = out_ptr[u]; e < out_ptr[u + 1]; ++e) {
+          double c = out_w ? contribution * out_w[e] : contribution;
+          __atomic_store(&CL[offset[e]], &c, __ATOMIC_RELAXED);
+        }
+      }
+      x[u] = xn;
+      l1 += fabs(xn - prev);
+    }
+    ++it;
+    if (scaled) {
+      double S2 = 0.0;
+      for (int64_t v = 0; v < n; ++v) S2 += x[v];
+      r = (l1 + fabs(S2 - S)) / S;
+    } else {
+      r = l1;
+    }
     if (r < tol) break;
   }
   if (scaled) {

@@ -427,3 +427,21 @@ def test_pins_catch_planted_mistakes(mutation):
     finally:
         oracle.set_mutation(0)
     assert _pins_pass()
+
+
+def test_par_fused_host_variant():
+    """The host parallel fused variant (Section 6.3): one thread is exactly the
+    mass-scaled sequential loop; several threads reach the Jacobi fixed point,
+    which the dense solve pins."""
+    n = 300
+    s, t = gg.random_graph(n, 1800, 31)
+    og = oracle.csr(n, s, t)
+    x_dense = dense.solve(n, s, t, None, 0.85, None)
+    xs, its, _ = oracle.pagerank_fused(og, 0.85, tol=1e-14, max_iter=2000, scaled=True)
+    x1, it1, _ = oracle.pagerank_fused_par(og, 0.85, tol=1e-14, max_iter=2000, scaled=True, threads=1)
+    assert it1 == its and np.array_equal(x1, xs)
+    for th in (2, 4, 8):
+        for scaled in (True, False):
+            x, it, r = oracle.pagerank_fused_par(og, 0.85, tol=1e-14, max_iter=5000, scaled=scaled, threads=th)
+            assert r < 1e-14
+            assert np.abs(x - x_dense).sum() <= 1e-12
