@@ -80,6 +80,10 @@ def workload(name):
         w = gg.road8m()
         w.update(tol=1e-8, desc="2896 x 2896 street grid, segments kept 0.75, one-way 0.1, seed 6, "
                                 "row-major ids")
+    elif name in ("rmat21", "rmat22", "rmat23"):
+        sc = int(name[4:])
+        w = gg.rmat_permuted(sc, seed=sc)
+        w.update(tol=1e-8, desc="R-MAT scale %d, edge factor 16, a=.57 b=c=.19, seed %d, permuted ids" % (sc, sc))
     elif name == "rmat18w":
         w = gg.rmat18_weighted()
         w.update(tol=1e-12, desc="weighted R-MAT scale 18, weights U[0.5,1.5], seed 4")
@@ -167,13 +171,34 @@ def solve_legs(torch, g, m, tol, steps, warmup, names, x_ref=None):
     return forms
 
 
-def roofline(achieved_gbs, traffic, kernel, bytes_sweep, us_sweep, launches):
+def roofline(achieved_gbs, traffic, kernel, bytes_sweep, us_sweep, launches, edge_bytes=None):
     """`achieved` and `traffic` are per sweep: the sweep kernel's launches of one
-    sweep (one per Gauss-Seidel block in the fused form), timed together."""
-    return {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
-            "alg_bytes_per_sweep": bytes_sweep, "us_per_sweep": round(us_sweep, 2),
-            "launches_per_sweep": launches}
+    sweep (one per Gauss-Seidel block in the fused form), timed together.
+    `edge_bytes` is the pessimistic count that adds one value read per edge
+    gather to the algorithmic bytes."""
+    r = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+         "alg_bytes_per_sweep": bytes_sweep, "us_per_sweep": round(us_sweep, 2),
+         "launches_per_sweep": launches}
+    if edge_bytes is not None:
+        r["edge_bytes_per_sweep"] = edge_bytes
+        r["edge_gbs"] = round(edge_bytes / (us_sweep * 1e-6) / 1e9, 1)
+    if traffic is not None:
+        r["traffic_gbs"] = round(traffic / (us_sweep * 1e-6) / 1e9, 1)
+    return r
+
+
+def host_cpu():
+    """CPU model string and the number of logical CPUs the host shows."""
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
 
 
 # ----------------------------------------------------------------- legs --
@@ -253,6 +278,27 @@ def leg_road(torch, fpr, steps, warmup):
     return out
 
 
+def leg_scale(torch, fpr, name, steps, warmup):
+    """One of the intermediate R-MAT sizes the paper's synthetic set covers
+    (scales 21-23, Section 6.2), permuted ids: time to L1 < 1e-8 of the four
+    main forms and the sweep kernel's time per sweep."""
+    w = workload(name)
+    g = fpr.Graph(w["n"], w["src"], w["dst"])
+    n, m = g.n, g.m
+    del w
+    forms = solve_legs(torch, g, m, 1e-8, steps, warmup, ["jacobi-fp64", "fused-fp64", "jacobi-fp32", "fused-fp32"])
+    kern = {k: sweep_kernel_us(g, *k.split("-"), sweeps=20) for k in forms}
+    out = dict(workload=name, n=n, m=m, tol=1e-8, gs_blocks=g.stats()["gs_blocks"],
+               forms={k: rounded(v) for k, v in forms.items()},
+               kernel_us={k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
+               alg_gbs={k: sig(b_alg(n, m, 8 if k.endswith("fp64") else 4) / (v[0] * 1e-6) / 1e9)
+                        for k, v in kern.items()},
+               speedup_vs_jacobi_fp64={k: sig(forms["jacobi-fp64"]["ms"] / f["ms"]) for k, f in forms.items()
+                                       if k != "jacobi-fp64"})
+    g.close()
+    return out
+
+
 def leg_rmat24(torch, fpr, steps, warmup):
     t0 = time.perf_counter()
     w = workload("rmat24")
@@ -275,7 +321,7 @@ def leg_rmat24(torch, fpr, steps, warmup):
                forms={k: rounded(v) for k, v in forms.items()},
                speedup_fused_fp32_vs_jacobi_fp64=sig(forms["jacobi-fp64"]["ms"] / forms["fused-fp32"]["ms"]),
                roofline=roofline(ach, traffic_record("fused_fp32_rmat24"), "k_sweep<float, fused>", b32, k32,
-                                 g.stats()["gs_blocks"]),
+                                 g.stats()["gs_blocks"], b32 + 4 * m),
                finalize_us=round(f32, 2), jacobi_fp64_sweep_kernel_us=round(k64, 2))
     g.close()
     return out
@@ -336,7 +382,8 @@ def study(args):
     of the fused form and of the edge-list form (L1), the L1 distance between
     the fused and the Jacobi results at the same threshold (the paper compares
     FusEd against the edge-centric baseline this way), the certificate bound of
-    each, and the per-sweep residuals of the 1e-15 solves."""
+    each, the per-sweep residuals of the 1e-15 solves, and the per-sweep L1 and
+    max-norm errors against the fixed point (the paper's error curves)."""
     import torch
     import paper_2203_09284_amd as fpr
     torch.cuda.set_device(0)
@@ -366,7 +413,21 @@ def study(args):
         for mode in ("jacobi", "fused"):
             _, it, _, _, tr = g.solve(d=D, tol=1e-15, max_iter=2000, mode=mode, trace=True)
             traces[mode] = [sig(float(v), 4) for v in tr]
-        out["workloads"][name] = {"n": g.n, "m": g.m, "rows": rows, "residual_trace_1e-15": traces}
+        # error curves: the iterate after each sweep against the fixed point
+        # solved to 1e-15, in L1 and max-norm (one sweep per call, from 1/n)
+        xstar = g.solve(d=D, tol=1e-15, max_iter=2000, mode="jacobi")[0]
+        errors = {}
+        for mode in ("jacobi", "fused"):
+            x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
+            e1, einf = [], []
+            for _ in range(len(traces[mode])):
+                g.iterate(x, 1, d=D, mode=mode)
+                diff = (x - xstar).abs()
+                e1.append(sig(float(diff.sum()), 4))
+                einf.append(sig(float(diff.max()), 4))
+            errors[mode] = {"l1": e1, "linf": einf}
+        out["workloads"][name] = {"n": g.n, "m": g.m, "rows": rows, "residual_trace_1e-15": traces,
+                                  "error_trace": errors}
         g.close()
     print(json.dumps(out), flush=True)
 
@@ -426,6 +487,8 @@ def main():
     ap.add_argument("--profile", default=None, help="{jacobi,fused,edge_list}-{fp64,fp32}")
     ap.add_argument("--profile-sweeps", type=int, default=20)
     ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--scales", nargs="*", type=int, default=None, metavar="SCALE",
+                    help="add the permuted R-MAT legs of these scales (21-23) to the line")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("KEY", "FETCH_CSV", "WRITE_CSV", "DRIVER_LOG"))
     ap.add_argument("--study", nargs="*", default=None, metavar="WORKLOAD",
                     help="convergence study over thresholds 1e-6..1e-15 (default: er10k rmat20)")
@@ -504,11 +567,20 @@ def main():
                           "contributionList and offsetList, FP64, median of 3 runs of %.2f s on %d threads; "
                           "1 thread: %.2f s" % (tol, it_cpu, cpu_s, cores, one_s),
                    single_thread_gteps=sig(og.m * it1 / one_s / 1e9))
+        cpu["cpu_model"], cpu["nproc"] = host_cpu()
         if not args.quick:
             cpu["thread_scaling"] = host_scaling(oracle, og, tol, cores)
         log("cpu oracle: %.3f GTEPS on %d threads, %.3f on 1" % (cpu["value"], cores, cpu["single_thread_gteps"]))
     g.close()
     del og, w
+
+    for sc in args.scales or []:
+        name = "rmat%d" % sc
+        try:
+            extra[name] = leg_scale(torch, fpr, name, max(3, args.steps // 4), 1)
+        except Exception as e:
+            extra[name] = dict(error=str(e)[:300])
+            log("%s leg failed: %s" % (name, e))
 
     if not args.quick and not args.no_rmat24:
         try:
@@ -536,7 +608,7 @@ def main():
         "config": {"workload": "rmat20", "graph": w_desc("rmat20"), "n": n, "m": m, "d": D, "tol": tol,
                    "form": "fused-fp64", "step": "one solve from 1/n to L1<tol"},
         "roofline": roofline(achieved, traffic_record("fused_fp64_rmat20"), "k_sweep<double, fused>",
-                             bytes_sweep, k_fused, st["gs_blocks"]),
+                             bytes_sweep, k_fused, st["gs_blocks"], bytes_sweep + 8 * m),
         "cpu_baseline": cpu,
         "forms": {k: rounded(f) for k, f in forms.items()},
         "kernel_us": {k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
