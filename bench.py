@@ -142,9 +142,10 @@ def timed(torch, fn, steps, warmup):
 
 
 def sweep_kernel_us(g, mode, precision="fp64", sweeps=50, reps=3):
-    """Average device time of one launch of the sweep kernel and of its finalize
-    kernel, in microseconds: HIP events recorded by the library on its own work
-    stream around each kernel (pr_profile_sweeps), best of `reps` runs."""
+    """Average device time per sweep of the sweep kernel (all of its launches in
+    one sweep) and of its finalize kernel, in microseconds: HIP events recorded
+    by the library on its own work stream around them (pr_profile_sweeps), best
+    of `reps` runs."""
     best = None
     for _ in range(reps):
         ks, kf = g.profile_sweeps(sweeps, d=D, mode=mode, precision=precision)
@@ -534,7 +535,7 @@ def main():
     kern = {name: sweep_kernel_us(g, *name.split("-")) for name in
             ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32", "edge_list-fp64")}
     for name, (ks, kf) in kern.items():
-        log("%-12s sweep kernel %.1f us + finalize %.1f us per launch" % (name, ks, kf))
+        log("%-12s sweep kernel %.1f us + finalize %.1f us per sweep" % (name, ks, kf))
     k_fused = kern["fused-fp64"][0]
 
     extra = {}

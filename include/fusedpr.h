@@ -230,7 +230,11 @@ int pr_iterate(pr_graph *g, double d, const pr_opts *o, const double *p, double 
  * and on return, as pr_iterate; teleport 1/n), launched one by one on the
  * library's work stream with HIP events recorded before the sweep kernel,
  * between it and its reduction (finalize) kernel, and after the latter.
- *   sweep_ms, finalize_ms   host: average milliseconds per launch of each
+ *   sweep_ms, finalize_ms   host: average milliseconds per sweep of each; the
+ *                           sweep kernel's time covers all of its launches in
+ *                           one sweep (one per Gauss-Seidel block in the fused
+ *                           form; the scatter and the list sums in the
+ *                           edge-list form)
  * Measurement support for the sweep of the recurrence above; 1 <= sweeps <= 4096. */
 int pr_profile_sweeps(pr_graph *g, double d, const pr_opts *o, double *x, int sweeps, double *sweep_ms,
                       double *finalize_ms, void *stream);

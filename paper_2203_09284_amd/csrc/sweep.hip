@@ -589,18 +589,25 @@ void k_sweep(SweepArgs<T> a) {
   const SweepState *st = a.st;
   if (st->done) return;
   const Ctx<T> C = make_ctx<T, FUSED>(a, st);
-  if constexpr (!CL) load_hot<T, FUSED>(C, hot);
-  __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kSweepWaves + wave));
+  // the first block's list length and first item record are loaded while the
+  // hot set is staged
+  int base = a.block_pos[a.blk_lo];
+  int cnt = a.wave_cnt[(size_t)a.blk_lo * a.n_waves + gw];
+  int4 next = cnt > 0 ? a.items[base + gw] : make_int4(kZero, 0, 0, 0);
+  if constexpr (!CL) load_hot<T, FUSED>(C, hot);
+  __syncthreads();
   Red red;
   int par = 0;
   double *rowsum = rowsum_all[wave];
   for (int b = a.blk_lo; b < a.blk_hi; ++b) {
-    const int base = a.block_pos[b];
-    const int cnt = a.wave_cnt[(size_t)b * a.n_waves + gw];
+    if (b != a.blk_lo) {
+      base = a.block_pos[b];
+      cnt = a.wave_cnt[(size_t)b * a.n_waves + gw];
+      next = cnt > 0 ? a.items[base + gw] : make_int4(kZero, 0, 0, 0);
+    }
     // the next item's record is loaded while the current one runs
-    int4 next = cnt > 0 ? a.items[base + gw] : make_int4(kZero, 0, 0, 0);
     for (int k = 0; k < cnt; ++k) {
       const int4 wi = next;
       if (k + 1 < cnt) next = a.items[base + (k + 1) * a.n_waves + gw];
@@ -661,11 +668,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(ScatterArgs<T> a) {
 }
 
 // The hubs split into chunk items: each adds its chunk sums in chunk order and
-// is updated (one thread per hub, chunk loads batched).
+// is updated (one thread per hub, chunk loads batched; `first` is the record
+// of the thread's first hub, loaded ahead).
 template <typename T, bool FUSED>
-__device__ __forceinline__ void finish_split_hubs(const Ctx<T> &C, const SweepArgs<T> &a, Red &red) {
+__device__ __forceinline__ void finish_split_hubs(const Ctx<T> &C, const SweepArgs<T> &a, int4 first, Red &red) {
   for (int h = threadIdx.x; h < a.n_msplit; h += kFinBlock) {
-    const int4 hs = a.msplit[h];
+    const int4 hs = h == (int)threadIdx.x ? first : a.msplit[h];
     const uint32_t u = C.rows[hs.x];
     const uint32_t slot = C.rowpos[hs.x];
     const double xo = (double)C.x[u];
@@ -690,16 +698,13 @@ template <typename T, bool FUSED>
 __global__ __launch_bounds__(kFinBlock) void k_finalize(SweepArgs<T> a) {
   __shared__ double s_red[3][kFinBlock / 64];
   SweepState *st = a.st;
-  if (st->done) return;
-  const Ctx<T> C = make_ctx<T, FUSED>(a, st);
-  const double S_old = st->S;
   const bool linf = (a.flags & kFlagLinf) != 0;
-  Red red;
-  finish_split_hubs<T, FUSED>(C, a, red);
   const int n = a.n_part;
   const size_t ps = (size_t)a.part_stride;
-  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kFinBlock) {
-    double c[8], dg[8], tt[8];
+  // the first batch of partials and the first split hub's record are loaded
+  // together with the state: none depends on the others
+  double c[8], dg[8], tt[8];
+  auto load = [&](int i0) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int i = i0 + k * kFinBlock;
@@ -708,6 +713,15 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(SweepArgs<T> a) {
       dg[k] = ok ? a.wave_part[ps + i] : 0.0;
       tt[k] = ok ? a.wave_part[2 * ps + i] : 0.0;
     }
+  };
+  load(threadIdx.x);
+  const int4 hub0 = (int)threadIdx.x < a.n_msplit ? a.msplit[threadIdx.x] : make_int4(0, 0, 0, 0);
+  if (st->done) return;
+  const Ctx<T> C = make_ctx<T, FUSED>(a, st);
+  const double S_old = st->S;
+  Red red;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kFinBlock) {
+    if (i0 != (int)threadIdx.x) load(i0);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       red.chg = linf ? fmax(red.chg, c[k]) : red.chg + c[k];
@@ -715,6 +729,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(SweepArgs<T> a) {
       red.tot += tt[k];
     }
   }
+  finish_split_hubs<T, FUSED>(C, a, hub0, red);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double chg = linf ? wave_max(red.chg) : wave_sum(red.chg);
   double dang = wave_sum(red.dang);
@@ -1100,8 +1115,11 @@ int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &
     const int cnt = std::min(G, max_iter - done_sweeps);
     if ((rc = run_sweeps<T>(g, a, form, o.use_hip_graph != 0, cnt))) return rc;
     if ((rc = poll_state(g, P))) return rc;
+    const int before = done_sweeps;
     done_sweeps = g->host_st->iter;
     if (g->host_st->done || done_sweeps >= max_iter) break;
+    if (done_sweeps != before + cnt)
+      return pr_fail(PR_EDEVICE, "internal: %d sweeps completed after %d + %d launched", done_sweeps, before, cnt);
     const double r = g->host_st->resid;
     if (!(r == r)) return pr_fail(PR_EDEVICE, "residual is NaN after sweep %d", done_sweeps);
     if (stall && r >= 0.5 * prev) break;
@@ -1431,8 +1449,11 @@ extern "C" int pr_adjoint(pr_graph *g, double d, const double *x, const double *
     launch_sweeps(g, a, false, g->weighted, cnt, g->work);
     PR_HIP(hipGetLastError());
     if ((rc = poll_state(g, P))) return rc;
+    const int before = done_sweeps;
     done_sweeps = g->host_st->iter;
     if (g->host_st->done || done_sweeps >= max_iter) break;
+    if (done_sweeps != before + cnt)
+      return pr_fail(PR_EDEVICE, "internal: %d sweeps completed after %d + %d launched", done_sweeps, before, cnt);
     if (!(g->host_st->resid == g->host_st->resid)) return pr_fail(PR_EDEVICE, "adjoint residual is NaN");
   }
   if ((rc = fpr_adjoint_gradients(g, d, x, lam, dLdp, dLdw, g->work))) return rc;

@@ -196,8 +196,9 @@ class Graph:
 
     def profile_sweeps(self, sweeps: int, d: float = 0.85, mode: str = "jacobi", precision: str = "fp64",
                        fused_scaled: bool = True, stream=None):
-        """pr_profile_sweeps from x = 1/n: average device milliseconds per launch of
-        the sweep kernel and of its finalize kernel, (sweep_ms, finalize_ms)."""
+        """pr_profile_sweeps from x = 1/n: average device milliseconds per sweep of
+        the sweep kernel (all of its launches in that sweep) and of its finalize
+        kernel, (sweep_ms, finalize_ms)."""
         o = self._opts(mode, precision, "uniform", "l1", True, fused_scaled, None, False, None, None, None)
         x = torch.full((self.n,), 1.0 / self.n, dtype=torch.float64, device=self.device)
         a = ctypes.c_double(0.0)
