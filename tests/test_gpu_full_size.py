@@ -9,6 +9,8 @@ benchmark times (default plans, hipGraph sweeps):
              (sampled rows, certificate; the oracle cannot build this CSR quickly)
   road8m     road-network-shaped 2896 x 2896 street grid, FP64 Jacobi / fused /
              edge-list and FP32 fused, tol 1e-12 against the oracle
+  rmat21     R-MAT scale 21 (permuted ids, the smallest of the intermediate
+             sizes), FP64 and FP32 Jacobi / fused against the oracle
 """
 import numpy as np
 import pytest
@@ -180,4 +182,23 @@ def test_road8m_forms():
         assert ok and l1(x.cpu().numpy(), xr) <= 1e-9, mode
     x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=2000, mode="fused", precision="fp32")
     assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
+    g.close()
+
+
+@pytest.mark.timeout(900)
+def test_rmat21_forms():
+    fpr = _fpr()
+    w = gg.rmat_permuted(21, seed=21)
+    n = w["n"]
+    og = oracle.csr(n, w["src"], w["dst"])
+    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=1000, threads=THREADS)
+    say("rmat21")
+    g = fpr.Graph(n, w["src"], w["dst"])
+    assert g.m == og.m
+    for mode in ("jacobi", "fused"):
+        for prec in ("fp64", "fp32"):
+            x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=1000, mode=mode, precision=prec)
+            err = l1(x.cpu().numpy(), xr)
+            say("  %s %s sweeps=%d L1=%.2e" % (mode, prec, it, err))
+            assert ok and err <= 1e-9, (mode, prec)
     g.close()
