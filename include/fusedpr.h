@@ -124,7 +124,8 @@ typedef struct pr_plan_opts {
   int tile_rows;         /* rows per tile at most (1..128, default 128) */
   int steps;             /* one-wavefront rows per work item (default 1) */
   int hot_slots;         /* gather slots staged in LDS per sweep workgroup (-1 = as many as fit,
-                            0 = none) */
+                            0 = none); the batched sweep stages at most 3072 of its four-column
+                            slots */
   int gather_layout;     /* order of the gathered array: 1 (default) sorted by gather count, the
                             hottest vertices first; 0 vertex-id order; 2 the most gathered
                             vertices (as many as the LDS copy holds in FP32) first, the rest in

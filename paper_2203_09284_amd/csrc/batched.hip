@@ -9,6 +9,11 @@
 // wavefront per long row, chunked hubs completed by the finalize kernel, rows
 // without in-edges), applied to four columns at once.
 //
+// Each workgroup copies the first `hot` gather slots (the most gathered
+// vertices) of its pass into LDS before the sweep; a gather below that slot
+// reads the copy.  The copy holds the values the sweep would load, so the
+// results do not depend on its size.
+//
 // Ranks and contributions are FP32 (sums with Neumaier compensation per
 // column, TwoSum when lanes combine); per-column residuals and dangling mass
 // are FP64.  A column whose L1 residual drops below tol is frozen: its values
@@ -34,6 +39,11 @@ constexpr int kBC = 4;           // columns per pass
 constexpr int kBBlock = 512;     // threads per workgroup
 constexpr int kBWaves = kBBlock / 64;
 constexpr int kBFin = 256;       // threads of the finalize kernel
+#ifndef FPR_BATCHED_HOT
+#define FPR_BATCHED_HOT 3072
+#endif
+constexpr int kBHot = FPR_BATCHED_HOT;  // float4 gather slots staged in LDS (16 bytes each)
+static_assert(kBHot % kBBlock == 0, "the LDS copy is loaded in whole rounds of the workgroup");
 
 struct BState {
   double D[kBC];      // dangling mass per column of the current iterate
@@ -74,6 +84,7 @@ struct BArgs {
   int n_chunks;
   int n_waves;
   int chunk;
+  int hot;  // gather slots staged in LDS (<= kBHot)
 };
 
 struct Col4 {
@@ -138,6 +149,40 @@ __device__ __forceinline__ BCtx make_bctx(const BArgs &a, int pass) {
   return C;
 }
 
+// The global load goes through an explicit global address-space pointer so
+// that it is not merged with the LDS read into one flat load.
+typedef float f4v __attribute__((ext_vector_type(4)));
+using gptr4 = const __attribute__((address_space(1))) f4v *;
+
+__device__ __forceinline__ float4 bgather(const BCtx &C, const float4 *hot, int32_t s) {
+  const bool h = s < C.a->hot;
+  const float4 vh = hot[h ? s : 0];
+  float4 vg = vh;
+  if (!h) {
+    const f4v t = ((gptr4)C.cin)[s];
+    vg = make_float4(t.x, t.y, t.z, t.w);
+  }
+  return vg;
+}
+
+// Copy of the pass's gather slots [0, hot) into LDS, all loads issued before
+// the first LDS write.
+__device__ __forceinline__ void bload_hot(const BCtx &C, float4 *hot) {
+  constexpr int kPer = kBHot / kBBlock;
+  const int H = C.a->hot;
+  float4 buf[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int q = (int)threadIdx.x + k * kBBlock;
+    buf[k] = q < H ? C.cin[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int q = (int)threadIdx.x + k * kBBlock;
+    if (q < H) hot[q] = buf[k];
+  }
+}
+
 __device__ __forceinline__ float comp(const float4 &v, int c) {
   return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
 }
@@ -172,7 +217,8 @@ __device__ __forceinline__ void bupdate(const BCtx &C, int i, const double *s, B
 
 // Tile of short rows (see the single-vector sweep): lane l takes edges
 // 8l..8l+7, a segmented scan across lanes completes rows; four columns at once.
-__device__ __forceinline__ void btile(const BCtx &C, double (*rowsum)[kBC], int t, BRed &red) {
+__device__ __forceinline__ void btile(const BCtx &C, const float4 *hot, double (*rowsum)[kBC], int t,
+                                      BRed &red) {
   const BArgs &a = *C.a;
   const int lane = threadIdx.x & 63;
   const int4 d = a.tiles[t];
@@ -185,7 +231,7 @@ __device__ __forceinline__ void btile(const BCtx &C, double (*rowsum)[kBC], int 
   float4 v[kBatch];
 #pragma unroll
   for (int k = 0; k < kBatch; ++k) {
-    v[k] = C.cin[s[k]];
+    v[k] = bgather(C, hot, s[k]);
     if (lane * kBatch + k >= ne) v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   const int pc = __popc(fl);
@@ -245,7 +291,7 @@ __device__ __forceinline__ void btile(const BCtx &C, double (*rowsum)[kBC], int 
 }
 
 // Edges [e0, e0 + L) summed by the whole wavefront (lanes stride the list).
-__device__ __forceinline__ void bstride(const BCtx &C, uint32_t e0, int L, double *out) {
+__device__ __forceinline__ void bstride(const BCtx &C, const float4 *hot, uint32_t e0, int L, double *out) {
   const BArgs &a = *C.a;
   const int lane = threadIdx.x & 63;
   Col4 acc;
@@ -255,7 +301,7 @@ __device__ __forceinline__ void bstride(const BCtx &C, uint32_t e0, int L, doubl
     for (int b = 0; b < kBatch; ++b) s[b] = j0 + 64 * b < L ? a.idx[e0 + j0 + 64 * b] : 0;
     float4 v[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) v[b] = C.cin[s[b]];
+    for (int b = 0; b < kBatch; ++b) v[b] = bgather(C, hot, s[b]);
 #pragma unroll
     for (int b = 0; b < kBatch; ++b)
       if (j0 + 64 * b < L) acc.add(v[b]);
@@ -266,10 +312,13 @@ __device__ __forceinline__ void bstride(const BCtx &C, uint32_t e0, int L, doubl
 }
 
 __global__ __launch_bounds__(kBBlock) void k_bsweep(BArgs a) {
+  __shared__ __align__(16) float4 hot[kBHot];
   __shared__ double rowsum_all[kBWaves][kTileRows][kBC];
   const int pass = blockIdx.y;
   if (a.st[pass].all_done) return;
   const BCtx C = make_bctx(a, pass);
+  bload_hot(C, hot);
+  __syncthreads();
   const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kBWaves + (threadIdx.x >> 6)));
   const int lane = threadIdx.x & 63;
   double(*rowsum)[kBC] = rowsum_all[threadIdx.x >> 6];
@@ -277,12 +326,12 @@ __global__ __launch_bounds__(kBBlock) void k_bsweep(BArgs a) {
   for (int item = gw; item < a.n_items; item += a.n_waves) {
     const int4 wi = a.items[item];
     if (wi.x == kTile) {
-      btile(C, rowsum, wi.y, red);
+      btile(C, hot, rowsum, wi.y, red);
     } else if (wi.x == kRows) {
       for (int r = wi.y; r < wi.z; ++r) {
         double s[kBC];
         const uint32_t e0 = a.rptr[r];
-        bstride(C, e0, (int)(a.rptr[r + 1] - e0), s);
+        bstride(C, hot, e0, (int)(a.rptr[r + 1] - e0), s);
         if (lane == 0) bupdate(C, r, s, red);
       }
     } else if (wi.x == kHeavy) {
@@ -290,7 +339,7 @@ __global__ __launch_bounds__(kBBlock) void k_bsweep(BArgs a) {
       const uint32_t rb = a.rptr[wi.y];
       const int L = (int)(a.rptr[wi.y + 1] - rb);
       const int ne = min(a.chunk, L - wi.z * a.chunk);
-      bstride(C, rb + (uint32_t)wi.z * (uint32_t)a.chunk, ne, s);
+      bstride(C, hot, rb + (uint32_t)wi.z * (uint32_t)a.chunk, ne, s);
       if (lane == 0) {
         double *hp = a.hpart + ((size_t)pass * a.n_chunks + wi.w + wi.z) * kBC;
 #pragma unroll
@@ -538,6 +587,8 @@ BArgs make_bargs(pr_graph *g, BWork &w, double d, int passes, int pass0) {
   a.n_chunks = std::max(1, P.n_chunks);
   a.n_waves = P.n_waves;
   a.chunk = P.chunk;
+  const int64_t hot = g->popts.hot_slots < 0 ? kBHot : std::min<int64_t>(g->popts.hot_slots, kBHot);
+  a.hot = (int)std::min<int64_t>(hot, g->n);
   (void)passes;
   return a;
 }

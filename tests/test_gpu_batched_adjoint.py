@@ -80,6 +80,29 @@ def test_batched_tile_widths_agree_and_linearity():
     g.close()
 
 
+def test_batched_lds_copy_does_not_change_bits():
+    """The LDS copy of the hottest slots holds the values the sweep would load,
+    so its size (none, a ragged few, 2048, the default 3072) leaves every bit
+    of the result unchanged; n = 8192 puts most slots outside it."""
+    fpr = _fpr()
+    n = 1 << 13
+    s, t = gg.rmat(13, 16, seed=7)
+    seeds = gg.sample_distinct(n, 24, 7, 4)
+    sd = torch.tensor(seeds, dtype=torch.int32, device="cuda")
+    outs = []
+    for hot in (0, 5, 2048, -1):
+        say("batched hot_slots=%d" % hot)
+        g = fpr.Graph(n, s, t, plan=dict(hot_slots=hot))
+        X, its, res = g.solve_batched(sd, d=D, tol=1e-6, tile=8)
+        outs.append((X.cpu().numpy(), its, res))
+        g.close()
+    for X, its, res in outs[1:]:
+        assert np.array_equal(X, outs[0][0]) and np.array_equal(its, outs[0][1])
+    og = oracle.csr(n, s, t)
+    for j in (0, 23):
+        assert l1(outs[-1][0][:, j].astype(np.float64), _ppr_ref(og, n, seeds[j])) <= 1e-5, j
+
+
 def test_batched_autotune_cache(tmp_path):
     fpr = _fpr()
     n = 1 << 11
