@@ -124,8 +124,7 @@ typedef struct pr_plan_opts {
   int tile_rows;         /* rows per tile at most (1..128, default 128) */
   int steps;             /* one-wavefront rows per work item (default 1) */
   int hot_slots;         /* gather slots staged in LDS per sweep workgroup (-1 = as many as fit,
-                            0 = none); the batched sweep stages at most 3072 of its four-column
-                            slots */
+                            0 = none) */
   int gather_layout;     /* order of the gathered array: 1 (default) sorted by gather count, the
                             hottest vertices first; 0 vertex-id order; 2 the most gathered
                             vertices (as many as the LDS copy holds in FP32) first, the rest in
@@ -256,9 +255,13 @@ int pr_certificate(pr_graph *g, double d, const double *p, const double *x, doub
  *   X       device float[n * k], row-major (vertex-major): X[v * k + j]
  *   iters   host int[k]: sweeps until column j froze (or max_iter)
  *   resid   host double[k]: last residual of each column
- *   tile    columns advanced per launch (a multiple of 4, at most 64; four
- *           columns share each gather); 0 = autotuned (pr_autotune_batched,
- *           cache file from the FUSEDPR_TUNE_CACHE environment variable)
+ *   tile    columns advanced per launch (a multiple of 4, at most 64); 0 =
+ *           autotuned (pr_autotune_batched, cache file from the
+ *           FUSEDPR_TUNE_CACHE environment variable).  Inside a launch the
+ *           columns of a vertex form one contiguous row, read whole per
+ *           in-edge.  The results do not depend on the tile width.
+ * Stream order: runs on the graph's work stream after the work queued on
+ * `stream`, and returns once the results are in X, iters and resid.
  * ---------------------------------------------------------------------- */
 int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter, int k, const int32_t *seeds,
                      int tile, float *X, int *iters, double *resid, void *stream);

@@ -1,24 +1,28 @@
 // Batched personalized PageRank: k teleport vectors, one-hot on seeds[j],
-//     X[:, j] = (1-d) e_{seed_j} + d (P X[:, j])      (Eq. 1 with a personalised teleport),
+//     X[:, j] = (1-d) e_{seed_j} + d (P X[:, j] + D_j / n)   (Eq. 1 with a personalised teleport),
 // solved as one multi-column Jacobi pull per sweep.
 //
-// Columns are grouped four to a "pass" (a float4 per vertex), so one random
-// 16-byte gather serves four columns; a launch runs `tile`/4 passes side by
-// side (grid.y = pass), which is the autotuned tile width.  The work items are
-// the forward plan's (row tiles with a segmented scan across lanes, one
-// wavefront per long row, chunked hubs completed by the finalize kernel, rows
-// without in-edges), applied to four columns at once.
+// Layout.  A launch advances T columns (T a multiple of 4, at most 64: the
+// tile width).  Ranks and contributions are vertex-major: the T values of a
+// vertex are one row of 4T bytes (256 bytes at T = 64), so an in-edge costs
+// one row read, made by the 16 lanes of a lane group with 16-byte loads.  A
+// wavefront is four such groups; lane j of a group holds columns 4j..4j+3
+// (lanes with 4j >= T stay idle).
 //
-// Each workgroup copies the first `hot` gather slots (the most gathered
-// vertices) of its pass into LDS before the sweep; a gather below that slot
-// reads the copy.  The copy holds the values the sweep would load, so the
-// results do not depend on its size.
+// Work (the plan's batched list).  Short and empty rows come in runs; each
+// run is walked by one lane group, row by row, up to 8 gathers in flight per
+// lane.  A long row is one item: the four groups sum one quarter of its list
+// each.  A hub is split into `chunk`-edge items of the same kind, whose sums
+// the finalize kernel adds in chunk order.  None of this depends on T, and
+// every column is summed in the same order whatever the tile width, so the
+// results do not depend on it.
 //
-// Ranks and contributions are FP32 (sums with Neumaier compensation per
-// column, TwoSum when lanes combine); per-column residuals and dangling mass
-// are FP64.  A column whose L1 residual drops below tol is frozen: its values
-// stop changing and its sweep count is recorded; a pass ends when its four
-// columns are frozen, and the launch when every pass has ended.
+// Arithmetic.  Ranks and contributions are FP32; sums use Neumaier
+// compensation per lane and TwoSum when quarters combine (in quarter order).
+// Per-column residuals and dangling mass are FP64, reduced in a fixed order.
+// A column whose L1 residual drops below tol is frozen: its values stop
+// changing and its sweep count is recorded.  A launch's sweeps stop once all
+// its columns are frozen.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -35,521 +39,412 @@ using namespace fpr::dev;
 
 namespace {
 
-constexpr int kBC = 4;           // columns per pass
-constexpr int kBBlock = 512;     // threads per workgroup
-constexpr int kBWaves = kBBlock / 64;
-constexpr int kBFin = 256;       // threads of the finalize kernel
-#ifndef FPR_BATCHED_HOT
-#define FPR_BATCHED_HOT 3072
-#endif
-constexpr int kBHot = FPR_BATCHED_HOT;  // float4 gather slots staged in LDS (16 bytes each)
-static_assert(kBHot % kBBlock == 0, "the LDS copy is loaded in whole rounds of the workgroup");
+constexpr int kVBlock = 512;          // threads per workgroup of the sweep
+constexpr int kVWaves = kVBlock / 64;
+constexpr int kVGroup = 16;           // lanes per group: one 256-byte row of 64 columns
+constexpr int kVMaxT = 64;            // columns per launch at most
+constexpr int kVFin = 256;            // threads per workgroup of the finalize kernel (one per column)
 
-struct BState {
-  double D[kBC];      // dangling mass per column of the current iterate
-  double resid[kBC];  // last L1 change per column
-  int done[kBC];      // column frozen
-  int iters[kBC];     // sweeps until the column froze (or so far)
-  int iter;           // sweeps run in this pass
-  int all_done;       // every column frozen, or max_iter reached
+struct VState {
+  double D[kVMaxT];      // dangling mass per column of the current iterate
+  double resid[kVMaxT];  // last L1 change per column
+  int done[kVMaxT];      // column frozen
+  int iters[kVMaxT];     // sweeps until the column froze (or so far)
+  double tol;
   int max_iter;
   int pad;
-  double tol;
 };
 
-struct BArgs {
+struct VArgs {
   const uint32_t *rows;
   const uint32_t *rowpos;
   const uint32_t *rptr;
   const int32_t *idx;
   const int4 *items;
-  const int4 *tiles;
-  const int32_t *tidx;
-  const uint8_t *tmask;
+  const int2 *vrun;
   const int4 *hsplit;
   const uint32_t *gpos;
   const double *inv_w;
-  const int32_t *seeds;  // [passes * 4], -1 for padding columns
-  float4 *x;             // [passes][n] vertex order
-  float4 *c0;            // [passes][n] gather-layout order
+  const int32_t *seeds;  // [T], -1 for padding columns
+  float4 *x;             // [n][Q] vertex order
+  float4 *c0;            // [n][Q] gather-layout order
   float4 *c1;
-  double *hpart;         // [passes][n_chunks][4]
-  double *wave_part;     // [passes][2][4][n_waves]: change, dangling per column
-  BState *st;            // [passes]
+  double *hpart;         // [n_chunks][T]
+  double *wg_part;       // [2][T][n_wg]: change and dangling mass per column and workgroup
+  VState *st;
   double d;
   double inv_n;
   int64_t n;
   int n_items;
   int n_split;
-  int n_chunks;
-  int n_waves;
+  int n_wg;
   int chunk;
-  int hot;  // gather slots staged in LDS (<= kBHot)
+  int T;    // columns of this launch
+  int Q;    // T / 4: float4 per row
+  int par;  // sweep parity: 0 reads c0 and writes c1
 };
 
-struct Col4 {
-  LaneSum<float> v[kBC];
+struct Sum4 {
+  LaneSum<float> v[4];
   __device__ __forceinline__ void add(const float4 &a) {
     v[0].add(a.x);
     v[1].add(a.y);
     v[2].add(a.z);
     v[3].add(a.w);
   }
-  __device__ __forceinline__ Col4 shfl_up(int off) const {
-    Col4 r;
+  __device__ __forceinline__ void combine_with(const Sum4 &l) {
 #pragma unroll
-    for (int c = 0; c < kBC; ++c) r.v[c] = v[c].shfl_up(off);
+    for (int q = 0; q < 4; ++q) v[q].combine_with(l.v[q]);
+  }
+  // the sums held by lane `src` (every lane of the wavefront takes part)
+  __device__ __forceinline__ Sum4 from_lane(int src) const {
+    Sum4 r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r.v[q].s = __shfl(v[q].s, src, 64);
+      r.v[q].c = __shfl(v[q].c, src, 64);
+    }
     return r;
   }
-  __device__ __forceinline__ void add_before(const Col4 &e) {
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) v[c].add_before(e.v[c]);
-  }
-  __device__ __forceinline__ void combine_with(const Col4 &l) {
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) v[c].combine_with(l.v[c]);
-  }
-  __device__ __forceinline__ void group_reduce(int lanes) {
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) v[c].group_reduce(lanes);
-  }
 };
 
-struct BRed {
-  double chg[kBC] = {0.0, 0.0, 0.0, 0.0};
-  double dang[kBC] = {0.0, 0.0, 0.0, 0.0};
+struct VRed {
+  double chg[4] = {0.0, 0.0, 0.0, 0.0};
+  double dang[4] = {0.0, 0.0, 0.0, 0.0};
 };
 
-// Pass-local view: the pass index selects the columns and buffers.
-struct BCtx {
-  const BArgs *a;
+// Lane view of a launch: the lane's group, its columns and their state.
+struct VCtx {
   const float4 *cin;
   float4 *cout;
-  float4 *x;
-  double dterm[kBC];
-  int seed[kBC];
-  int done[kBC];
+  int g, j;
+  bool act;
+  bool frozen[4];
+  int seed[4];
+  double dterm[4];
 };
 
-__device__ __forceinline__ BCtx make_bctx(const BArgs &a, int pass) {
-  BCtx C;
-  C.a = &a;
-  const BState *st = a.st + pass;
-  const int it = st->iter;
-  const size_t off = (size_t)pass * a.n;
-  C.cin = ((it & 1) ? a.c1 : a.c0) + off;
-  C.cout = ((it & 1) ? a.c0 : a.c1) + off;
-  C.x = a.x + off;
+__device__ __forceinline__ VCtx make_vctx(const VArgs &a) {
+  VCtx C;
+  const int lane = threadIdx.x & 63;
+  C.g = lane / kVGroup;
+  C.j = lane % kVGroup;
+  C.act = C.j < a.Q;
+  C.cin = a.par ? a.c1 : a.c0;
+  C.cout = a.par ? a.c0 : a.c1;
 #pragma unroll
-  for (int c = 0; c < kBC; ++c) {
-    C.dterm[c] = st->D[c] * a.inv_n;
-    C.seed[c] = a.seeds[pass * kBC + c];
-    C.done[c] = st->done[c];
+  for (int q = 0; q < 4; ++q) {
+    const int col = 4 * C.j + q;
+    C.seed[q] = C.act ? a.seeds[col] : -1;
+    C.frozen[q] = !C.act || C.seed[q] < 0 || a.st->done[col] != 0;
+    C.dterm[q] = C.act ? a.st->D[col] * a.inv_n : 0.0;
   }
   return C;
 }
 
-// The global load goes through an explicit global address-space pointer so
-// that it is not merged with the LDS read into one flat load.
-typedef float f4v __attribute__((ext_vector_type(4)));
-using gptr4 = const __attribute__((address_space(1))) f4v *;
-
-__device__ __forceinline__ float4 bgather(const BCtx &C, const float4 *hot, int32_t s) {
-  const bool h = s < C.a->hot;
-  const float4 vh = hot[h ? s : 0];
-  float4 vg = vh;
-  if (!h) {
-    const f4v t = ((gptr4)C.cin)[s];
-    vg = make_float4(t.x, t.y, t.z, t.w);
-  }
-  return vg;
-}
-
-// Copy of the pass's gather slots [0, hot) into LDS, all loads issued before
-// the first LDS write.
-__device__ __forceinline__ void bload_hot(const BCtx &C, float4 *hot) {
-  constexpr int kPer = kBHot / kBBlock;
-  const int H = C.a->hot;
-  float4 buf[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int q = (int)threadIdx.x + k * kBBlock;
-    buf[k] = q < H ? C.cin[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int q = (int)threadIdx.x + k * kBBlock;
-    if (q < H) hot[q] = buf[k];
-  }
-}
-
-__device__ __forceinline__ float comp(const float4 &v, int c) {
-  return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
-}
-
-// Update of row-table entry i with column sums s[4]; frozen columns keep x.
-__device__ __forceinline__ void bupdate(const BCtx &C, int i, const double *s, BRed &red) {
-  const BArgs &a = *C.a;
-  const uint32_t u = a.rows[i];
-  const float4 xo = C.x[u];
-  const double iw = a.inv_w[u];
-  float xn[kBC];
-#pragma unroll
-  for (int c = 0; c < kBC; ++c) {
-    const float old = comp(xo, c);
-    if (C.done[c] || C.seed[c] < 0) {
-      xn[c] = old;
-    } else {
-      const double tele = ((int)u == C.seed[c]) ? (1.0 - a.d) : 0.0;
-      xn[c] = (float)(tele + a.d * (s[c] + C.dterm[c]));
-      red.chg[c] += fabs((double)xn[c] - (double)old);
-    }
-  }
-  C.x[u] = make_float4(xn[0], xn[1], xn[2], xn[3]);
-  if (iw != 0.0) {
-    C.cout[a.rowpos[i]] = make_float4((float)((double)xn[0] * iw), (float)((double)xn[1] * iw),
-                                      (float)((double)xn[2] * iw), (float)((double)xn[3] * iw));
-  } else {
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) red.dang[c] += (double)xn[c];
-  }
-}
-
-// Tile of short rows (see the single-vector sweep): lane l takes edges
-// 8l..8l+7, a segmented scan across lanes completes rows; four columns at once.
-__device__ __forceinline__ void btile(const BCtx &C, const float4 *hot, double (*rowsum)[kBC], int t,
-                                      BRed &red) {
-  const BArgs &a = *C.a;
-  const int lane = threadIdx.x & 63;
-  const int4 d = a.tiles[t];
-  const int r0 = d.x, nr = d.y, ne = d.z;
-  const size_t base = (size_t)t * kTileEdges;
-  int32_t s[kBatch];
-#pragma unroll
-  for (int k = 0; k < kBatch; ++k) s[k] = a.tidx[base + k * 64 + lane];
-  const uint32_t fl = a.tmask[(size_t)t * 64 + lane];
-  float4 v[kBatch];
-#pragma unroll
-  for (int k = 0; k < kBatch; ++k) {
-    v[k] = bgather(C, hot, s[k]);
-    if (lane * kBatch + k >= ne) v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  const int pc = __popc(fl);
-  int incl = pc;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int o = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += o;
-  }
-  const int rowbase = incl - pc;
-  Col4 cur, head;
-  bool seen = false;
-  int j = 0;
-#pragma unroll
-  for (int k = 0; k < kBatch; ++k) {
-    const bool st = (fl >> k) & 1u;
-    if (st && seen) {
-#pragma unroll
-      for (int c = 0; c < kBC; ++c) rowsum[rowbase + j - 1][c] = cur.v[c].value();
-    }
-    if (st && !seen) head = cur;
-    j += st ? 1 : 0;
-    seen = seen || st;
-    if (st) cur = Col4();
-    cur.add(v[k]);
-  }
-  if (!seen) head = cur;
-  Col4 sc = cur;
-  bool f = seen;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    Col4 prev = sc.shfl_up(off);
-    const bool pf = __shfl_up((int)f, off, 64) != 0;
-    if (lane >= off) {
-      if (!f) sc.add_before(prev);
-      f = f || pf;
-    }
-  }
-  Col4 carry = sc.shfl_up(1);
-  if (lane == 0) carry = Col4();
-  if (seen && lane > 0) {
-    carry.combine_with(head);
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) rowsum[rowbase - 1][c] = carry.v[c].value();
-  }
-  if (lane == ((ne - 1) >> 3)) {
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) rowsum[nr - 1][c] = sc.v[c].value();
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int r = lane; r < nr; r += 64) bupdate(C, r0 + r, rowsum[r], red);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Edges [e0, e0 + L) summed by the whole wavefront (lanes stride the list).
-__device__ __forceinline__ void bstride(const BCtx &C, const float4 *hot, uint32_t e0, int L, double *out) {
-  const BArgs &a = *C.a;
-  const int lane = threadIdx.x & 63;
-  Col4 acc;
-  for (int j0 = lane; j0 < L; j0 += kBatch * 64) {
+// Sum over the in-edges [e0, e1) in list order, up to 8 row reads in flight.
+__device__ __forceinline__ void range_sum(const VArgs &a, const VCtx &C, uint32_t e0, uint32_t e1, Sum4 &acc) {
+  for (uint32_t e = e0; e < e1; e += kBatch) {
+    const int cnt = (int)min((uint32_t)kBatch, e1 - e);
     int32_t s[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) s[b] = j0 + 64 * b < L ? a.idx[e0 + j0 + 64 * b] : 0;
+    for (int b = 0; b < kBatch; ++b) s[b] = b < cnt ? a.idx[e + b] : 0;
     float4 v[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) v[b] = bgather(C, hot, s[b]);
+    for (int b = 0; b < kBatch; ++b)
+      v[b] = (b < cnt && C.act) ? C.cin[(size_t)s[b] * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int b = 0; b < kBatch; ++b)
-      if (j0 + 64 * b < L) acc.add(v[b]);
+      if (b < cnt) acc.add(v[b]);
   }
-  acc.group_reduce(64);
-#pragma unroll
-  for (int c = 0; c < kBC; ++c) out[c] = acc.v[c].value();
 }
 
-__global__ __launch_bounds__(kBBlock) void k_bsweep(BArgs a) {
-  __shared__ __align__(16) float4 hot[kBHot];
-  __shared__ double rowsum_all[kBWaves][kTileRows][kBC];
-  const int pass = blockIdx.y;
-  if (a.st[pass].all_done) return;
-  const BCtx C = make_bctx(a, pass);
-  bload_hot(C, hot);
-  __syncthreads();
-  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kBWaves + (threadIdx.x >> 6)));
-  const int lane = threadIdx.x & 63;
-  double(*rowsum)[kBC] = rowsum_all[threadIdx.x >> 6];
-  BRed red;
-  for (int item = gw; item < a.n_items; item += a.n_waves) {
-    const int4 wi = a.items[item];
-    if (wi.x == kTile) {
-      btile(C, hot, rowsum, wi.y, red);
-    } else if (wi.x == kRows) {
-      for (int r = wi.y; r < wi.z; ++r) {
-        double s[kBC];
-        const uint32_t e0 = a.rptr[r];
-        bstride(C, hot, e0, (int)(a.rptr[r + 1] - e0), s);
-        if (lane == 0) bupdate(C, r, s, red);
-      }
-    } else if (wi.x == kHeavy) {
-      double s[kBC];
-      const uint32_t rb = a.rptr[wi.y];
-      const int L = (int)(a.rptr[wi.y + 1] - rb);
-      const int ne = min(a.chunk, L - wi.z * a.chunk);
-      bstride(C, hot, rb + (uint32_t)wi.z * (uint32_t)a.chunk, ne, s);
-      if (lane == 0) {
-        double *hp = a.hpart + ((size_t)pass * a.n_chunks + wi.w + wi.z) * kBC;
+__device__ __forceinline__ float comp(const float4 &v, int q) {
+  return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+}
+
+// Update of vertex u (gather slot `slot`, 1/W_u = iw, old row xo) from its
+// column sums s[4]; frozen columns keep their values.
+__device__ __forceinline__ void vupdate(const VArgs &a, const VCtx &C, uint32_t u, uint32_t slot, double iw,
+                                        const float4 &xo, const double *s, VRed &red) {
+  float xn[4];
 #pragma unroll
-        for (int c = 0; c < kBC; ++c) hp[c] = s[c];
-      }
+  for (int q = 0; q < 4; ++q) {
+    const float old = comp(xo, q);
+    if (C.frozen[q]) {
+      xn[q] = old;
     } else {
-      const double zero[kBC] = {0.0, 0.0, 0.0, 0.0};
-      for (int r = wi.y + lane; r < wi.z; r += 64) bupdate(C, r, zero, red);
+      const double tele = ((int)u == C.seed[q]) ? (1.0 - a.d) : 0.0;
+      xn[q] = (float)(tele + a.d * (s[q] + C.dterm[q]));
+      red.chg[q] += fabs((double)xn[q] - (double)old);
     }
   }
-  double *wp = a.wave_part + (size_t)pass * 2 * kBC * a.n_waves;
+  a.x[(size_t)u * a.Q + C.j] = make_float4(xn[0], xn[1], xn[2], xn[3]);
+  if (iw != 0.0) {
+    C.cout[(size_t)slot * a.Q + C.j] =
+        make_float4((float)((double)xn[0] * iw), (float)((double)xn[1] * iw), (float)((double)xn[2] * iw),
+                    (float)((double)xn[3] * iw));
+  } else {
 #pragma unroll
-  for (int c = 0; c < kBC; ++c) {
-    const double ch = wave_sum(red.chg[c]);
-    const double dg = wave_sum(red.dang[c]);
-    if (lane == 0) {
-      wp[(size_t)c * a.n_waves + gw] = ch;
-      wp[(size_t)(kBC + c) * a.n_waves + gw] = dg;
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBFin) void k_bfinal(BArgs a) {
-  __shared__ double s_red[2 * kBC][kBFin / 64];
-  const int pass = blockIdx.x;
-  BState *st = a.st + pass;
-  if (st->all_done) return;
-  const BCtx C = make_bctx(a, pass);
-  BRed red;
-  for (int h = threadIdx.x; h < a.n_split; h += kBFin) {
-    const int4 hs = a.hsplit[h];
-    double s[kBC] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < hs.z; ++k) {
-      const double *hp = a.hpart + ((size_t)pass * a.n_chunks + hs.y + k) * kBC;
-#pragma unroll
-      for (int c = 0; c < kBC; ++c) s[c] += hp[c];
-    }
-    bupdate(C, hs.x, s, red);
-  }
-  const double *wp = a.wave_part + (size_t)pass * 2 * kBC * a.n_waves;
-  for (int i = threadIdx.x; i < a.n_waves; i += kBFin) {
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) {
-      red.chg[c] += wp[(size_t)c * a.n_waves + i];
-      red.dang[c] += wp[(size_t)(kBC + c) * a.n_waves + i];
-    }
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int c = 0; c < kBC; ++c) {
-    const double ch = wave_sum(red.chg[c]);
-    const double dg = wave_sum(red.dang[c]);
-    if (lane == 0) {
-      s_red[c][wave] = ch;
-      s_red[kBC + c][wave] = dg;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int it = st->iter + 1;
-    st->iter = it;
-    int all = 1;
-    for (int c = 0; c < kBC; ++c) {
-      double ch = 0.0, dg = 0.0;
-      for (int w = 0; w < kBFin / 64; ++w) {
-        ch += s_red[c][w];
-        dg += s_red[kBC + c][w];
-      }
-      st->D[c] = dg;
-      if (!st->done[c]) {
-        st->resid[c] = ch;
-        st->iters[c] = it;
-        if (!(ch >= st->tol)) st->done[c] = 1;
-      }
-      all &= st->done[c];
-    }
-    if (all || it >= st->max_iter) st->all_done = 1;
+    for (int q = 0; q < 4; ++q) red.dang[q] += (double)xn[q];
   }
 }
 
-// x = one-hot seeds, c = x / W in gather order, partial dangling mass per column.
-__global__ __launch_bounds__(kBlock) void k_binit(BArgs a, double *part, int nparts) {
-  __shared__ double s_red[kBC][kWaves];
-  const int pass = blockIdx.y;
-  const size_t off = (size_t)pass * a.n;
-  int seed[kBC];
-#pragma unroll
-  for (int c = 0; c < kBC; ++c) seed[c] = a.seeds[pass * kBC + c];
-  double dang[kBC] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < a.n; u += (int64_t)gridDim.x * kBlock) {
-    float xv[kBC];
-#pragma unroll
-    for (int c = 0; c < kBC; ++c) xv[c] = ((int)u == seed[c]) ? 1.0f : 0.0f;
-    a.x[off + u] = make_float4(xv[0], xv[1], xv[2], xv[3]);
+// A run of rows [r0, r1), walked by one lane group.
+__device__ __forceinline__ void run_rows(const VArgs &a, const VCtx &C, int r0, int r1, VRed &red) {
+  uint32_t e0 = a.rptr[r0];
+  for (int r = r0; r < r1; ++r) {
+    const uint32_t e1 = a.rptr[r + 1];
+    const uint32_t u = a.rows[r];
+    const uint32_t slot = a.rowpos[r];
     const double iw = a.inv_w[u];
-    if (iw != 0.0) {
-      a.c0[off + a.gpos[u]] = make_float4((float)(xv[0] * iw), (float)(xv[1] * iw), (float)(xv[2] * iw),
-                                          (float)(xv[3] * iw));
-    } else {
+    const float4 xo = C.act ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    Sum4 acc;
+    range_sum(a, C, e0, e1, acc);
+    double s[4];
 #pragma unroll
-      for (int c = 0; c < kBC; ++c) dang[c] += xv[c];
+    for (int q = 0; q < 4; ++q) s[q] = acc.v[q].value();
+    if (C.act) vupdate(a, C, u, slot, iw, xo, s, red);
+    e0 = e1;
+  }
+}
+
+// The four groups sum one quarter each of [e0, e1); group 0 ends with the
+// whole sum (quarters combined in order).
+__device__ __forceinline__ Sum4 quarter_sum(const VArgs &a, const VCtx &C, uint32_t e0, uint32_t e1) {
+  const uint32_t L = e1 - e0;
+  const uint32_t q0 = e0 + (uint32_t)(((uint64_t)L * C.g) / 4);
+  const uint32_t q1 = e0 + (uint32_t)(((uint64_t)L * (C.g + 1)) / 4);
+  Sum4 acc;
+  range_sum(a, C, q0, q1, acc);
+  Sum4 tot = acc;
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    const Sum4 o = acc.from_lane(C.j + kVGroup * k);
+    tot.combine_with(o);
+  }
+  return tot;
+}
+
+__global__ __launch_bounds__(kVBlock) void k_vsweep(VArgs a) {
+  __shared__ double s_part[kVWaves][2][kVMaxT];
+  const VCtx C = make_vctx(a);
+  // every group holds the same columns: the vote is uniform over the workgroup
+  const bool all_frozen = C.frozen[0] && C.frozen[1] && C.frozen[2] && C.frozen[3];
+  if (__ballot(!all_frozen) == 0ull) return;
+  const int wave = threadIdx.x >> 6;
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kVWaves + wave));
+  const int n_waves = a.n_wg * kVWaves;
+  VRed red;
+  for (int item = gw; item < a.n_items; item += n_waves) {
+    const int4 wi = a.items[item];
+    if (wi.x == kVQuad) {
+      if (C.g < wi.z) {
+        const int2 rr = a.vrun[wi.y + C.g];
+        run_rows(a, C, rr.x, rr.y, red);
+      }
+    } else if (wi.x == kVLong) {
+      const int r = wi.y;
+      const uint32_t u = a.rows[r];
+      const uint32_t slot = a.rowpos[r];
+      const double iw = a.inv_w[u];
+      const float4 xo = (C.g == 0 && C.act) ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const Sum4 tot = quarter_sum(a, C, a.rptr[r], a.rptr[r + 1]);
+      if (C.g == 0 && C.act) {
+        double s[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] = tot.v[q].value();
+        vupdate(a, C, u, slot, iw, xo, s, red);
+      }
+    } else {  // kHeavy: chunk wi.z of hub row wi.y, partial sums to hpart[wi.w + wi.z]
+      const uint32_t rb = a.rptr[wi.y], re = a.rptr[wi.y + 1];
+      const uint32_t c0 = rb + (uint32_t)wi.z * (uint32_t)a.chunk;
+      const uint32_t c1 = min(re, c0 + (uint32_t)a.chunk);
+      const Sum4 tot = quarter_sum(a, C, c0, c1);
+      if (C.g == 0 && C.act) {
+        double *hp = a.hpart + (size_t)(wi.w + wi.z) * a.T + 4 * C.j;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hp[q] = tot.v[q].value();
+      }
     }
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // per column: the four groups in order, then the waves of the workgroup in order
 #pragma unroll
-  for (int c = 0; c < kBC; ++c) {
-    const double v = wave_sum(dang[c]);
-    if (lane == 0) s_red[c][wave] = v;
+  for (int q = 0; q < 4; ++q) {
+    double ch = red.chg[q], dg = red.dang[q];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      const double oc = __shfl(red.chg[q], C.j + kVGroup * k, 64);
+      const double od = __shfl(red.dang[q], C.j + kVGroup * k, 64);
+      ch += oc;
+      dg += od;
+    }
+    if (C.g == 0 && C.act) {
+      s_part[wave][0][4 * C.j + q] = ch;
+      s_part[wave][1][4 * C.j + q] = dg;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * a.T) {
+    const int kind = threadIdx.x / a.T, col = threadIdx.x % a.T;
+    double v = s_part[0][kind][col];
+    for (int w = 1; w < kVWaves; ++w) v += s_part[w][kind][col];
+    a.wg_part[((size_t)kind * a.T + col) * a.n_wg + blockIdx.x] = v;
+  }
+}
+
+// One workgroup per column: completes the split hubs, sums the workgroup
+// partials in a fixed order, and updates the column's state.
+__global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a) {
+  __shared__ double s_red[2][kVFin / 64];
+  const int col = blockIdx.x;
+  VState *st = a.st;
+  if (st->done[col]) return;
+  const int seed = a.seeds[col];
+  const double dterm = st->D[col] * a.inv_n;
+  float *xf = reinterpret_cast<float *>(a.x);
+  float *cf = reinterpret_cast<float *>(a.par ? a.c0 : a.c1);
+  double chg = 0.0, dang = 0.0;
+  for (int i = threadIdx.x; i < a.n_wg; i += kVFin) {
+    chg += a.wg_part[(size_t)col * a.n_wg + i];
+    dang += a.wg_part[((size_t)a.T + col) * a.n_wg + i];
+  }
+  for (int h = threadIdx.x; h < a.n_split; h += kVFin) {
+    const int4 hs = a.hsplit[h];
+    const uint32_t u = a.rows[hs.x];
+    const uint32_t slot = a.rowpos[hs.x];
+    double s = 0.0;
+    for (int k = 0; k < hs.z; ++k) s += a.hpart[(size_t)(hs.y + k) * a.T + col];
+    const float old = xf[(size_t)u * a.T + col];
+    const double tele = ((int)u == seed) ? (1.0 - a.d) : 0.0;
+    const float xn = (float)(tele + a.d * (s + dterm));
+    chg += fabs((double)xn - (double)old);
+    xf[(size_t)u * a.T + col] = xn;
+    const double iw = a.inv_w[u];
+    if (iw != 0.0) cf[(size_t)slot * a.T + col] = (float)((double)xn * iw);
+    else dang += (double)xn;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  chg = wave_sum(chg);
+  dang = wave_sum(dang);
+  if (lane == 0) {
+    s_red[0][wave] = chg;
+    s_red[1][wave] = dang;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int c = 0; c < kBC; ++c) {
-      double v = 0.0;
-      for (int w = 0; w < kWaves; ++w) v += s_red[c][w];
-      part[((size_t)pass * kBC + c) * nparts + blockIdx.x] = v;
+    double ch = s_red[0][0], dg = s_red[1][0];
+    for (int w = 1; w < kVFin / 64; ++w) {
+      ch += s_red[0][w];
+      dg += s_red[1][w];
     }
+    const int it = st->iters[col] + 1;
+    st->iters[col] = it;
+    st->resid[col] = ch;
+    st->D[col] = dg;
+    if (!(ch >= st->tol) || it >= st->max_iter) st->done[col] = 1;
   }
 }
 
-__global__ void k_binit_final(BArgs a, const double *part, int nparts, double tol, int max_iter) {
-  if (threadIdx.x != 0) return;
-  const int pass = blockIdx.x;
-  BState *st = a.st + pass;
-  for (int c = 0; c < kBC; ++c) {
-    double D = 0.0;
-    for (int i = 0; i < nparts; ++i) D += part[((size_t)pass * kBC + c) * nparts + i];
-    st->D[c] = D;
-    st->resid[c] = INFINITY;
-    const int active = a.seeds[pass * kBC + c] >= 0;
-    st->done[c] = active ? 0 : 1;
-    st->iters[c] = 0;
-  }
-  st->iter = 0;
-  st->all_done = 0;
-  st->max_iter = max_iter;
-  st->tol = tol;
-}
-
-// Scatter the pass's columns into the caller's row-major X[n][k].
-__global__ __launch_bounds__(kBlock) void k_bout(BArgs a, float *X, int k, int pass0) {
-  const int pass = blockIdx.y;
-  const size_t off = (size_t)pass * a.n;
-  const int col0 = (pass0 + pass) * kBC;
-  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < a.n; u += (int64_t)gridDim.x * kBlock) {
-    const float4 v = a.x[off + u];
-    float *row = X + (size_t)u * k + col0;
-    if (col0 + 0 < k) row[0] = v.x;
-    if (col0 + 1 < k) row[1] = v.y;
-    if (col0 + 2 < k) row[2] = v.z;
-    if (col0 + 3 < k) row[3] = v.w;
+// x = 0 and c (the first sweep's input) = 0, as float4 rows.
+__global__ __launch_bounds__(kBlock) void k_vzero(float4 *x, float4 *c, int64_t count) {
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
+    x[i] = z;
+    c[i] = z;
   }
 }
 
-__global__ void k_bseeds(const int32_t *seeds, int k, int32_t *out, int total) {
+// One thread per column: the one-hot start x = e_seed, its contribution, and
+// the column's state.
+__global__ void k_vseed(VArgs a, double tol, int max_iter) {
+  const int col = threadIdx.x;
+  VState *st = a.st;
+  if (col == 0) {
+    st->tol = tol;
+    st->max_iter = max_iter;
+  }
+  if (col >= a.T) return;
+  const int seed = a.seeds[col];
+  double D = 0.0;
+  if (seed >= 0) {
+    reinterpret_cast<float *>(a.x)[(size_t)seed * a.T + col] = 1.0f;
+    const double iw = a.inv_w[seed];
+    if (iw != 0.0) reinterpret_cast<float *>(a.c0)[(size_t)a.gpos[seed] * a.T + col] = (float)(1.0 * iw);
+    else D = 1.0;
+  }
+  st->D[col] = D;
+  st->resid[col] = INFINITY;
+  st->done[col] = seed >= 0 ? 0 : 1;
+  st->iters[col] = 0;
+}
+
+// The launch's columns into the caller's row-major X[n][k].
+__global__ __launch_bounds__(kBlock) void k_vout(VArgs a, float *X, int k, int col0) {
+  const float *xf = reinterpret_cast<const float *>(a.x);
+  const int64_t count = a.n * a.T;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
+    const int64_t u = i / a.T;
+    const int c = (int)(i - u * a.T);
+    if (col0 + c < k) X[u * k + col0 + c] = xf[i];
+  }
+}
+
+__global__ void k_vseeds(const int32_t *seeds, int k, int32_t *out, int total) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < total) out[i] = i < k ? seeds[i] : -1;
 }
 
-__global__ void k_bcheck(const int32_t *seeds, int k, int64_t n, int *bad) {
+__global__ void k_vcheck(const int32_t *seeds, int k, int64_t n, int *bad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k && (seeds[i] < 0 || seeds[i] >= n)) *bad = 1;
 }
 
 // ---------------------------------------------------------------- host --
 
-struct BWork {
-  int passes_cap = 0;
+struct VWork {
+  int64_t cols_cap = 0;  // columns the row arrays hold
   float4 *x = nullptr, *c0 = nullptr, *c1 = nullptr;
-  double *hpart = nullptr, *wave_part = nullptr, *part = nullptr;
-  BState *st = nullptr;
-  BState *host_st = nullptr;
+  double *hpart = nullptr, *wg_part = nullptr;
+  VState *st = nullptr;
+  VState *host_st = nullptr;
   int32_t *seeds = nullptr;
   int seeds_cap = 0;
   int *flag = nullptr;
 };
 
-std::vector<std::pair<const pr_graph *, BWork>> g_bwork;
+std::vector<std::pair<const pr_graph *, VWork>> g_vwork;
 
-BWork *bwork_for(pr_graph *g) {
-  for (auto &e : g_bwork)
+VWork *vwork_for(pr_graph *g) {
+  for (auto &e : g_vwork)
     if (e.first == g) return &e.second;
-  g_bwork.emplace_back(g, BWork());
-  return &g_bwork.back().second;
+  g_vwork.emplace_back(g, VWork());
+  return &g_vwork.back().second;
 }
 
-int ensure_bwork(pr_graph *g, BWork &w, int passes) {
+int ensure_vwork(pr_graph *g, VWork &w, int T) {
   int rc;
-  if (w.passes_cap < passes) {
+  if (w.cols_cap < T) {
     const size_t n = (size_t)g->n;
     const DevPlan &P = g->fwd;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.x, sizeof(float4) * n * passes))) return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.c0, sizeof(float4) * n * passes))) return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.c1, sizeof(float4) * n * passes))) return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.hpart, sizeof(double) * kBC * (size_t)std::max(1, P.n_chunks) * passes)))
+    const size_t rows = n * (size_t)(T / 4);
+    if ((rc = fpr_dev_alloc(g, (void **)&w.x, sizeof(float4) * rows))) return rc;
+    if ((rc = fpr_dev_alloc(g, (void **)&w.c0, sizeof(float4) * rows))) return rc;
+    if ((rc = fpr_dev_alloc(g, (void **)&w.c1, sizeof(float4) * rows))) return rc;
+    if ((rc = fpr_dev_alloc(g, (void **)&w.hpart, sizeof(double) * (size_t)T * (size_t)std::max(1, P.n_chunks))))
       return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.wave_part, sizeof(double) * 2 * kBC * (size_t)P.n_waves * passes)))
+    if ((rc = fpr_dev_alloc(g, (void **)&w.wg_part, sizeof(double) * 2 * (size_t)T * (size_t)(P.n_waves / kVWaves))))
       return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.part, sizeof(double) * kBC * 1024 * passes))) return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.st, sizeof(BState) * passes))) return rc;
-    if (w.host_st) (void)hipHostFree(w.host_st);
-    w.host_st = nullptr;
-    if (hipHostMalloc((void **)&w.host_st, sizeof(BState) * passes) != hipSuccess)
-      return pr_fail(PR_ENOMEM, "pinned allocation failed");
-    w.passes_cap = passes;
+    w.cols_cap = T;
   }
+  if (!w.st && (rc = fpr_dev_alloc(g, (void **)&w.st, sizeof(VState)))) return rc;
+  if (!w.host_st && hipHostMalloc((void **)&w.host_st, sizeof(VState)) != hipSuccess)
+    return pr_fail(PR_ENOMEM, "pinned allocation failed");
   if (!w.flag && (rc = fpr_dev_alloc(g, (void **)&w.flag, sizeof(int)))) return rc;
   return PR_OK;
 }
 
-int ensure_seeds(pr_graph *g, BWork &w, int total) {
+int ensure_seeds(pr_graph *g, VWork &w, int total) {
   if (w.seeds_cap >= total) return PR_OK;
   int rc = fpr_dev_alloc(g, (void **)&w.seeds, sizeof(int32_t) * total);
   if (rc) return rc;
@@ -557,85 +452,84 @@ int ensure_seeds(pr_graph *g, BWork &w, int total) {
   return PR_OK;
 }
 
-BArgs make_bargs(pr_graph *g, BWork &w, double d, int passes, int pass0) {
+VArgs make_vargs(pr_graph *g, VWork &w, double d, int T, int col0) {
   const DevPlan &P = g->fwd;
-  BArgs a;
+  VArgs a;
   memset(&a, 0, sizeof(a));
   a.rows = P.rows;
   a.rowpos = P.rowpos;
   a.rptr = P.rptr;
   a.idx = P.idx;
   a.items = P.bitems;
-  a.tiles = P.tiles;
-  a.tidx = P.tidx;
-  a.tmask = P.tmask;
+  a.vrun = P.vrun;
   a.hsplit = P.hsplit;
   a.gpos = P.gpos;
   a.inv_w = g->inv_w;
-  a.seeds = w.seeds + (size_t)pass0 * kBC;
+  a.seeds = w.seeds + col0;
   a.x = w.x;
   a.c0 = w.c0;
   a.c1 = w.c1;
   a.hpart = w.hpart;
-  a.wave_part = w.wave_part;
+  a.wg_part = w.wg_part;
   a.st = w.st;
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
   a.n = g->n;
   a.n_items = P.n_bitems;
   a.n_split = P.n_split;
-  a.n_chunks = std::max(1, P.n_chunks);
-  a.n_waves = P.n_waves;
+  a.n_wg = P.n_waves / kVWaves;
   a.chunk = P.chunk;
-  const int64_t hot = g->popts.hot_slots < 0 ? kBHot : std::min<int64_t>(g->popts.hot_slots, kBHot);
-  a.hot = (int)std::min<int64_t>(hot, g->n);
-  (void)passes;
+  a.T = T;
+  a.Q = T / 4;
+  a.par = 0;
   return a;
 }
 
-// Runs `passes` passes (starting at pass0 of the padded seed list) to
-// convergence; writes their columns of X.  sweeps_out / resid_out: per column.
-int run_passes(pr_graph *g, BWork &w, double d, double tol, int max_iter, int passes, int pass0,
-               float *X, int k, int *iters, double *resid, bool write_out, int fixed_sweeps) {
-  int rc;
-  BArgs a = make_bargs(g, w, d, passes, pass0);
-  const int igrid = (int)std::min<int64_t>(1024, (g->n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_binit, dim3(igrid, passes), dim3(kBlock), 0, g->work, a, w.part, igrid);
-  hipLaunchKernelGGL(k_binit_final, dim3(passes), dim3(64), 0, g->work, a, (const double *)w.part, igrid,
-                     fixed_sweeps > 0 ? -1.0 : tol, fixed_sweeps > 0 ? fixed_sweeps : max_iter);
+// Runs the T columns starting at col0 of the padded seed list to convergence
+// (or exactly fixed_sweeps sweeps when > 0); writes their columns of X.
+int run_columns(pr_graph *g, VWork &w, double d, double tol, int max_iter, int T, int col0, float *X, int k,
+                int *iters, double *resid, bool write_out, int fixed_sweeps) {
+  if (T < 4 || T > kVMaxT || (T % 4) != 0 || T > w.cols_cap)
+    return pr_fail(PR_EDEVICE, "batched: %d columns per launch", T);
+  if (g->fwd.n_waves % kVWaves != 0) return pr_fail(PR_EDEVICE, "batched: wave count mismatch");
+  VArgs a = make_vargs(g, w, d, T, col0);
+  const int64_t rows = g->n * (int64_t)(T / 4);
+  const int zgrid = (int)std::min<int64_t>(4096, (rows + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_vzero, dim3(zgrid), dim3(kBlock), 0, g->work, a.x, a.c0, rows);
+  hipLaunchKernelGGL(k_vseed, dim3(1), dim3(kVMaxT), 0, g->work, a, fixed_sweeps > 0 ? -1.0 : tol,
+                     fixed_sweeps > 0 ? fixed_sweeps : max_iter);
   PR_HIP(hipGetLastError());
-  const int grid = g->fwd.n_waves / kBWaves;
-  if (grid * kBWaves != g->fwd.n_waves) return pr_fail(PR_EDEVICE, "batched: wave count mismatch");
   const int G = 8;
   int done_sweeps = 0;
   const int limit = fixed_sweeps > 0 ? fixed_sweeps : max_iter;
   for (;;) {
     const int cnt = std::min(G, limit - done_sweeps);
     for (int s = 0; s < cnt; ++s) {
-      hipLaunchKernelGGL(k_bsweep, dim3(grid, passes), dim3(kBBlock), 0, g->work, a);
-      hipLaunchKernelGGL(k_bfinal, dim3(passes), dim3(kBFin), 0, g->work, a);
+      a.par = (done_sweeps + s) & 1;
+      hipLaunchKernelGGL(k_vsweep, dim3(a.n_wg), dim3(kVBlock), 0, g->work, a);
+      hipLaunchKernelGGL(k_vfinal, dim3(T), dim3(kVFin), 0, g->work, a);
     }
     PR_HIP(hipGetLastError());
-    PR_HIP(hipMemcpyAsync(w.host_st, w.st, sizeof(BState) * passes, hipMemcpyDeviceToHost, g->work));
+    PR_HIP(hipMemcpyAsync(w.host_st, w.st, sizeof(VState), hipMemcpyDeviceToHost, g->work));
     PR_HIP(hipStreamSynchronize(g->work));
     done_sweeps += cnt;
     bool all = true;
-    for (int p = 0; p < passes; ++p) all &= w.host_st[p].all_done != 0;
+    for (int c = 0; c < T; ++c) all &= w.host_st->done[c] != 0;
     if (all || done_sweeps >= limit) break;
   }
   if (write_out) {
-    hipLaunchKernelGGL(k_bout, dim3(igrid, passes), dim3(kBlock), 0, g->work, a, X, k, pass0);
+    const int ogrid = (int)std::min<int64_t>(4096, (g->n * T + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_vout, dim3(ogrid), dim3(kBlock), 0, g->work, a, X, k, col0);
     PR_HIP(hipGetLastError());
   }
   if (iters && resid) {
-    for (int p = 0; p < passes; ++p)
-      for (int c = 0; c < kBC; ++c) {
-        const int col = (pass0 + p) * kBC + c;
-        if (col < k) {
-          iters[col] = w.host_st[p].iters[c];
-          resid[col] = w.host_st[p].resid[c];
-        }
+    for (int c = 0; c < T; ++c) {
+      const int col = col0 + c;
+      if (col < k) {
+        iters[col] = w.host_st->iters[c];
+        resid[col] = w.host_st->resid[c];
       }
+    }
   }
   return PR_OK;
 }
@@ -676,10 +570,10 @@ std::vector<TuneMemo> g_tune_memo;
 }  // namespace
 
 void fpr_batched_release(pr_graph *g) {
-  for (size_t i = 0; i < g_bwork.size();) {
-    if (g_bwork[i].first == g) {
-      if (g_bwork[i].second.host_st) (void)hipHostFree(g_bwork[i].second.host_st);
-      g_bwork.erase(g_bwork.begin() + i);
+  for (size_t i = 0; i < g_vwork.size();) {
+    if (g_vwork[i].first == g) {
+      if (g_vwork[i].second.host_st) (void)hipHostFree(g_vwork[i].second.host_st);
+      g_vwork.erase(g_vwork.begin() + i);
     } else {
       ++i;
     }
@@ -712,8 +606,8 @@ extern "C" int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, i
   hipStream_t user = (hipStream_t)stream;
   (void)hipEventRecord(g->ev_in, user);
   (void)hipStreamWaitEvent(g->work, g->ev_in, 0);
-  BWork &w = *bwork_for(g);
-  const int kpad = (k + kBC - 1) / kBC * kBC;
+  VWork &w = *vwork_for(g);
+  const int kpad = (k + 3) / 4 * 4;
   int rc;
   if ((rc = ensure_seeds(g, w, kpad))) return rc;
   // tuning seeds: vertices 0.. (the timing does not depend on which)
@@ -724,17 +618,14 @@ extern "C" int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, i
   PR_HIP(hipEventCreate(&e0));
   PR_HIP(hipEventCreate(&e1));
   double best_t = INFINITY;
-  int best = kBC;
+  int best = 4;
   const int sweeps = 4;
-  for (int t = kBC; t <= std::max(kBC, std::min(64, kpad)); t *= 2) {
-    const int passes = t / kBC;
-    if ((rc = ensure_bwork(g, w, passes))) return rc;
-    // one warm-up, one timed run of `sweeps` sweeps on `passes` passes
-    if ((rc = run_passes(g, w, 0.85, 1.0, sweeps, passes, 0, nullptr, k, nullptr, nullptr, false, sweeps)))
-      return rc;
+  for (int t = 4; t <= std::max(4, std::min(kVMaxT, kpad)); t *= 2) {
+    if ((rc = ensure_vwork(g, w, t))) return rc;
+    // one warm-up, one timed run of `sweeps` sweeps on t columns
+    if ((rc = run_columns(g, w, 0.85, 1.0, sweeps, t, 0, nullptr, k, nullptr, nullptr, false, sweeps))) return rc;
     PR_HIP(hipEventRecord(e0, g->work));
-    if ((rc = run_passes(g, w, 0.85, 1.0, sweeps, passes, 0, nullptr, k, nullptr, nullptr, false, sweeps)))
-      return rc;
+    if ((rc = run_columns(g, w, 0.85, 1.0, sweeps, t, 0, nullptr, k, nullptr, nullptr, false, sweeps))) return rc;
     PR_HIP(hipEventRecord(e1, g->work));
     PR_HIP(hipEventSynchronize(e1));
     float ms = 0.0f;
@@ -772,8 +663,8 @@ extern "C" int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter,
   if (max_iter < 1) return pr_fail(PR_EINVAL, "max_iter=%d must be >= 1", max_iter);
   if (k < 1 || k > 1024) return pr_fail(PR_EINVAL, "k=%d outside [1, 1024]", k);
   if (!seeds || !X || !iters || !resid) return pr_fail(PR_EINVAL, "NULL argument");
-  if (tile < 0 || tile > 64 || (tile % kBC) != 0)
-    return pr_fail(PR_EINVAL, "tile=%d must be 0 (autotune) or a multiple of %d up to 64", tile, kBC);
+  if (tile < 0 || tile > kVMaxT || (tile % 4) != 0)
+    return pr_fail(PR_EINVAL, "tile=%d must be 0 (autotune) or a multiple of 4 up to %d", tile, kVMaxT);
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != g->device)
     return pr_fail(PR_EINVAL, "the graph lives on device %d but device %d is current", g->device, cur);
@@ -784,22 +675,21 @@ extern "C" int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter,
   hipStream_t user = (hipStream_t)stream;
   (void)hipEventRecord(g->ev_in, user);
   (void)hipStreamWaitEvent(g->work, g->ev_in, 0);
-  BWork &w = *bwork_for(g);
-  const int kpad = (k + kBC - 1) / kBC * kBC;
-  const int npass = kpad / kBC;
-  const int per_launch = std::min(npass, tile / kBC);
+  VWork &w = *vwork_for(g);
+  const int kpad = (k + 3) / 4 * 4;
+  const int per_launch = std::min(kpad, tile);
   if ((rc = ensure_seeds(g, w, kpad))) return rc;
-  if ((rc = ensure_bwork(g, w, per_launch))) return rc;
-  hipLaunchKernelGGL(k_bseeds, dim3((kpad + 255) / 256), dim3(256), 0, g->work, seeds, k, w.seeds, kpad);
+  if ((rc = ensure_vwork(g, w, per_launch))) return rc;
+  hipLaunchKernelGGL(k_vseeds, dim3((kpad + 255) / 256), dim3(256), 0, g->work, seeds, k, w.seeds, kpad);
   PR_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), g->work));
-  hipLaunchKernelGGL(k_bcheck, dim3((k + 255) / 256), dim3(256), 0, g->work, seeds, k, (int64_t)g->n, w.flag);
+  hipLaunchKernelGGL(k_vcheck, dim3((k + 255) / 256), dim3(256), 0, g->work, seeds, k, (int64_t)g->n, w.flag);
   int bad = 0;
   PR_HIP(hipMemcpyAsync(&bad, w.flag, sizeof(int), hipMemcpyDeviceToHost, g->work));
   PR_HIP(hipStreamSynchronize(g->work));
   if (bad) return pr_fail(PR_EINVAL, "a seed vertex is outside [0, %lld)", (long long)g->n);
-  for (int p0 = 0; p0 < npass; p0 += per_launch) {
-    const int passes = std::min(per_launch, npass - p0);
-    if ((rc = run_passes(g, w, d, tol, max_iter, passes, p0, X, k, iters, resid, true, 0))) return rc;
+  for (int c0 = 0; c0 < kpad; c0 += per_launch) {
+    const int T = std::min(per_launch, kpad - c0);
+    if ((rc = run_columns(g, w, d, tol, max_iter, T, c0, X, k, iters, resid, true, 0))) return rc;
   }
   PR_HIP(hipStreamSynchronize(g->work));
   (void)hipEventRecord(g->ev_out, g->work);

@@ -41,8 +41,9 @@ constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather 
 constexpr int kHotLayout = kHotBytes / 4;     // slots kept in gather-count order by gather_layout 2
 constexpr int kTileEdges = 512;               // edges of a tile: 8 consecutive per lane
 constexpr int kTileRows = 128;                // rows of a tile at most (row sums staged in LDS)
+constexpr int kVRunCost = 64;                 // batched: batch rounds per run of short rows
 
-enum ItemKind : int { kTile = 0, kRows = 1, kHeavy = 2, kZero = 3, kHubWG = 4 };
+enum ItemKind : int { kTile = 0, kRows = 1, kHeavy = 2, kZero = 3, kHubWG = 4, kVLong = 5, kVQuad = 6 };
 
 // Sweep flags (runtime, uniform across the grid)
 enum SweepFlags : int {
@@ -80,7 +81,9 @@ struct DevPlan {
   int4 *items = nullptr;      // [n_items] sweep list: {kTile, tile} | {kRows, first, end, lanes per
                               // row} | {kHubWG, row} (whole workgroup) | {kHeavy, row, chunk, slot}
                               // | {kZero, first, end}
-  int4 *bitems = nullptr;     // [n_bitems] batched list: as items, hubs as {kHeavy, row, chunk, slot}
+  int4 *bitems = nullptr;     // [n_bitems] batched list: {kHeavy, row, chunk, slot} (hub chunk) |
+                              // {kVLong, row} (one long row) | {kVQuad, first run, runs (1..4)}
+  int2 *vrun = nullptr;       // [n_vrun] batched row runs [first, end) of short and empty rows
   int4 *tiles = nullptr;      // [n_tiles] {first row, rows, edges, 0}
   int32_t *tidx = nullptr;    // [n_tiles * 512] tile edges, lane-transposed: [k][lane] = edge 8*lane+k
   double *tw = nullptr;       // [n_tiles * 512] their weights, same layout (or null)
@@ -94,6 +97,7 @@ struct DevPlan {
   SweepState *st = nullptr;
   int n_items = 0;
   int n_bitems = 0;
+  int n_vrun = 0;
   int n_tiles = 0;
   int n_heavy = 0;
   int n_split = 0;

@@ -171,9 +171,12 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   //    `chunk`-edge items whose sums the finalize kernel adds (msplit /
   //    hpart); the items are dealt to wavefronts per block (below);
   //  * the batched list: each hub is split into `chunk`-edge items whose sums
-  //    the batched finalize kernel adds (hsplit / hpart).
+  //    the batched finalize kernel adds (hsplit / hpart); each row of the
+  //    one-wavefront bin is an item of its own; the short and empty rows are
+  //    cut into runs of about kVRunCost batch rounds, four runs to an item.
   const int W = g->grid * kSweepWaves;
   std::vector<int4> items, bitems, hsplit, msplit, tiles;
+  std::vector<int2> vrun;
   std::vector<int> wave_cnt;
   const int64_t wg_max = (int64_t)kSweepWaves * o.chunk;  // longest list of a workgroup item
   std::vector<int32_t> tidx;
@@ -200,6 +203,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
       P.e_heavy += L;
     }
     P.n_heavy_rows += (int64_t)hubs.size();
+    const int64_t long0 = i;  // the block's one-wavefront, short and empty rows: [long0, short0), [short0, ...)
     {
       const int64_t end = i + (int64_t)bins[(size_t)b * 4 + 1].size();
       for (int64_t i0 = i; i0 < end; i0 += o.steps)
@@ -208,6 +212,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
       P.e_medium += rptr[end] - rptr[i];
       i = end;
     }
+    const int64_t short0 = i;
     {
       const int64_t end = i + (int64_t)bins[(size_t)b * 4 + 2].size();
       P.n_light += end - i;
@@ -247,7 +252,27 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
       P.n_light += end - i;
       i = end;
     }
-    bitems.insert(bitems.end(), rest.begin(), rest.end());
+    // batched list: the long rows one by one, then the short and empty rows
+    // in runs (a run's cost: a round of up to 8 gathers per 8 edges, and one
+    // for the update), four runs to an item
+    for (int64_t r = long0; r < short0; ++r) bitems.push_back(make_int4(kVLong, (int)r, 0, 0));
+    {
+      std::vector<int2> runs;
+      for (int64_t r = short0; r < i;) {
+        const int64_t r0 = r;
+        int64_t c = 0;
+        while (r < i) {
+          const int64_t cr = (int64_t)(rptr[r + 1] - rptr[r] + 7) / 8 + 1;
+          if (c > 0 && c + cr > kVRunCost) break;
+          c += cr;
+          ++r;
+        }
+        runs.push_back(make_int2((int)r0, (int)r));
+      }
+      for (size_t q = 0; q < runs.size(); q += 4)
+        bitems.push_back(make_int4(kVQuad, (int)(vrun.size() + q), (int)std::min<size_t>(4, runs.size() - q), 0));
+      vrun.insert(vrun.end(), runs.begin(), runs.end());
+    }
     // The sweep list of this block: work items are dealt to the W
     // wavefronts of a launch by longest-processing-time first, with a cost
     // model in 512-edge gather rounds.  Hubs go first, each to all 8
@@ -342,6 +367,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     if (!bins[(size_t)b * 4].empty()) return pr_fail(PR_EDEVICE, "pr_graph_create: hub outside the last block");
   P.n_items = (int)items.size();
   P.n_bitems = (int)bitems.size();
+  P.n_vrun = (int)vrun.size();
   P.n_tiles = (int)tiles.size();
   P.n_heavy = (int)P.n_heavy_rows;
   P.n_split = (int)hsplit.size();
@@ -368,8 +394,16 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   };
   for (const int4 &it : items)
     if (!check(it)) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
-  for (const int4 &it : bitems)
-    if (it.x == kHubWG || !check(it)) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed");
+  for (const int4 &it : bitems) {
+    bool ok;
+    if (it.x == kVLong) ok = it.y >= 0 && it.y < n && rptr[it.y + 1] > rptr[it.y];
+    else if (it.x == kVQuad) ok = it.y >= 0 && it.z >= 1 && it.z <= 4 && (int64_t)it.y + it.z <= (int64_t)vrun.size();
+    else ok = it.x == kHeavy && check(it);
+    if (!ok) return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (batched item)");
+  }
+  for (const int2 &rr : vrun)
+    if (!(rr.x >= 0 && rr.x < rr.y && rr.y <= n))
+      return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (batched run)");
   // every wavefront of a workgroup meets each of its hub items at the same
   // list index
   for (int b = 0; b < B; ++b)
@@ -401,6 +435,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     if ((rc = upload(g, &P.block_pos, bpos.data(), bpos.size()))) return rc;
   }
   if ((rc = upload(g, &P.hsplit, hsplit.data(), hsplit.size()))) return rc;
+  if ((rc = upload(g, &P.vrun, vrun.data(), vrun.size()))) return rc;
   if ((rc = upload(g, &P.msplit, msplit.data(), msplit.size()))) return rc;
   if ((rc = upload(g, &P.tiles, tiles.data(), tiles.size()))) return rc;
   if ((rc = upload(g, &P.tidx, tidx.data(), tidx.size()))) return rc;

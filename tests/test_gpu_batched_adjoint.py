@@ -80,22 +80,26 @@ def test_batched_tile_widths_agree_and_linearity():
     g.close()
 
 
-def test_batched_lds_copy_does_not_change_bits():
-    """The LDS copy of the hottest slots holds the values the sweep would load,
-    so its size (none, a ragged few, 2048, the default 3072) leaves every bit
-    of the result unchanged; n = 8192 puts most slots outside it."""
+def test_batched_tile_widths_agree_with_hubs_and_long_rows():
+    """Small chunk and tile-row limits give the graph split hubs (chunk items
+    added by the finalize kernel), long rows (one quarter per lane group) and
+    short rows in runs.  Every tile width sums each column in the same order,
+    so the columns agree bit for bit; two columns are checked against the
+    oracle."""
     fpr = _fpr()
     n = 1 << 13
     s, t = gg.rmat(13, 16, seed=7)
     seeds = gg.sample_distinct(n, 24, 7, 4)
     sd = torch.tensor(seeds, dtype=torch.int32, device="cuda")
+    g = fpr.Graph(n, s, t, plan=dict(chunk=64, tile_max_row=16))
+    st = g.stats()
+    assert st["n_heavy"] > 0 and st["n_medium"] > 0, st
     outs = []
-    for hot in (0, 5, 2048, -1):
-        say("batched hot_slots=%d" % hot)
-        g = fpr.Graph(n, s, t, plan=dict(hot_slots=hot))
-        X, its, res = g.solve_batched(sd, d=D, tol=1e-6, tile=8)
+    for tile in (4, 8, 16, 64):
+        say("batched hubs tile=%d" % tile)
+        X, its, res = g.solve_batched(sd, d=D, tol=1e-6, tile=tile)
         outs.append((X.cpu().numpy(), its, res))
-        g.close()
+    g.close()
     for X, its, res in outs[1:]:
         assert np.array_equal(X, outs[0][0]) and np.array_equal(its, outs[0][1])
     og = oracle.csr(n, s, t)
