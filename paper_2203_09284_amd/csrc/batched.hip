@@ -10,8 +10,9 @@
 // (lanes with 4j >= T stay idle).
 //
 // Work (the plan's batched list).  Short and empty rows come in runs; each
-// run is walked by one lane group, row by row, up to 8 gathers in flight per
-// lane.  A long row is one item: the four groups sum one quarter of its list
+// run is walked by one lane group, row by row: a group loads 16 gather slots
+// at once (a lane each) and broadcasts them across its 16 lanes by DPP, with
+// 8 row reads in flight per lane.  A long row is one item: the four groups sum one quarter of its list
 // each.  A hub is split into `chunk`-edge items of the same kind, whose sums
 // the finalize kernel adds in chunk order.  None of this depends on T, and
 // every column is summed in the same order whatever the tile width, so the
@@ -142,20 +143,55 @@ __device__ __forceinline__ VCtx make_vctx(const VArgs &a) {
   return C;
 }
 
-// Sum over the in-edges [e0, e1) in list order, up to 8 row reads in flight.
+// Lane b of the caller's 16-lane row (DPP row_newbcast:b).
+template <int B>
+__device__ __forceinline__ int row_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + B, 0xf, 0xf, true);
+}
+
+// Adds the rows of cnt <= 16 in-edges, in list order, whose gather slots lane
+// b of the group holds in `sl` (one load of 16 slots per group instead of one
+// per edge); 8 row reads in flight per lane.
+__device__ __forceinline__ void chunk16(const VArgs &a, const VCtx &C, int sl, int cnt, Sum4 &acc) {
+  float4 v[kBatch];
+  int s[kBatch];
+  s[0] = row_bcast<0>(sl);
+  s[1] = row_bcast<1>(sl);
+  s[2] = row_bcast<2>(sl);
+  s[3] = row_bcast<3>(sl);
+  s[4] = row_bcast<4>(sl);
+  s[5] = row_bcast<5>(sl);
+  s[6] = row_bcast<6>(sl);
+  s[7] = row_bcast<7>(sl);
+#pragma unroll
+  for (int b = 0; b < kBatch; ++b)
+    v[b] = (b < cnt && C.act) ? C.cin[(size_t)s[b] * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int b = 0; b < kBatch; ++b)
+    if (b < cnt) acc.add(v[b]);
+  if (cnt > kBatch) {
+    s[0] = row_bcast<8>(sl);
+    s[1] = row_bcast<9>(sl);
+    s[2] = row_bcast<10>(sl);
+    s[3] = row_bcast<11>(sl);
+    s[4] = row_bcast<12>(sl);
+    s[5] = row_bcast<13>(sl);
+    s[6] = row_bcast<14>(sl);
+    s[7] = row_bcast<15>(sl);
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+      v[b] = (kBatch + b < cnt && C.act) ? C.cin[(size_t)s[b] * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+      if (kBatch + b < cnt) acc.add(v[b]);
+  }
+}
+
+// Sum over the in-edges [e0, e1) in list order.
 __device__ __forceinline__ void range_sum(const VArgs &a, const VCtx &C, uint32_t e0, uint32_t e1, Sum4 &acc) {
-  for (uint32_t e = e0; e < e1; e += kBatch) {
-    const int cnt = (int)min((uint32_t)kBatch, e1 - e);
-    int32_t s[kBatch];
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) s[b] = b < cnt ? a.idx[e + b] : 0;
-    float4 v[kBatch];
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b)
-      v[b] = (b < cnt && C.act) ? C.cin[(size_t)s[b] * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b)
-      if (b < cnt) acc.add(v[b]);
+  for (uint32_t e = e0; e < e1; e += 16) {
+    const int sl = e + C.j < e1 ? a.idx[e + C.j] : 0;
+    chunk16(a, C, sl, (int)min(16u, e1 - e), acc);
   }
 }
 
@@ -190,22 +226,35 @@ __device__ __forceinline__ void vupdate(const VArgs &a, const VCtx &C, uint32_t 
   }
 }
 
-// A run of rows [r0, r1), walked by one lane group.
+// A run of rows [r0, r1), walked by one lane group.  The next row's bounds,
+// vertex and slot, and the current row's update operands, load while the
+// current row's rows are read; the next row's first 16 gather slots load
+// while the current row is updated.
 __device__ __forceinline__ void run_rows(const VArgs &a, const VCtx &C, int r0, int r1, VRed &red) {
-  uint32_t e0 = a.rptr[r0];
+  uint32_t e0 = a.rptr[r0], e1 = a.rptr[r0 + 1];
+  uint32_t u = a.rows[r0], slot = a.rowpos[r0];
+  int sl = e0 + C.j < e1 ? a.idx[e0 + C.j] : 0;
   for (int r = r0; r < r1; ++r) {
-    const uint32_t e1 = a.rptr[r + 1];
-    const uint32_t u = a.rows[r];
-    const uint32_t slot = a.rowpos[r];
+    const bool more = r + 1 < r1;
+    const uint32_t ne1 = more ? a.rptr[r + 2] : e1;
+    const uint32_t nu = more ? a.rows[r + 1] : 0u;
+    const uint32_t nslot = more ? a.rowpos[r + 1] : 0u;
     const double iw = a.inv_w[u];
     const float4 xo = C.act ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
     Sum4 acc;
-    range_sum(a, C, e0, e1, acc);
+    for (uint32_t e = e0; e < e1; e += 16) {
+      if (e != e0) sl = e + C.j < e1 ? a.idx[e + C.j] : 0;
+      chunk16(a, C, sl, (int)min(16u, e1 - e), acc);
+    }
+    sl = (more && e1 + C.j < ne1) ? a.idx[e1 + C.j] : 0;
     double s[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) s[q] = acc.v[q].value();
     if (C.act) vupdate(a, C, u, slot, iw, xo, s, red);
     e0 = e1;
+    e1 = ne1;
+    u = nu;
+    slot = nslot;
   }
 }
 
@@ -226,7 +275,7 @@ __device__ __forceinline__ Sum4 quarter_sum(const VArgs &a, const VCtx &C, uint3
   return tot;
 }
 
-__global__ __launch_bounds__(kVBlock) void k_vsweep(VArgs a) {
+__global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_vsweep(VArgs a) {
   __shared__ double s_part[kVWaves][2][kVMaxT];
   const VCtx C = make_vctx(a);
   // every group holds the same columns: the vote is uniform over the workgroup
