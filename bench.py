@@ -26,7 +26,8 @@ The same JSON line carries, on the same GPU:
 
     python bench.py [--steps K] [--warmup W] [--quick]
     python bench.py --profile FORM [--workload rmat20|rmat24]   (kernel-only driver
-        for rocprofv3: sweeps of one form, then a reference copy kernel)
+        for rocprofv3: sweeps of one form, or one k = 64 batched solve with
+        FORM = batched, then a reference copy kernel)
     python bench.py --pmc-summary KEY FETCH_CSV WRITE_CSV DRIVER_LOG  (counter runs of
         that driver -> HBM bytes per sweep, into profiles/traffic.json)
     python bench.py --study [WORKLOAD ...]   (convergence study: thresholds 1e-6..1e-15,
@@ -50,6 +51,7 @@ METRIC = ("GTEPS/iter + time-to-L1 1e-8 (fused/batched/fp32 vs plain fp64), % HB
 HBM_PEAK_GBS = 8000.0
 D = 0.85
 KERNEL_SOURCES = ("sweep.hip", "device_common.h", "internal.h")
+BATCHED_SOURCES = ("batched.hip", "device_common.h", "internal.h")
 COPY_BYTES = 256 << 20  # the reference copy kernel reads and writes this many bytes
 
 
@@ -99,14 +101,14 @@ def b_alg(n, m, s):
     return 4 * m + 8 * (n + 1) + 2 * s * n + 4 * n
 
 
-def kernel_source_sha():
+def kernel_source_sha(files=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2203_09284_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_record(key):
+def traffic_record(key, files=KERNEL_SOURCES):
     """HBM bytes per sweep (the sweep kernel's launches of one sweep) from the
     committed rocprofv3 counter runs (profiles/traffic.json), valid only while
     the kernel sources are unchanged."""
@@ -117,7 +119,7 @@ def traffic_record(key):
         rec = json.load(open(path)).get(key)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_sha") != kernel_source_sha():
+    if not rec or rec.get("source_sha") != kernel_source_sha(files):
         return None
     return rec.get("bytes_per_sweep")
 
@@ -221,8 +223,14 @@ def leg_batched(torch, fpr, g, n, m, steps):
     t_s, its_s = timed(torch, sequential, 1, 1)
     log("64 sequential FP64 Jacobi PPR solves: %.2f ms" % t_s)
     col = float(its.sum())
+    # with all 64 columns in one launch, every sweep reads, per in-edge, the
+    # source's 256-byte row (rate over the whole solve, init and output included)
+    row_bytes = float(m) * 4 * 64 * int(its.max()) if tune == 64 else None
+    traffic = traffic_record("batched_rmat20", BATCHED_SOURCES) if n == (1 << 20) else None
     return rounded(dict(k=64, tol=1e-6, tile=tune, ms=t_b, max_sweeps=int(its.max()),
                         column_sweeps=int(col), column_gteps=m * col / (t_b * 1e-3) / 1e9,
+                        row_read_gbs=row_bytes / (t_b * 1e-3) / 1e9 if row_bytes else None,
+                        b_alg_per_sweep=b_alg(n, m, 4 * 64), traffic_per_sweep=traffic,
                         sequential_fp64_ms=t_s, sequential_sweeps=int(sum(its_s)),
                         speedup_vs_sequential_fp64=t_s / t_b))
 
@@ -359,6 +367,24 @@ def profile_driver(args):
     import paper_2203_09284_amd as fpr
     torch.cuda.set_device(0)
     w = workload(args.workload)
+    if args.profile == "batched":
+        import graphgen as gg
+        g = fpr.Graph(w["n"], w["src"], w["dst"])
+        seeds = torch.tensor(gg.ppr_seeds(g.n), dtype=torch.int32, device="cuda")
+        X, its, _ = g.solve_batched(seeds, d=D, tol=1e-6, tile=64)
+        torch.cuda.synchronize()
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        # sweeps that did work (launches after every column froze exit at once)
+        print(json.dumps({"profile": "batched", "workload": args.workload, "n": g.n, "m": g.m,
+                          "sweeps": int(its.max()), "copy_bytes": COPY_BYTES, "columns": 64,
+                          "b_alg": b_alg(g.n, g.m, 4 * 64),
+                          "source_sha": kernel_source_sha(BATCHED_SOURCES)}), flush=True)
+        g.close()
+        return
     mode, prec = args.profile.split("-")[:2]
     g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1 if mode == "edge_list" else 0))
     x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
@@ -443,6 +469,7 @@ def pmc_summary(args):
     import csv
     key, fetch_csv, write_csv, driver_log = args.pmc_summary
     drv = json.loads([ln for ln in open(driver_log) if ln.startswith('{"profile"')][-1])
+    kname = "k_vsweep(" if drv["profile"] == "batched" else "k_sweep<"
 
     def read(path, counter):
         sweep, copy = [], []
@@ -450,7 +477,7 @@ def pmc_summary(args):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"]) * 1024.0  # KiB per dispatch
-            if "k_sweep<" in r["Kernel_Name"]:
+            if kname in r["Kernel_Name"]:
                 sweep.append(v)
             elif "MulFunctor" in r["Kernel_Name"]:
                 copy.append(v)
@@ -485,7 +512,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only (no extra legs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rmat24", action="store_true")
-    ap.add_argument("--profile", default=None, help="{jacobi,fused,edge_list}-{fp64,fp32}")
+    ap.add_argument("--profile", default=None, help="{jacobi,fused,edge_list}-{fp64,fp32} | batched")
     ap.add_argument("--profile-sweeps", type=int, default=20)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--scales", nargs="*", type=int, default=None, metavar="SCALE",
