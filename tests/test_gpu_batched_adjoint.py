@@ -107,6 +107,53 @@ def test_batched_tile_widths_agree_with_hubs_and_long_rows():
         assert l1(outs[-1][0][:, j].astype(np.float64), _ppr_ref(og, n, seeds[j])) <= 1e-5, j
 
 
+def test_batched_more_columns_than_one_launch():
+    """k = 70 takes two launches of at most 64 columns (the second holds 6 real
+    and 2 padding columns): every column lands in its own place of X, and tile
+    widths 64 and 8 agree bit for bit."""
+    fpr = _fpr()
+    n = 1 << 11
+    s, t = gg.rmat(11, 16, seed=9)
+    og = oracle.csr(n, s, t)
+    seeds = gg.sample_distinct(n, 70, 9, 4)
+    sd = torch.tensor(seeds, dtype=torch.int32, device="cuda")
+    g = fpr.Graph(n, s, t)
+    say("batched k=70")
+    X64, its64, _ = g.solve_batched(sd, d=D, tol=1e-6, tile=64)
+    X8, its8, _ = g.solve_batched(sd, d=D, tol=1e-6, tile=8)
+    g.close()
+    X64 = X64.cpu().numpy()
+    X8 = X8.cpu().numpy()
+    assert X64.shape == (n, 70)
+    assert np.array_equal(X64, X8) and np.array_equal(its64, its8)
+    for j in (0, 63, 64, 69):
+        assert l1(X64[:, j].astype(np.float64), _ppr_ref(og, n, seeds[j])) <= 1e-5, j
+
+
+@pytest.mark.parametrize("n,edges", [(1, ([], [])), (5, ([], [])), (4, ([0, 1], [1, 2]))])
+def test_batched_degenerate_graphs(n, edges):
+    """Graphs without edges: every vertex is dangling and all mass is spread
+    uniformly, so column s is (1-d) e_s + d/n in closed form.  A path with a
+    dangling end is checked against the oracle."""
+    fpr = _fpr()
+    s = np.array(edges[0], np.int32)
+    t = np.array(edges[1], np.int32)
+    k = min(n, 3)
+    seeds = list(range(n - k, n))
+    say("batched degenerate n=%d m=%d" % (n, len(s)))
+    g = fpr.Graph(n, s, t)
+    X, its, res = g.solve_batched(torch.tensor(seeds, dtype=torch.int32, device="cuda"), d=D, tol=1e-7, tile=4)
+    g.close()
+    Xh = X.cpu().numpy().astype(np.float64)
+    for j, sj in enumerate(seeds):
+        if len(s) == 0:
+            want = np.full(n, D / n)
+            want[sj] += 1.0 - D
+        else:
+            want = _ppr_ref(oracle.csr(n, s, t), n, sj)
+        assert l1(Xh[:, j], want) <= 1e-6, (j, Xh[:, j], want)
+
+
 def test_batched_autotune_cache(tmp_path):
     fpr = _fpr()
     n = 1 << 11
