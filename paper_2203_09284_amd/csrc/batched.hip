@@ -362,8 +362,16 @@ __global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a) {
     const int4 hs = a.hsplit[h];
     const uint32_t u = a.rows[hs.x];
     const uint32_t slot = a.rowpos[hs.x];
+    // chunk sums in chunk order, eight loads in flight (a zero past the end
+    // leaves the sum unchanged)
     double s = 0.0;
-    for (int k = 0; k < hs.z; ++k) s += a.hpart[(size_t)(hs.y + k) * a.T + col];
+    for (int k0 = 0; k0 < hs.z; k0 += 8) {
+      double pt[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pt[k] = k0 + k < hs.z ? a.hpart[(size_t)(hs.y + k0 + k) * a.T + col] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += pt[k];
+    }
     const float old = xf[(size_t)u * a.T + col];
     const double tele = ((int)u == seed) ? (1.0 - a.d) : 0.0;
     const float xn = (float)(tele + a.d * (s + dterm));
@@ -542,6 +550,10 @@ int run_columns(pr_graph *g, VWork &w, double d, double tol, int max_iter, int T
     return pr_fail(PR_EDEVICE, "batched: %d columns per launch", T);
   if (g->fwd.n_waves % kVWaves != 0) return pr_fail(PR_EDEVICE, "batched: wave count mismatch");
   VArgs a = make_vargs(g, w, d, T, col0);
+  // one launch holding all k columns keeps its ranks in the caller's X (same
+  // row-major layout), with no copy at the end
+  const bool direct = write_out && T == k && ((uintptr_t)X % sizeof(float4)) == 0;
+  if (direct) a.x = reinterpret_cast<float4 *>(X);
   const int64_t rows = g->n * (int64_t)(T / 4);
   const int zgrid = (int)std::min<int64_t>(4096, (rows + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_vzero, dim3(zgrid), dim3(kBlock), 0, g->work, a.x, a.c0, rows);
@@ -566,7 +578,7 @@ int run_columns(pr_graph *g, VWork &w, double d, double tol, int max_iter, int T
     for (int c = 0; c < T; ++c) all &= w.host_st->done[c] != 0;
     if (all || done_sweeps >= limit) break;
   }
-  if (write_out) {
+  if (write_out && !direct) {
     const int ogrid = (int)std::min<int64_t>(4096, (g->n * T + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_vout, dim3(ogrid), dim3(kBlock), 0, g->work, a, X, k, col0);
     PR_HIP(hipGetLastError());
