@@ -50,8 +50,9 @@ sys.path.insert(0, ROOT)
 METRIC = ("GTEPS/iter + time-to-L1 1e-8 (fused/batched/fp32 vs plain fp64), % HBM peak")
 HBM_PEAK_GBS = 8000.0
 D = 0.85
-KERNEL_SOURCES = ("sweep.hip", "device_common.h", "internal.h")
-BATCHED_SOURCES = ("batched.hip", "device_common.h", "internal.h")
+# the kernels and the plan that shapes their launches
+KERNEL_SOURCES = ("sweep.hip", "plan.hip", "device_common.h", "internal.h")
+BATCHED_SOURCES = ("batched.hip", "plan.hip", "device_common.h", "internal.h")
 COPY_BYTES = 256 << 20  # the reference copy kernel reads and writes this many bytes
 
 

@@ -130,8 +130,9 @@ typedef struct pr_plan_opts {
                             vertices (as many as the LDS copy holds in FP32) first, the rest in
                             vertex-id order, which keeps the locality of an ordered input */
   int with_adjoint;      /* also plan the out-edge (transposed) pull for pr_adjoint */
-  int gs_blocks;         /* Gauss-Seidel blocks of the fused form (0 = default: 2, or 1 for
-                            graphs under 64 edges per sweep wavefront; else 1..64): the
+  int gs_blocks;         /* Gauss-Seidel blocks of the fused form (0 = default by edges per
+                            sweep wavefront: 1 under 64, 2 under 6144, 3 under 49152, else 8;
+                            else 1..64): the
                             vertices, in decreasing out-degree, are cut into this many blocks
                             of equal in-edge count (hubs join the last block) and swept one
                             launch each, so every block reads the contributions the blocks

@@ -519,9 +519,13 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
   }
   o.tile_max_row = std::min(o.tile_max_row, o.chunk);
   if (o.gs_blocks == 0) {
-    // a second launch per sweep pays off once a sweep is long against the
-    // cost of a launch: about 64 edges per wavefront
-    o.gs_blocks = csr->m >= 64 * (int64_t)g->grid * kSweepWaves ? 2 : 1;
+    // Each block costs a launch (ramp and tail, about 10 us) and saves
+    // sweeps; the longer a sweep, the more blocks pay off.  By edges per
+    // sweep wavefront: under 64 one block, under 6144 two (R-MAT-20), under
+    // 49152 three (R-MAT-21 to 23), else eight (R-MAT-24), the fastest
+    // measured counts at those sizes.
+    const int64_t epw = csr->m / ((int64_t)g->grid * kSweepWaves);
+    o.gs_blocks = epw < 64 ? 1 : epw < 6144 ? 2 : epw < 49152 ? 3 : 8;
   }
   g->popts = o;
   rc = [&]() -> int {
