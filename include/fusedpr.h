@@ -251,7 +251,8 @@ int pr_certificate(pr_graph *g, double d, const double *p, const double *x, doub
  * seeds[j] (Eq. 1 with a personalised teleport term), solved together as a
  * multi-column Jacobi pull per sweep.  Dangling mass is spread uniformly.
  * Ranks are FP32 (compensated sums), per-column residual and dangling mass
- * FP64; a column is frozen once its L1 residual is below tol.
+ * FP64; a column is frozen once its L1 residual is below tol.  Unweighted
+ * graphs only: a graph created with edge weights gives PR_EINVAL.
  *   seeds   device int32[k], ids in [0, n) (checked: PR_EINVAL);  1 <= k <= 1024
  *   X       device float[n * k], row-major (vertex-major): X[v * k + j]
  *   iters   host int[k]: sweeps until column j froze (or max_iter)

@@ -649,6 +649,7 @@ extern "C" int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, i
   pr_clear_error();
   if (!g || !tile) return pr_fail(PR_EINVAL, "pr_autotune_batched: NULL argument");
   if (k < 1 || k > 1024) return pr_fail(PR_EINVAL, "k=%d outside [1, 1024]", k);
+  if (g->weighted) return pr_fail(PR_EINVAL, "pr_autotune_batched: the graph has edge weights (unweighted graphs only)");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != g->device)
     return pr_fail(PR_EINVAL, "the graph lives on device %d but device %d is current", g->device, cur);
@@ -724,6 +725,7 @@ extern "C" int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter,
   if (max_iter < 1) return pr_fail(PR_EINVAL, "max_iter=%d must be >= 1", max_iter);
   if (k < 1 || k > 1024) return pr_fail(PR_EINVAL, "k=%d outside [1, 1024]", k);
   if (!seeds || !X || !iters || !resid) return pr_fail(PR_EINVAL, "NULL argument");
+  if (g->weighted) return pr_fail(PR_EINVAL, "pr_solve_batched: the graph has edge weights (unweighted graphs only)");
   if (tile < 0 || tile > kVMaxT || (tile % 4) != 0)
     return pr_fail(PR_EINVAL, "tile=%d must be 0 (autotune) or a multiple of 4 up to %d", tile, kVMaxT);
   int cur = -1;

@@ -171,6 +171,17 @@ def test_batched_autotune_cache(tmp_path):
     g2.close()
 
 
+def test_batched_rejects_weighted_graphs():
+    fpr = _fpr()
+    from paper_2203_09284_amd._lib import FusedPRError
+    s, t = gg.cycle(10)
+    g = fpr.Graph(10, s, t, gg.weights(len(s), 3))
+    say("batched weighted")
+    with pytest.raises(FusedPRError):
+        g.solve_batched(torch.tensor([1, 2], dtype=torch.int32, device="cuda"), tile=4)
+    g.close()
+
+
 def test_batched_rejects_bad_seeds():
     fpr = _fpr()
     from paper_2203_09284_amd._lib import FusedPRError
