@@ -178,7 +178,17 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   std::vector<int4> items, bitems, hsplit, msplit, tiles;
   std::vector<int2> vrun;
   std::vector<int> wave_cnt;
-  const int64_t wg_max = (int64_t)kSweepWaves * o.chunk;  // longest list of a workgroup item
+  // No single item may outlast the launch that holds it.  A whole-workgroup
+  // hub takes at most 8 chunks and at most a workgroup's share of a launch's
+  // edges (longer hubs are split); a split hub's pieces are the smallest
+  // power of two, at least 1024, that covers a wavefront's share (at most
+  // `chunk`).
+  const int64_t share = m / ((int64_t)B * W);
+  const int64_t wg_max =
+      std::max<int64_t>(o.chunk, std::min<int64_t>((int64_t)kSweepWaves * o.chunk, share * kSweepWaves));
+  int64_t piece = o.chunk;
+  while (piece > 1024 && piece / 2 >= share) piece /= 2;
+  P.chunk = (int)piece;
   std::vector<int32_t> tidx;
   std::vector<double> tw;
   std::vector<uint8_t> tmask;
@@ -191,7 +201,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     std::vector<int4> mega;  // chunk items of the hubs longer than wg_max
     for (size_t h = 0; h < hubs.size(); ++h, ++i) {
       int64_t L = rptr[i + 1] - rptr[i];
-      int64_t nch = (L + o.chunk - 1) / o.chunk;
+      int64_t nch = (L + piece - 1) / piece;
       int slot = (int)chunks;
       hsplit.push_back(make_int4((int)i, slot, (int)nch, 0));
       if (L > wg_max) msplit.push_back(make_int4((int)i, slot, (int)nch, 0));
@@ -291,7 +301,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
             for (int r = it.y; r < it.z; ++r) c += rounds(rptr[r + 1] - rptr[r], 512) + 0.25;
             return c;
           }
-          case kHeavy: return rounds(std::min<int64_t>(o.chunk, rptr[it.y + 1] - rptr[it.y] - (int64_t)it.z * o.chunk), 512);
+          case kHeavy: return rounds(std::min<int64_t>(piece, rptr[it.y + 1] - rptr[it.y] - (int64_t)it.z * piece), 512);
           case kZero: return 0.25 + (it.z - it.y) / 512.0;
           default: return 1.0;
         }
@@ -378,7 +388,7 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   auto check = [&](const int4 &it) {
     if (it.x == kHeavy)
       return it.y >= 0 && it.y < n && it.w >= 0 && it.w + it.z < chunks &&
-             (int64_t)it.z * o.chunk < (int64_t)(rptr[it.y + 1] - rptr[it.y]);
+             (int64_t)it.z * piece < (int64_t)(rptr[it.y + 1] - rptr[it.y]);
     if (it.x == kHubWG)
       return it.y >= 0 && it.y < n && (int64_t)(rptr[it.y + 1] - rptr[it.y]) > o.chunk &&
              (int64_t)(rptr[it.y + 1] - rptr[it.y]) <= wg_max;
