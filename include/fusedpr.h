@@ -114,8 +114,9 @@ typedef struct pr_graph pr_graph;
 
 typedef struct pr_plan_opts {
   int chunk;             /* lists longer than this (hubs) are summed by several wavefronts:
-                            up to 8 * chunk edges by the 8 wavefronts of one workgroup, longer
-                            ones in chunk-edge pieces, one wavefront each, added by the
+                            up to 8 * chunk edges (and at most one workgroup's share of a
+                            launch) by the 8 wavefronts of one workgroup, longer ones in
+                            pieces of at most chunk edges, one wavefront each, added by the
                             finalize kernel (0 = default: about the edges per wavefront of
                             a sweep launch, a power of two in [1024, 16384]; else [64, 2^20]) */
   int tile_max_row;      /* lists of 1..tile_max_row edges are packed into 512-edge tiles
