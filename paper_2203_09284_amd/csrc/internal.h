@@ -30,7 +30,7 @@ constexpr int kWaves = kBlock / 64;
 #define FPR_SWEEP_BLOCK 512
 #endif
 #ifndef FPR_HOT_KB
-#define FPR_HOT_KB 64
+#define FPR_HOT_KB 70
 #endif
 constexpr int kSweepBlock = FPR_SWEEP_BLOCK;  // threads per workgroup of the sweep
 constexpr int kSweepWaves = kSweepBlock / 64;
