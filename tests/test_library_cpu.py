@@ -119,3 +119,36 @@ def test_error_message_is_thread_local_and_cleared():
     csr, _ = build_csr(4, np.array([0], np.int32), np.array([1], np.int32))
     lib.pr_csr_free(ctypes.byref(csr))
     assert lib.pr_last_error() == b""
+
+
+def _source_lines(folder, exts):
+    for dirpath, _, files in os.walk(os.path.join(ROOT, folder)):
+        if "__pycache__" in dirpath:
+            continue
+        for f in files:
+            if f.endswith(exts):
+                path = os.path.join(dirpath, f)
+                for ln in open(path, errors="replace"):
+                    yield os.path.relpath(path, ROOT), ln
+
+
+def test_product_and_oracle_share_no_code():
+    # The library and its binding never import, include or load the oracle;
+    # the oracle never reaches into the library; the input generators use neither.
+    link = re.compile(r"^\s*(import|from|#\s*include)\b|CDLL|dlopen|\.so\b")
+    for path, ln in _source_lines("paper_2203_09284_amd", (".py", ".hip", ".h", ".cpp")):
+        assert not (link.search(ln) and "oracle" in ln), (path, ln)
+    for folder in ("oracle", "graphgen"):
+        for path, ln in _source_lines(folder, (".py", ".c", ".h")):
+            if link.search(ln):
+                assert "paper_2203_09284_amd" not in ln and "fusedpr" not in ln and "csrc" not in ln, (path, ln)
+    for path, ln in _source_lines("graphgen", (".py",)):
+        assert not (link.search(ln) and "oracle" in ln), (path, ln)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    from paper_2203_09284_amd import _lib as L
+    monkeypatch.setattr(L, "_LIB", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError, match="not built"):
+        L.lib()
