@@ -541,7 +541,8 @@ def main():
     import paper_2203_09284_amd as fpr
     import oracle
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU: the HIP library has no CPU path")
     torch.cuda.set_device(0)
     cores = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()

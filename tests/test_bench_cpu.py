@@ -74,3 +74,14 @@ def test_recorded_traffic_is_dropped_when_the_sources_change(monkeypatch):
     assert bench.traffic_record(key) == rec[key]["bytes_per_sweep"]
     monkeypatch.setattr(bench, "kernel_source_sha", lambda files=bench.KERNEL_SOURCES: "0" * 16)
     assert bench.traffic_record(key) is None
+
+
+def test_no_gpu_is_an_error_not_a_cpu_run():
+    import pytest
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1", "--warmup", "0"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0 and "needs a GPU" in r.stderr
+    assert '"metric"' not in r.stdout
