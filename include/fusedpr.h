@@ -207,7 +207,9 @@ void pr_opts_default(pr_opts *o);
  * are fused into one kernel per sweep.
  *   d        damping factor, 0 < d < 1 (the paper uses 0.85)
  *   tol      > 0;  max_iter >= 1
- *   p        device double[n] teleport vector (finite, >= 0, sum 1), or NULL for 1/n
+ *   p        device double[n] teleport vector (finite, >= 0, sum 1), or NULL for 1/n;
+ *            device memory, so the library does not check it: a p outside this
+ *            contract gives ranks and residuals that mean nothing, with no error
  *   x        device double[n]: start vector if o->warm_start, else ignored on entry;
  *            the ranks on return (sum 1 for uniform dangling)
  *   iters    host: sweeps executed (FP32: FP32 sweeps + FP64 refinement sweeps)
