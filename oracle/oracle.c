@@ -57,7 +57,8 @@ enum { ORC_DANGLING_UNIFORM = 0, ORC_DANGLING_LEAK = 1 };
 
 /* Mutations (0 = none): 1 drop the dangling term, 2 drop the teleport term,
  * 3 use in-degree instead of out-degree, 4 transpose the graph (gather over
- * out-edges), 5 wrong sign in the adjoint's normalisation term. */
+ * out-edges), 5 wrong sign in the adjoint's normalisation term, 6 teleport
+ * 1/n in place of the personalization vector p. */
 static int g_mutation = 0;
 void orc_set_mutation(int m) { g_mutation = m; }
 
@@ -253,7 +254,7 @@ int orc_ec_iterate(int64_t n, const int64_t *in_ptr, const int32_t *in_src, cons
       } else {
         for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) sum += CL[e];
       }
-      double pu = p ? p[u] : inv_n;
+      double pu = (p && g_mutation != 6) ? p[u] : inv_n;
       double teleport = (g_mutation == 2) ? 0.0 : (1.0 - d) * pu;
       x[u] = teleport + d * (sum + D * inv_n);
       delta[u] = fabs(x[u] - prev);

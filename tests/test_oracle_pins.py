@@ -188,6 +188,21 @@ def test_closed_forms(name, n, edges, formula):
         assert np.max(np.abs(x - want)) <= 1e-15 * max(1.0, n * want.max())
 
 
+@pytest.mark.parametrize("n,seed", [(7, 0), (7, 3), (50, 49)])
+def test_one_hot_teleport_on_a_cycle_closed_form(n, seed):
+    # Eq. 1 with p = e_s on the directed cycle v -> v+1: x_u = (1-d)[u=s] + d x_{u-1},
+    # so x_{s+k} = d^k x_s with x_s = (1-d) / (1 - d^n) (the personalized teleport
+    # of batched PageRank; no vertex is dangling)
+    g = oracle.csr(n, *gg.cycle(n))
+    k = (np.arange(n) - seed) % n
+    want = (1 - D) * D ** k / (1 - D ** n)
+    p = np.zeros(n)
+    p[seed] = 1.0
+    for fn in (oracle.pagerank_ec, oracle.pagerank_fused):
+        x, _, _ = fn(g, D, tol=1e-17, max_iter=2000, p=p)
+        assert np.max(np.abs(x - want)) <= 1e-14 * want.max()
+
+
 def test_cycle_converges_after_one_sweep():
     g = oracle.csr(10, *gg.cycle(10))
     x, it, r, tr, sums = oracle.pagerank_ec(g, D, tol=1e-30, max_iter=3, trace=True)
@@ -410,6 +425,12 @@ def _pins_pass():
     xu, _, _ = oracle.pagerank_ec(gu, D, tol=1e-15, max_iter=3000)
     if l1(xu, dense.solve(128, rs, rt, None, D)) > 1e-12:
         return False
+    cs, ct = gg.cycle(9)
+    pc = np.zeros(9)
+    pc[4] = 1.0
+    xc, _, _ = oracle.pagerank_ec(oracle.csr(9, cs, ct), D, tol=1e-17, max_iter=2000, p=pc)
+    if np.max(np.abs(xc - (1 - D) * D ** ((np.arange(9) - 4) % 9) / (1 - D ** 9))) > 1e-14:
+        return False
     lam, gp, gw, _, _ = oracle.adjoint(g, x, gvec, D)
     for v in range(n):
         a, b = g.out_ptr[v], g.out_ptr[v + 1]
@@ -418,7 +439,7 @@ def _pins_pass():
     return True
 
 
-@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6])
 def test_pins_catch_planted_mistakes(mutation):
     assert _pins_pass()
     try:
