@@ -85,3 +85,20 @@ def test_no_gpu_is_an_error_not_a_cpu_run():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0 and "needs a GPU" in r.stderr
     assert '"metric"' not in r.stdout
+
+
+def test_host_thread_scaling_leg():
+    import graphgen as gg
+    import numpy as np
+    import oracle
+    s, t = gg.rmat(10, 8, seed=5)
+    og = oracle.csr(1 << 10, s, t)
+    rows = bench.host_scaling(oracle, og, 1e-10, 4)
+    assert [r["threads"] for r in rows] == [1, 2, 4]
+    _, it_ec, _ = oracle.pagerank_ec(og, bench.D, tol=1e-10, max_iter=1000)
+    _, it_f, _ = oracle.pagerank_fused(og, bench.D, tol=1e-10, max_iter=1000, scaled=True)
+    assert rows[0]["ec_sweeps"] == it_ec and rows[0]["fused_sweeps"] == it_f
+    # the edge-centric form is deterministic at any thread count; the fused one
+    # is asynchronous across threads but still reaches the tolerance
+    assert all(r["ec_sweeps"] == it_ec for r in rows)
+    assert all(1 <= r["fused_sweeps"] < 1000 and np.isfinite(r["fused_speedup_vs_ec"]) for r in rows)
