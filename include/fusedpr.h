@@ -220,7 +220,9 @@ int pr_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, 
              double *x, int *iters, double *resid, void *stream);
 
 /* Exactly `sweeps` sweeps from the x passed in (no convergence test), in the
- * form o->mode and the precision o->precision select.  x is FP64 on entry and
+ * form o->mode and the precision o->precision select: the body of
+ * Algorithm 1's loop (Eq. 2, Jacobi) or of Algorithm 2's (Eq. 9, fused),
+ * without the stop test of Eq. 3.  x is FP64 on entry and
  * on return; FP32 sweeps run on an internal FP32 copy that is cast back after
  * the last sweep (no refinement).  resid (host, nullable) receives the residual
  * of the last sweep.  elapsed_ms (host, nullable) receives the time between
@@ -239,12 +241,14 @@ int pr_iterate(pr_graph *g, double d, const pr_opts *o, const double *p, double 
  *                           one sweep (one per Gauss-Seidel block in the fused
  *                           form; the scatter and the list sums in the
  *                           edge-list form)
- * Measurement support for the sweep of the recurrence above; 1 <= sweeps <= 4096. */
+ * Measurement support for the sweep of the recurrence above (the per-iteration
+ * time the paper compares in Section 6); 1 <= sweeps <= 4096. */
 int pr_profile_sweeps(pr_graph *g, double d, const pr_opts *o, double *x, int sweeps, double *sweep_ms,
                       double *finalize_ms, void *stream);
 
 /* ||F(x) - x||_1 for any device vector x (FP64), where F is one exact
- * application of the recurrence above.  Bounds the error of x:
+ * application of Eq. 1 (one Jacobi sweep, Eq. 2).  Not in the paper: F is a
+ * contraction with factor d in the L1 norm, which bounds the error of x:
  * ||x - x*||_1 <= ||F(x) - x||_1 / (1 - d).  result: host double. */
 int pr_certificate(pr_graph *g, double d, const double *p, const double *x, double *result,
                    void *stream);
@@ -271,8 +275,9 @@ int pr_certificate(pr_graph *g, double d, const double *p, const double *x, doub
 int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter, int k, const int32_t *seeds,
                      int tile, float *X, int *iters, double *resid, void *stream);
 
-/* Autotuner for pr_solve_batched: times the candidate tile widths on this
- * graph and device and returns the fastest in *tile.  When cache_path is not
+/* Autotuner for pr_solve_batched (Eq. 1 with one-hot teleports; not in the
+ * paper, which solves one vector at a time): times the candidate tile widths
+ * on this graph and device and returns the fastest in *tile.  When cache_path is not
  * NULL the choice is read from / appended to that JSON-lines file, keyed by
  * the graph's size signature, k and the device name. */
 int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, int *tile, void *stream);
@@ -280,6 +285,9 @@ int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, int *tile, v
 /* ------------------------------------------------------------------------
  * Adjoint (implicit differentiation of the fixed point).
  *
+ * Not in the paper, which only solves the forward problem: the fixed point
+ * of Eq. 1 is x = (1-d)(I - dP)^{-1} p, so its gradients need one solve with
+ * the transposed operator instead of differentiating through the iterates.
  * For a scalar loss L(x) with dL/dx = g, solves (I - dP)^T lam = g by the
  * transposed Jacobi pull over out-edges, then
  *   dL/dp_u       = (1-d) lam_u
