@@ -152,3 +152,13 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError, match="not built"):
         L.lib()
+
+
+def test_every_compute_entry_point_cites_the_paper():
+    text = open(HEADER).read()
+    cited = {}
+    for m in re.finditer(r"(/\*.*?\*/)\s*(?:[a-z_0-9 ]+\*?\s*)(pr_[a-z_0-9]+)\s*\(", text, flags=re.S):
+        cited[m.group(2)] = bool(re.search(r"Section \d|Eq\. ?\d|Algorithm \d|Fig\. ?\d", m.group(1)))
+    for name in ("pr_build_csr", "pr_graph_create", "pr_solve", "pr_iterate", "pr_profile_sweeps",
+                 "pr_certificate", "pr_solve_batched", "pr_autotune_batched", "pr_adjoint"):
+        assert cited.get(name), name
