@@ -22,7 +22,7 @@ The same JSON line carries, on the same GPU:
   rmat24      R-MAT scale 24 in BFS order: FP32 fused + FP64 refinement
               against plain FP64 Jacobi, with the FP32 sweep's roofline;
   roofline    of the dominant kernel (the fused FP64 sweep at scale 20);
-  cpu_baseline the FP64 CPU oracle (Algorithm 1) timed on the host cores.
+  cpu_baseline the FP64 CPU oracle (Jacobi iteration of Eq. 1) timed on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--quick]
     python bench.py --profile FORM [--workload rmat20|rmat24]   (kernel-only driver
@@ -239,7 +239,7 @@ def leg_batched(torch, fpr, g, n, m, steps):
 def leg_er10k(torch, fpr, oracle, steps, warmup):
     w = workload("er10k")
     og = oracle.csr(w["n"], w["src"], w["dst"])
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=1000)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-15, max_iter=1000)
     g = fpr.Graph(w["n"], w["src"], w["dst"])
     forms = solve_legs(torch, g, g.m, 1e-10, steps, warmup, ["jacobi-fp64", "fused-fp64"], xr)
     g.close()
@@ -257,7 +257,7 @@ def leg_adjoint(torch, fpr, oracle, steps, warmup, threads):
     t_a, (lam, gp, gw, it2, _) = timed(torch, lambda: g.adjoint(x, gdev, d=D, tol=1e-12), steps, warmup)
     log("adjoint rmat18w: forward %.3f ms (%d sweeps), adjoint+grads %.3f ms (%d sweeps)" % (t_f, it, t_a, it2))
     og = oracle.csr(n, w["src"], w["dst"], w["w"])
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=2000, threads=threads)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-15, max_iter=2000, threads=threads)
     lam_o, gp_o, gw_o, _, _ = oracle.adjoint(og, xr, gvec, D, tol=1e-14)
     rel = lambda a, b: float(np.abs(a.cpu().numpy() - b).sum() / np.abs(b).sum())
     out = dict(workload="rmat18w", n=n, m=g.m, tol=1e-12, forward_ms=t_f, forward_sweeps=it,
@@ -339,20 +339,21 @@ def leg_rmat24(torch, fpr, steps, warmup):
 
 def host_scaling(oracle, og, tol, cores):
     """The paper's host comparison (Section 6.3, its thread-scaling figure) on
-    this box: edge-centric Algorithm 1 (Seq-EC / Par-EC) against the fused loop
-    (Seq-FusEd / Par-FusEd, mass-scaled, in place and asynchronous across
-    threads), FP64, same graph and stop rule, for 1..cores threads."""
+    this box: the oracle's Jacobi iteration (the baseline's numbers, Seq-EC /
+    Par-EC) against its in-place Eq. 9 loop (Seq-FusEd / Par-FusEd, mass-scaled,
+    asynchronous across threads), FP64, same graph and stop rule, for
+    1..cores threads."""
     out = []
     counts = [k for k in (1, 2, 4, 8, 12, 16, 20) if k <= cores]
     for th in counts:
         t0 = time.perf_counter()
-        _, it_ec, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=1000, threads=th)
+        _, it_ec, _ = oracle.jacobi(og, D, tol=tol, max_iter=1000, threads=th)
         t_ec = time.perf_counter() - t0
         t0 = time.perf_counter()
         if th == 1:
-            _, it_f, _ = oracle.pagerank_fused(og, D, tol=tol, max_iter=1000, scaled=True)
+            _, it_f, _ = oracle.gauss_seidel(og, D, tol=tol, max_iter=1000, scaled=True)
         else:
-            _, it_f, _ = oracle.pagerank_fused_par(og, D, tol=tol, max_iter=1000, scaled=True, threads=th)
+            _, it_f, _ = oracle.gauss_seidel_threads(og, D, tol=tol, max_iter=1000, scaled=True, threads=th)
         t_f = time.perf_counter() - t0
         out.append(dict(threads=th, ec_s=sig(t_ec, 4), ec_sweeps=it_ec, fused_s=sig(t_f, 4), fused_sweeps=it_f,
                         fused_speedup_vs_ec=sig(t_ec / t_f, 4)))
@@ -556,7 +557,7 @@ def main():
     m = g.m
     log("graph on device: m'=%d items=%d grid=%d setup %.1fs" % (m, st["n_items"], st["grid"], setup_s))
     og = oracle.csr(n, w["src"], w["dst"])
-    x_ref, _, _ = oracle.pagerank_ec(og, D, tol=1e-13, max_iter=1000, threads=cores)
+    x_ref, _, _ = oracle.jacobi(og, D, tol=1e-13, max_iter=1000, threads=cores)
 
     forms = solve_legs(torch, g, m, tol, args.steps, args.warmup,
                        ["jacobi-fp64", "fused-fp64", "fused-fp64-unscaled", "jacobi-fp32", "fused-fp32",
@@ -581,20 +582,20 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        # the oracle as it stands: Algorithm 1 with contributionList/offsetList,
-        # FP64, the same graph and tolerance; median of three full solves
+        # the oracle as it stands: its Jacobi iteration of Eq. 1, FP64, the
+        # same graph and tolerance; median of three full solves
         runs = []
         for _ in range(3):
             t0 = time.perf_counter()
-            _, it_cpu, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=1000, threads=cores)
+            _, it_cpu, _ = oracle.jacobi(og, D, tol=tol, max_iter=1000, threads=cores)
             runs.append(time.perf_counter() - t0)
         cpu_s = float(np.median(runs))
         t0 = time.perf_counter()
-        _, it1, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=1000, threads=1)
+        _, it1, _ = oracle.jacobi(og, D, tol=tol, max_iter=1000, threads=1)
         one_s = time.perf_counter() - t0
         cpu = dict(value=sig(og.m * it_cpu / cpu_s / 1e9), unit="GTEPS", cores=cores, kind="oracle",
-                   sample="full solve of the same R-MAT-20 graph to L1<%g (%d sweeps): Algorithm 1 with "
-                          "contributionList and offsetList, FP64, median of 3 runs of %.2f s on %d threads; "
+                   sample="full solve of the same R-MAT-20 graph to L1<%g (%d sweeps): the oracle's Jacobi "
+                          "iteration of Eq. 1, FP64, median of 3 runs of %.2f s on %d threads; "
                           "1 thread: %.2f s" % (tol, it_cpu, cpu_s, cores, one_s),
                    single_thread_gteps=sig(og.m * it1 / one_s / 1e9))
         cpu["cpu_model"], cpu["nproc"] = host_cpu()

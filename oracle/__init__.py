@@ -4,16 +4,18 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library
 (``paper_2203_09284_amd``) and never imports it.
 
-``oracle.c`` holds the arithmetic (edge-centric Algorithm 1, loop-fused
-Algorithm 2, F(x), the adjoint); ``dense.py`` holds the dense-matrix checks for
+``oracle.c`` holds the arithmetic (the Jacobi iteration of Eq. 1, the in-place
+Gauss-Seidel recurrence of Eq. 9 that the loop-fused algorithm computes, F(x)
+and its residual, the adjoint); ``dense.py`` holds the dense-matrix checks for
 graphs of at most a few thousand vertices.  This module only marshals
 arguments.
 
 Parity pins (tests/test_oracle_pins.py): dense solve, closed forms, the
 sum(x) = 1 invariant, the contraction bound, the DAG forward-substitution case,
-brute-force adjacency sets, Eq. 9 written as a direct Gauss-Seidel recurrence,
-the offsetList example of Section 3, finite differences and the duality /
-homogeneity identities of the adjoint.
+brute-force adjacency sets, Eq. 9 and Eq. 2 written as small pure-Python loops,
+the offsetList example of Section 3, the edge-list residual against a dense
+F(x), finite differences and the duality / homogeneity identities of the
+adjoint.
 """
 from __future__ import annotations
 
@@ -58,19 +60,19 @@ def _lib():
     lib.orc_csr_count.restype = i64
     lib.orc_csr_build.argtypes = [i64, i64, vp, vp, vp] + [vp] * 10
     lib.orc_csr_build.restype = cint
-    lib.orc_ec_iterate.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint,
-                                   cint, cint, vp, vp, vp, vp]
-    lib.orc_ec_iterate.restype = cint
-    lib.orc_fused_iterate.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint,
-                                      cint, cint, vp, vp, vp]
-    lib.orc_fused_iterate.restype = cint
-    lib.orc_fused_par_iterate.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint, cint, cint,
-                                          vp, vp]
-    lib.orc_fused_par_iterate.restype = cint
+    lib.orc_jacobi.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint,
+                               cint, cint, vp, vp, vp, vp]
+    lib.orc_jacobi.restype = cint
+    lib.orc_gauss_seidel.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint,
+                                     cint, cint, vp, vp, vp]
+    lib.orc_gauss_seidel.restype = cint
+    lib.orc_gauss_seidel_threads.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, cint,
+                                             cint, cint, vp, vp]
+    lib.orc_gauss_seidel_threads.restype = cint
     lib.orc_apply_F.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, dbl, cint, vp, vp]
     lib.orc_apply_F.restype = cint
-    lib.orc_apply_F_rows.argtypes = [i64, vp, vp, vp, vp, vp, dbl, dbl, vp, i64, vp, vp]
-    lib.orc_apply_F_rows.restype = cint
+    lib.orc_residual_edges.argtypes = [i64, i64, vp, vp, vp, vp, dbl, vp, vp, cint]
+    lib.orc_residual_edges.restype = dbl
     lib.orc_adjoint.argtypes = [i64, vp, vp, vp, vp, vp, vp, dbl, dbl, cint, vp, vp, vp, vp]
     lib.orc_adjoint.restype = cint
     lib.orc_sample_in_lists.argtypes = [i64, i64, vp, vp, i64, vp, i64, vp, vp]
@@ -151,69 +153,73 @@ def csr(n: int, src, dst, w=None) -> Graph:
                  in_deg, edge_map[:m_in])
 
 
-def pagerank_ec(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int = 1000, p=None,
-                x0=None, norm: str = "l1", dangling: str = "uniform", threads: int = 1,
-                trace: bool = False):
-    """Algorithm 1 (edge-centric Jacobi).  Returns (x, sweeps, residual[, trace, sums])."""
-    x = np.full(g.n, 1.0 / g.n) if x0 is None else np.array(x0, np.float64, copy=True)
-    if x0 is None and p is not None:
-        x = np.array(p, np.float64, copy=True)
+def _start(g: Graph, p, x0):
+    if x0 is not None:
+        return np.array(x0, np.float64, copy=True)
+    if p is not None:
+        return np.array(p, np.float64, copy=True)
+    return np.full(g.n, 1.0 / g.n)
+
+
+def jacobi(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int = 1000, p=None,
+           x0=None, norm: str = "l1", dangling: str = "uniform", threads: int = 1,
+           trace: bool = False):
+    """x <- F(x) until the residual is below tol (Eq. 1 / Eq. 2).
+    Returns (x, sweeps, residual[, trace, sums])."""
+    x = _start(g, p, x0)
     p = None if p is None else np.ascontiguousarray(p, np.float64)
     res = np.zeros(1)
     tr = np.zeros(max_iter) if trace else None
     sm = np.zeros(max_iter) if trace else None
-    it = _lib().orc_ec_iterate(g.n, _p(g.in_ptr), _p(g.in_src), _p(g.in_w), _p(g.out_ptr),
-                               _p(g.out_w), _p(g.offset), _p(g.out_deg), _p(g.in_deg), _p(p), d,
-                               tol, max_iter, NORM[norm], DANGLING[dangling], threads, _p(x),
-                               _p(res), _p(tr), _p(sm))
+    it = _lib().orc_jacobi(g.n, _p(g.in_ptr), _p(g.in_src), _p(g.in_w), _p(g.out_ptr),
+                           _p(g.out_dst), _p(g.out_w), _p(g.out_deg), _p(g.in_deg), _p(p), d,
+                           tol, max_iter, NORM[norm], DANGLING[dangling], threads, _p(x),
+                           _p(res), _p(tr), _p(sm))
     if it < 0:
-        raise MemoryError("orc_ec_iterate")
+        raise MemoryError("orc_jacobi")
     if trace:
         return x, it, float(res[0]), tr[:it], sm[:it]
     return x, it, float(res[0])
 
 
-def pagerank_fused(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int = 1000, p=None,
-                   x0=None, norm: str = "l1", dangling: str = "uniform", trace: bool = False,
-                   scaled: bool = False):
-    """Algorithm 2, strict ascending order (Seq-FusEd); scaled=True is the
+def gauss_seidel(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int = 1000, p=None,
+                 x0=None, norm: str = "l1", dangling: str = "uniform", trace: bool = False,
+                 scaled: bool = False):
+    """Eq. 9 in place, ascending vertex order (Seq-FusEd); scaled=True is the
     mass-scaled variant.  Returns (x, sweeps, residual[, trace])."""
-    x = np.full(g.n, 1.0 / g.n) if x0 is None else np.array(x0, np.float64, copy=True)
-    if x0 is None and p is not None:
-        x = np.array(p, np.float64, copy=True)
+    x = _start(g, p, x0)
     p = None if p is None else np.ascontiguousarray(p, np.float64)
     res = np.zeros(1)
     tr = np.zeros(max_iter) if trace else None
-    it = _lib().orc_fused_iterate(g.n, _p(g.in_ptr), _p(g.in_src), _p(g.in_w), _p(g.out_ptr),
-                                  _p(g.out_w), _p(g.offset), _p(g.out_deg), _p(p), d, tol,
-                                  max_iter, NORM[norm], DANGLING[dangling], int(scaled), _p(x),
-                                  _p(res), _p(tr))
+    it = _lib().orc_gauss_seidel(g.n, _p(g.in_ptr), _p(g.in_src), _p(g.in_w), _p(g.out_ptr),
+                                 _p(g.out_w), _p(g.out_deg), _p(p), d, tol, max_iter, NORM[norm],
+                                 DANGLING[dangling], int(scaled), _p(x), _p(res), _p(tr))
     if it == -2:
         raise ValueError("the mass-scaled variant needs uniform dangling and the L1 norm")
     if it < 0:
-        raise MemoryError("orc_fused_iterate")
+        raise MemoryError("orc_gauss_seidel")
     if trace:
         return x, it, float(res[0]), tr[:it]
     return x, it, float(res[0])
 
 
-def pagerank_fused_par(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int = 1000, p=None,
-                       x0=None, dangling: str = "uniform", scaled: bool = True, threads: int = 1):
-    """The paper's parallel fused variant (Section 6.3) on `threads` host
+def gauss_seidel_threads(g: Graph, d: float = 0.85, tol: float = 1e-10, max_iter: int = 1000,
+                         p=None, x0=None, dangling: str = "uniform", scaled: bool = True,
+                         threads: int = 1):
+    """The paper's parallel fused variant (Sections 4.3, 6.3) on `threads` host
     threads, in place and asynchronous across threads; host timing only.
     Returns (x, sweeps, residual)."""
-    x = np.full(g.n, 1.0 / g.n) if x0 is None else np.array(x0, np.float64, copy=True)
-    if x0 is None and p is not None:
-        x = np.array(p, np.float64, copy=True)
+    x = _start(g, p, x0)
     p = None if p is None else np.ascontiguousarray(p, np.float64)
     res = np.zeros(1)
-    it = _lib().orc_fused_par_iterate(g.n, _p(g.in_ptr), _p(g.out_ptr), _p(g.out_w), _p(g.offset),
-                                      _p(g.out_deg), _p(p), d, tol, max_iter, DANGLING[dangling],
-                                      int(scaled), int(threads), _p(x), _p(res))
+    it = _lib().orc_gauss_seidel_threads(g.n, _p(g.in_ptr), _p(g.in_src), _p(g.in_w),
+                                         _p(g.out_ptr), _p(g.out_w), _p(g.out_deg), _p(p), d, tol,
+                                         max_iter, DANGLING[dangling], int(scaled), int(threads),
+                                         _p(x), _p(res))
     if it == -2:
         raise ValueError("the mass-scaled variant needs uniform dangling")
     if it < 0:
-        raise MemoryError("orc_fused_par_iterate")
+        raise MemoryError("orc_gauss_seidel_threads")
     return x, it, float(res[0])
 
 
@@ -271,13 +277,21 @@ def sample_in_lists(n: int, src, dst, rows):
     return out
 
 
-def apply_F_rows(g_n: int, in_ptr, in_src, in_w, W, p, d: float, D: float, x, rows):
-    """F(x) at the given rows only (sampled checks), from caller-held oracle arrays."""
-    rows = np.ascontiguousarray(rows, np.int32)
-    y = np.zeros(len(rows))
+def residual_edges(n: int, src, dst, x, d: float = 0.85, p=None, w=None, threads: int = 1,
+                   want_F: bool = False):
+    """||F(x) - x||_1 from the raw edge list (self-loops skipped; each (src, dst)
+    pair must appear once), with no graph built.  ||x - x*||_1 is at most this
+    / (1 - d).  Returns the residual, or (residual, F(x)) with want_F."""
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
     x = np.ascontiguousarray(x, np.float64)
-    W = np.ascontiguousarray(W, np.float64)
+    w = None if w is None else np.ascontiguousarray(w, np.float64)
     p = None if p is None else np.ascontiguousarray(p, np.float64)
-    _lib().orc_apply_F_rows(g_n, _p(in_ptr), _p(in_src), _p(in_w), _p(W), _p(p), d, D, _p(x),
-                            len(rows), _p(rows), _p(y))
-    return y
+    if len(src) != len(dst) or len(x) != n or (w is not None and len(w) != len(src)):
+        raise ValueError("edge list / vector sizes disagree")
+    y = np.zeros(n) if want_F else None
+    r = _lib().orc_residual_edges(n, len(src), _p(src), _p(dst), _p(w), _p(p), d, _p(x), _p(y),
+                                  int(threads))
+    if r != r:
+        raise MemoryError("orc_residual_edges")
+    return (float(r), y) if want_F else float(r)

@@ -13,30 +13,35 @@
  * paper's recurrence (Section 1, Eq. 1) with the dangling mass D spread
  * uniformly, D = sum of x over dangling vertices.
  *
- * Data structures follow the paper's edge-centric baseline (Section 3):
+ * The canonical graph follows the paper's edge-centric baseline (Section 3):
  *   - inList  : edges grouped by destination (destinations ascending), sources
- *               ascending within a destination.  Position e of this order is
- *               slot e of the contributionList (CL).
+ *               ascending within a destination; position e of this order is
+ *               slot e of the paper's contributionList.
  *   - outList : edges grouped by source, destinations ascending.
- *   - offsetList[e_out] = CL slot of the same (src, dst) edge (Section 3, the
- *               offsetList/contributionList example and Fig. 1).
+ *   - offsetList[e_out] = contributionList slot of the same (src, dst) edge
+ *               (Section 3, the offsetList/contributionList example, Fig. 1).
+ * The iterations are written from the equations, not from the paper's
+ * listings: they pull share_v = x_v / W_v over each inList.  The numbers they
+ * add, and the order they add them in, are the ones the edge-centric layout
+ * stores and sums.
  *
  * Routines (each names the passage it follows):
  *   orc_csr_count / orc_csr_build  canonical graph: self-loops dropped, repeated
  *                                  (src, dst) pairs merged, their weights summed in
- *                                  input order.
- *   orc_ec_iterate   Algorithm 1 (edge-centric Jacobi): phase 1 scatters
- *                    x_v / W_v into CL through offsetList, phase 2 sums each
- *                    vertex's contiguous CL slice and applies the update.
- *   orc_fused_par_iterate the parallel variant (Section 6.3), host timing only.
- *   orc_fused_iterate Algorithm 2 (loop-fused): CL primed once, then one loop
- *                    that pulls, updates, and immediately scatters the new
- *                    contribution, in ascending vertex order (Seq-FusEd,
- *                    Section 6.3), which is Gauss-Seidel as in Eq. 9; plus a
- *                    mass-scaled variant (see the function).
- *   orc_apply_F      one application of F (for residual certificates).
- *   orc_adjoint      transposed fixed point (I - dP)^T lam = g and the
- *                    gradients dL/dp = (1-d) lam, dL/dw.
+ *                                  input order; offsetList.
+ *   orc_jacobi        x <- F(x) (Eq. 1, per iteration Eq. 2): the fixed point's
+ *                     plain definition iterated.
+ *   orc_gauss_seidel  Eq. 9 in place, ascending vertex order (Seq-FusEd of
+ *                     Section 6.3, the loop-fused form of Section 4); plus a
+ *                     mass-scaled variant (see the function).
+ *   orc_gauss_seidel_threads  the parallel loop-fused variant (Sections 4.3 and
+ *                     6.3), host timing only.
+ *   orc_apply_F       one application of F (certificates).
+ *   orc_residual_edges ||F(x) - x||_1 from a plain edge list, no graph built
+ *                     (certificates at sizes the CSR build cannot reach quickly).
+ *   orc_adjoint       transposed fixed point (I - dP)^T lam = g and the
+ *                     gradients dL/dp = (1-d) lam, dL/dw.
+ *   orc_sample_in_lists  brute-force in-neighbour lists of chosen rows.
  *
  * The paper is silent on dangling vertices, uses the max-norm for its stop
  * rule (Eq. 3), and stops on error <= threshold.  This oracle spreads dangling
@@ -169,9 +174,17 @@ int orc_csr_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, 
   return 0;
 }
 
-/* ----------------------------------------------------- helpers -------- */
+/* ------------------------------------------------ Eq. 1 pieces -------- */
+/*
+ * Notation (Section 1, Eq. 1, with the dangling reading described above):
+ *   W_v      out-weight sum of v (out-degree when unweighted), summed in
+ *            outList order;
+ *   share_v  x_v / W_v, the rank v passes along each unit of out-weight
+ *            (0 for a dangling vertex: its mass travels through D instead);
+ *   D        total rank of the dangling vertices, spread as D/n everywhere;
+ *   F(x)_u = (1-d) p_u + d ( sum_{v->u} w(v->u) share_v + D/n ).
+ */
 
-/* W(v): out-weight sum (out-degree when unweighted), summed in outList order. */
 static void out_weight_sums(int64_t n, const int64_t *out_ptr, const double *out_w,
                             const int32_t *out_deg, double *W) {
   for (int64_t v = 0; v < n; ++v) {
@@ -200,251 +213,225 @@ static double chunked_sum(int64_t n, const double *vals) {
   return s;
 }
 
-static double dangling_mass(int64_t n, const double *x, const double *W) {
+static double dangling_total(int64_t n, const double *x, const double *W) {
   double D = 0.0;
   for (int64_t v = 0; v < n; ++v)
     if (W[v] == 0.0) D += x[v];
   return D;
 }
 
-/* ------------------------------------------------ Algorithm 1 --------- */
+static double plain_sum(int64_t n, const double *x) {
+  double s = 0.0;
+  for (int64_t v = 0; v < n; ++v) s += x[v];
+  return s;
+}
+
+/* sum_{v->u} w(v->u) share_v over u's inList (sources ascending). */
+static double pulled(int64_t u, const int64_t *in_ptr, const int32_t *in_src, const double *in_w,
+                     const double *share) {
+  double acc = 0.0;
+  for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e)
+    acc += in_w ? share[in_src[e]] * in_w[e] : share[in_src[e]];
+  return acc;
+}
+
+/* --------------------------------------------- Jacobi (Eq. 1 / Eq. 2) --- */
 /*
- * Edge-centric Jacobi (Algorithm 1).  x holds the start vector on entry and
- * the last iterate on exit.  p: personalization (nullable => 1/n).
- * trace (nullable, max_iter entries): residual after each sweep.
- * sums (nullable, max_iter entries): sum of x after each sweep.
- * Returns the number of sweeps executed; *res gets the last residual.
+ * The plain definition: x^{k+1} = F(x^k), every component computed from the
+ * previous iterate only (the edge-centric baseline of Section 3 computes
+ * exactly these numbers: the contributions it stores per edge are
+ * w(v->u) share_v, and it sums each vertex's slice in inList order).  Stops
+ * when the residual ||x^{k+1} - x^k|| (L1, or max-norm as Eq. 3) is below tol,
+ * or after max_iter sweeps.
+ *   x       start vector on entry, last iterate on exit
+ *   p       personalization (nullable => 1/n)
+ *   threads OpenMP threads over vertices (0 = the runtime's default); the
+ *           result does not depend on it
+ *   trace   (nullable, max_iter entries) residual after each sweep
+ *   sums    (nullable, max_iter entries) sum of x after each sweep
+ * Returns the sweeps executed (-1 on allocation failure); *res = last residual.
  */
-int orc_ec_iterate(int64_t n, const int64_t *in_ptr, const int32_t *in_src, const double *in_w,
-                   const int64_t *out_ptr, const double *out_w, const int64_t *offset,
-                   const int32_t *out_deg, const int32_t *in_deg, const double *p, double d,
-                   double tol, int max_iter, int norm, int dangling, int threads, double *x,
-                   double *res, double *trace, double *sums) {
+int orc_jacobi(int64_t n, const int64_t *in_ptr, const int32_t *in_src, const double *in_w,
+               const int64_t *out_ptr, const int32_t *out_dst, const double *out_w,
+               const int32_t *out_deg, const int32_t *in_deg, const double *p, double d,
+               double tol, int max_iter, int norm, int dangling, int threads, double *x,
+               double *res, double *trace, double *sums) {
   if (threads > 0) omp_set_num_threads(threads);
-  int64_t mu = in_ptr[n];
-  double *CL = (double *)malloc(sizeof(double) * (size_t)(mu > 0 ? mu : 1));
   double *W = (double *)malloc(sizeof(double) * (size_t)n);
-  double *delta = (double *)malloc(sizeof(double) * (size_t)n);
-  if (!CL || !W || !delta) { free(CL); free(W); free(delta); return -1; }
+  double *share = (double *)malloc(sizeof(double) * (size_t)n);
+  double *y = (double *)malloc(sizeof(double) * (size_t)n);
+  double *change = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!W || !share || !y || !change) { free(W); free(share); free(y); free(change); return -1; }
   out_weight_sums(n, out_ptr, out_w, out_deg, W);
   if (g_mutation == 3)
     for (int64_t v = 0; v < n; ++v) W[v] = (double)in_deg[v];
   const double inv_n = 1.0 / (double)n;
-  int it = 0;
+  int sweeps = 0;
   double r = INFINITY;
-  while (it < max_iter) {
-    /* dangling mass of the current iterate */
-    double D = (dangling == ORC_DANGLING_UNIFORM && g_mutation != 1) ? dangling_mass(n, x, W) : 0.0;
-    /* phase 1: contribution of every vertex into its CL slots */
+  while (sweeps < max_iter) {
+    const double D = (dangling == ORC_DANGLING_UNIFORM && g_mutation != 1) ? dangling_total(n, x, W) : 0.0;
 #pragma omp parallel for schedule(static)
-    for (int64_t v = 0; v < n; ++v) {
-      if (W[v] == 0.0) continue;
-      double contribution = x[v] / W[v];
-      for (int64_t e = out_ptr[v]; e < out_ptr[v + 1]; ++e)
-        CL[offset[e]] = out_w ? contribution * out_w[e] : contribution;
-    }
-    /* phase 2: contiguous pull, update, per-vertex error */
+    for (int64_t v = 0; v < n; ++v) share[v] = W[v] != 0.0 ? x[v] / W[v] : 0.0;
 #pragma omp parallel for schedule(static)
     for (int64_t u = 0; u < n; ++u) {
-      double prev = x[u];
-      double sum = 0.0;
+      double acc;
       if (g_mutation == 4) {
-        /* planted mistake: gathers over out-edges (transposed operand) */
-        for (int64_t e = out_ptr[u]; e < out_ptr[u + 1]; ++e) sum += CL[e];
+        /* planted mistake: the transposed operand (out-neighbours) */
+        acc = 0.0;
+        for (int64_t e = out_ptr[u]; e < out_ptr[u + 1]; ++e)
+          acc += out_w ? share[out_dst[e]] * out_w[e] : share[out_dst[e]];
       } else {
-        for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) sum += CL[e];
+        acc = pulled(u, in_ptr, in_src, in_w, share);
       }
-      double pu = (p && g_mutation != 6) ? p[u] : inv_n;
-      double teleport = (g_mutation == 2) ? 0.0 : (1.0 - d) * pu;
-      x[u] = teleport + d * (sum + D * inv_n);
-      delta[u] = fabs(x[u] - prev);
+      const double pu = (p && g_mutation != 6) ? p[u] : inv_n;
+      const double teleport = (g_mutation == 2) ? 0.0 : (1.0 - d) * pu;
+      y[u] = teleport + d * (acc + D * inv_n);
+      change[u] = fabs(y[u] - x[u]);
     }
-    ++it;
+    memcpy(x, y, sizeof(double) * (size_t)n);
+    ++sweeps;
     if (norm == ORC_NORM_LINF) {
       r = 0.0;
-      for (int64_t u = 0; u < n; ++u) r = delta[u] > r ? delta[u] : r;
+      for (int64_t u = 0; u < n; ++u) r = change[u] > r ? change[u] : r;
     } else {
-      r = chunked_sum(n, delta);
+      r = chunked_sum(n, change);
     }
-    if (trace) trace[it - 1] = r;
-    if (sums) sums[it - 1] = chunked_sum(n, x);
+    if (trace) trace[sweeps - 1] = r;
+    if (sums) sums[sweeps - 1] = chunked_sum(n, x);
     if (r < tol) break;
   }
   *res = r;
-  free(CL); free(W); free(delta);
-  return it;
+  free(W); free(share); free(y); free(change);
+  return sweeps;
 }
 
-/* ------------------------------------------------ Algorithm 2 --------- */
+/* ------------------------------------- Gauss-Seidel (Eq. 9, in place) --- */
 /*
- * Loop-fused edge-centric PageRank (Algorithm 2) in strict ascending vertex
- * order (Seq-FusEd).  CL is primed once from the start vector; each vertex's
- * new contribution overwrites its CL slots right after its update, so later
- * vertices read it in the same sweep (Eq. 9).
+ * The loop-fused form of Section 4 reaches a vertex's new rank before the
+ * vertices after it are pulled, so u reads x^{k+1}_v for in-neighbours v < u
+ * and x^k_v for v >= u (Eq. 9), vertices taken in ascending id (Seq-FusEd).
+ * Here x and share are overwritten in place, which is that recurrence.
  *
- * scaled = 0: the dangling mass is kept live (recomputed at the start of each
- *   sweep, adjusted as dangling vertices update) -- Gauss-Seidel on the full
- *   column-stochastic matrix.
+ * scaled = 0: the dangling total is recomputed at the start of each sweep and
+ *   kept current as dangling vertices change (Gauss-Seidel on the full
+ *   column-stochastic matrix).
  * scaled = 1: mass-scaled variant.  A Gauss-Seidel sweep does not conserve
- *   sum(x), and that drift is its slowest error mode.  Here the dangling mass D
- *   and the total mass S are taken from the previous sweep and the teleport
- *   term is scaled by S:  x_u <- (1-d) p_u S + d (sum + D/n).  Dividing the
- *   iterates by S turns this into Gauss-Seidel followed by renormalisation to
- *   sum 1 (the fixed point's sum when p sums to 1), so the fixed point is the
- *   same.  The residual is the bound (||x' - x||_1 + |S' - S|) / S on the step
- *   of the normalised iterates, and x is normalised on exit.  Needs uniform
- *   dangling and the L1 norm.
+ *   sum(x), and that drift is its slowest error mode.  Here D and the total
+ *   mass S are the previous sweep's and the teleport term is scaled by S:
+ *   x_u <- (1-d) p_u S + d (pulled + D/n).  Dividing the iterates by S turns
+ *   this into Gauss-Seidel followed by renormalisation to sum 1 (the fixed
+ *   point's sum when p sums to 1), so the fixed point is unchanged.  The
+ *   residual is (||x' - x||_1 + |S' - S|) / S, a bound on the step of the
+ *   normalised iterates, and x is normalised on exit.  Needs uniform dangling
+ *   and the L1 norm.
  */
-int orc_fused_iterate(int64_t n, const int64_t *in_ptr, const int32_t *in_src, const double *in_w,
-                      const int64_t *out_ptr, const double *out_w, const int64_t *offset,
-                      const int32_t *out_deg, const double *p, double d, double tol,
-                      int max_iter, int norm, int dangling, int scaled, double *x, double *res,
-                      double *trace) {
-  (void)in_src; (void)in_w;
+int orc_gauss_seidel(int64_t n, const int64_t *in_ptr, const int32_t *in_src, const double *in_w,
+                     const int64_t *out_ptr, const double *out_w, const int32_t *out_deg,
+                     const double *p, double d, double tol, int max_iter, int norm, int dangling,
+                     int scaled, double *x, double *res, double *trace) {
   const int uniform = (dangling == ORC_DANGLING_UNIFORM);
   if (scaled && (!uniform || norm != ORC_NORM_L1)) return -2;
-  int64_t mu = in_ptr[n];
-  double *CL = (double *)malloc(sizeof(double) * (size_t)(mu > 0 ? mu : 1));
   double *W = (double *)malloc(sizeof(double) * (size_t)n);
-  if (!CL || !W) { free(CL); free(W); return -1; }
+  double *share = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!W || !share) { free(W); free(share); return -1; }
   out_weight_sums(n, out_ptr, out_w, out_deg, W);
+  for (int64_t v = 0; v < n; ++v) share[v] = W[v] != 0.0 ? x[v] / W[v] : 0.0;
   const double inv_n = 1.0 / (double)n;
-  for (int64_t v = 0; v < n; ++v) {
-    if (W[v] == 0.0) continue;
-    double contribution = x[v] / W[v];
-    for (int64_t e = out_ptr[v]; e < out_ptr[v + 1]; ++e)
-      CL[offset[e]] = out_w ? contribution * out_w[e] : contribution;
-  }
-  int it = 0;
+  int sweeps = 0;
   double r = INFINITY;
-  while (it < max_iter) {
-    double D = uniform ? dangling_mass(n, x, W) : 0.0;
-    double S = 1.0;
-    if (scaled) {
-      S = 0.0;
-      for (int64_t v = 0; v < n; ++v) S += x[v];
-    }
+  while (sweeps < max_iter) {
+    double D = uniform ? dangling_total(n, x, W) : 0.0;
+    const double S = scaled ? plain_sum(n, x) : 1.0;
     double l1 = 0.0, linf = 0.0;
     for (int64_t u = 0; u < n; ++u) {
-      double prev = x[u];
-      double sum = 0.0;
-      for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) sum += CL[e];
-      double pu = p ? p[u] : inv_n;
-      double xn = (1.0 - d) * pu * S + d * (sum + D * inv_n);
+      const double acc = pulled(u, in_ptr, in_src, in_w, share);
+      const double pu = p ? p[u] : inv_n;
+      const double xn = (1.0 - d) * pu * S + d * (acc + D * inv_n);
+      const double step = fabs(xn - x[u]);
       if (W[u] == 0.0) {
-        if (uniform && !scaled) D += xn - prev;
+        if (uniform && !scaled) D += xn - x[u];
       } else {
-        double contribution = xn / W[u];
-        for (int64_t e = out_ptr[u]; e < out_ptr[u + 1]; ++e)
-          CL[offset[e]] = out_w ? contribution * out_w[e] : contribution;
+        share[u] = xn / W[u];
       }
       x[u] = xn;
-      double dl = fabs(xn - prev);
-      l1 += dl;
-      if (dl > linf) linf = dl;
+      l1 += step;
+      if (step > linf) linf = step;
     }
-    ++it;
-    if (scaled) {
-      double S2 = 0.0;
-      for (int64_t v = 0; v < n; ++v) S2 += x[v];
-      r = (l1 + fabs(S2 - S)) / S;
-    } else {
-      r = (norm == ORC_NORM_LINF) ? linf : l1;
-    }
-    if (trace) trace[it - 1] = r;
+    ++sweeps;
+    r = scaled ? (l1 + fabs(plain_sum(n, x) - S)) / S : (norm == ORC_NORM_LINF ? linf : l1);
+    if (trace) trace[sweeps - 1] = r;
     if (r < tol) break;
   }
   if (scaled) {
-    double S = 0.0;
-    for (int64_t v = 0; v < n; ++v) S += x[v];
+    const double S = plain_sum(n, x);
     for (int64_t v = 0; v < n; ++v) x[v] /= S;
   }
   *res = r;
-  free(CL); free(W);
-  return it;
+  free(W); free(share);
+  return sweeps;
 }
 
 /*
- * Par-FusEd: the paper's parallel loop-fused variant (Section 6.3), for host
- * timing only (never a parity reference).  The vertices are split statically
- * over `threads` OpenMP threads; each thread runs the loop of Algorithm 2 over
- * its range in ascending order, in place on the shared contributionList, so a
- * thread reads whatever value another thread last wrote (relaxed atomic loads
- * and stores: a value is old or new, never torn).  The dangling mass is taken
- * at the start of each sweep; `scaled` selects the mass-scaled form described
- * above.  With one thread and scaled = 1 it computes what orc_fused_iterate
- * computes with scaled = 1.  L1 residual only.
+ * Par-FusEd: the paper's parallel loop-fused variant (Sections 4.3 and 6.3),
+ * for host timing only (never a parity reference).  The vertices are split
+ * statically over `threads` OpenMP threads; each thread applies Eq. 9 to its
+ * own range in ascending order, in place on the shared share[] array, so it
+ * reads whatever value another thread last stored (relaxed atomic loads and
+ * stores: a value is old or new, never torn).  D is the one at the start of
+ * each sweep; `scaled` selects the mass-scaled form described above.  With one
+ * thread and scaled = 1 it computes what orc_gauss_seidel computes with
+ * scaled = 1.  L1 residual only.
  */
-int orc_fused_par_iterate(int64_t n, const int64_t *in_ptr, const int64_t *out_ptr,
-                          const double *out_w, const int64_t *offset, const int32_t *out_deg,
-                          const double *p, double d, double tol, int max_iter, int dangling,
-                          int scaled, int threads, double *x, double *res) {
+int orc_gauss_seidel_threads(int64_t n, const int64_t *in_ptr, const int32_t *in_src,
+                             const double *in_w, const int64_t *out_ptr, const double *out_w,
+                             const int32_t *out_deg, const double *p, double d, double tol,
+                             int max_iter, int dangling, int scaled, int threads, double *x,
+                             double *res) {
   const int uniform = (dangling == ORC_DANGLING_UNIFORM);
   if (scaled && !uniform) return -2;
-  int64_t mu = in_ptr[n];
-  double *CL = (double *)malloc(sizeof(double) * (size_t)(mu > 0 ? mu : 1));
   double *W = (double *)malloc(sizeof(double) * (size_t)n);
-  if (!CL || !W) { free(CL); free(W); return -1; }
+  double *share = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!W || !share) { free(W); free(share); return -1; }
   out_weight_sums(n, out_ptr, out_w, out_deg, W);
+  for (int64_t v = 0; v < n; ++v) share[v] = W[v] != 0.0 ? x[v] / W[v] : 0.0;
   const double inv_n = 1.0 / (double)n;
-  for (int64_t v = 0; v < n; ++v) {
-    if (W[v] == 0.0) continue;
-    double contribution = x[v] / W[v];
-    for (int64_t e = out_ptr[v]; e < out_ptr[v + 1]; ++e)
-      CL[offset[e]] = out_w ? contribution * out_w[e] : contribution;
-  }
-  int it = 0;
+  int sweeps = 0;
   double r = INFINITY;
-  while (it < max_iter) {
-    const double D = uniform ? dangling_mass(n, x, W) : 0.0;
-    double S = 1.0;
-    if (scaled) {
-      S = 0.0;
-      for (int64_t v = 0; v < n; ++v) S += x[v];
-    }
+  while (sweeps < max_iter) {
+    const double D = uniform ? dangling_total(n, x, W) : 0.0;
+    const double S = scaled ? plain_sum(n, x) : 1.0;
     double l1 = 0.0;
 #pragma omp parallel for schedule(static) num_threads(threads) reduction(+ : l1)
     for (int64_t u = 0; u < n; ++u) {
-      const double prev = x[u];
-      double sum = 0.0;
+      double acc = 0.0;
       for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) {
-        double c;
-        __atomic_load(&CL[e], &c, __ATOMIC_RELAXED);
-        sum += c;
+        double s;
+        __atomic_load(&share[in_src[e]], &s, __ATOMIC_RELAXED);
+        acc += in_w ? s * in_w[e] : s;
       }
       const double pu = p ? p[u] : inv_n;
-      const double xn = (1.0 - d) * pu * S + d * (sum + D * inv_n);
+      const double xn = (1.0 - d) * pu * S + d * (acc + D * inv_n);
       if (W[u] != 0.0) {
-        const double contribution = xn / W[u];
-        for (int64_t e = out_ptr[u]; e < out_ptr[u + 1]; ++e) {
-          double c = out_w ? contribution * out_w[e] : contribution;
-          __atomic_store(&CL[offset[e]], &c, __ATOMIC_RELAXED);
-        }
+        const double s = xn / W[u];
+        __atomic_store(&share[u], &s, __ATOMIC_RELAXED);
       }
+      l1 += fabs(xn - x[u]);
       x[u] = xn;
-      l1 += fabs(xn - prev);
     }
-    ++it;
-    if (scaled) {
-      double S2 = 0.0;
-      for (int64_t v = 0; v < n; ++v) S2 += x[v];
-      r = (l1 + fabs(S2 - S)) / S;
-    } else {
-      r = l1;
-    }
+    ++sweeps;
+    r = scaled ? (l1 + fabs(plain_sum(n, x) - S)) / S : l1;
     if (r < tol) break;
   }
   if (scaled) {
-    double S = 0.0;
-    for (int64_t v = 0; v < n; ++v) S += x[v];
+    const double S = plain_sum(n, x);
     for (int64_t v = 0; v < n; ++v) x[v] /= S;
   }
   *res = r;
-  free(CL); free(W);
-  return it;
+  free(W); free(share);
+  return sweeps;
 }
 
-/* ------------------------------------------------ F and certificate --- */
+/* ------------------------------------------------ F and certificates --- */
 /* y = F(x) over the inList (sources of each destination), FP64. */
 int orc_apply_F(int64_t n, const int64_t *in_ptr, const int32_t *in_src, const double *in_w,
                 const int64_t *out_ptr, const double *out_w, const int32_t *out_deg,
@@ -452,38 +439,78 @@ int orc_apply_F(int64_t n, const int64_t *in_ptr, const int32_t *in_src, const d
   double *W = (double *)malloc(sizeof(double) * (size_t)n);
   if (!W) return -1;
   out_weight_sums(n, out_ptr, out_w, out_deg, W);
-  double D = (dangling == ORC_DANGLING_UNIFORM) ? dangling_mass(n, x, W) : 0.0;
+  const double D = (dangling == ORC_DANGLING_UNIFORM) ? dangling_total(n, x, W) : 0.0;
   const double inv_n = 1.0 / (double)n;
 #pragma omp parallel for schedule(static)
   for (int64_t u = 0; u < n; ++u) {
-    double sum = 0.0;
+    double acc = 0.0;
     for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) {
       int32_t v = in_src[e];
-      sum += (in_w ? in_w[e] : 1.0) * (x[v] / W[v]);
+      acc += (in_w ? in_w[e] : 1.0) * (x[v] / W[v]);
     }
-    double pu = p ? p[u] : inv_n;
-    y[u] = (1.0 - d) * pu + d * (sum + D * inv_n);
+    const double pu = p ? p[u] : inv_n;
+    y[u] = (1.0 - d) * pu + d * (acc + D * inv_n);
   }
   free(W);
   return 0;
 }
 
-/* F(x)_u for a list of vertices only (sampled checks on very large graphs). */
-int orc_apply_F_rows(int64_t n, const int64_t *in_ptr, const int32_t *in_src, const double *in_w,
-                     const double *W, const double *p, double d, double D, const double *x,
-                     int64_t k, const int32_t *rows, double *y) {
-  const double inv_n = 1.0 / (double)n;
-  for (int64_t i = 0; i < k; ++i) {
-    int32_t u = rows[i];
-    double sum = 0.0;
-    for (int64_t e = in_ptr[u]; e < in_ptr[u + 1]; ++e) {
-      int32_t v = in_src[e];
-      sum += (in_w ? in_w[e] : 1.0) * (x[v] / W[v]);
-    }
-    double pu = p ? p[u] : inv_n;
-    y[i] = (1.0 - d) * pu + d * (sum + D * inv_n);
+/*
+ * ||F(x) - x||_1 straight from an edge list, without building any graph
+ * structure: W_v is summed over the listed edges leaving v (their weights, or
+ * 1 each), D over the vertices whose W_v is 0, and
+ *     F(x)_u = (1-d) p_u + d ( sum over listed edges v->u of w x_v / W_v + D/n ).
+ * Self-loops are skipped, as the canonical graph drops them.  A repeated
+ * (src, dst) pair would be counted twice, so the list must hold each edge
+ * once; a list that does not gives a value for a different graph, which makes
+ * a comparison with the canonical graph's fixed point fail, never pass.
+ * For every x, ||x - x*||_1 <= this / (1 - d) (F is a d-contraction in L1).
+ *   w      edge weights (nullable: 1)
+ *   p      personalization (nullable: 1/n)
+ *   y      (nullable) receives F(x)
+ *   threads edge-range partitions, each summing into its own array; the arrays
+ *          are added in partition order, so the result depends only on
+ *          `threads` (1 = one plain sequential pass)
+ * Returns the residual, or NaN on allocation failure.
+ */
+double orc_residual_edges(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                          const double *w, const double *p, double d, const double *x,
+                          double *y, int threads) {
+  const int T = threads > 0 ? threads : 1;
+  double *W = (double *)calloc((size_t)n, sizeof(double));
+  double *acc = (double *)calloc((size_t)n * (size_t)T, sizeof(double));
+  if (!W || !acc) { free(W); free(acc); return NAN; }
+  const int transposed = (g_mutation == 4);
+  for (int64_t i = 0; i < m; ++i) {
+    const int32_t a = src[i], b = dst[i];
+    if (a == b) continue;
+    /* planted mistake 3: in-weight in place of out-weight */
+    W[g_mutation == 3 ? b : a] += w ? w[i] : 1.0;
   }
-  return 0;
+  const double D = (g_mutation == 1) ? 0.0 : dangling_total(n, x, W);
+#pragma omp parallel for schedule(static) num_threads(T)
+  for (int t = 0; t < T; ++t) {
+    double *mine = acc + (size_t)t * (size_t)n;
+    const int64_t lo = m * t / T, hi = m * (t + 1) / T;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int32_t a = transposed ? dst[i] : src[i], b = transposed ? src[i] : dst[i];
+      if (a == b || W[a] == 0.0) continue;
+      mine[b] += (w ? w[i] : 1.0) * (x[a] / W[a]);
+    }
+  }
+  const double inv_n = 1.0 / (double)n;
+  double r = 0.0;
+  for (int64_t u = 0; u < n; ++u) {
+    double s = acc[u];
+    for (int t = 1; t < T; ++t) s += acc[(size_t)t * (size_t)n + (size_t)u];
+    const double pu = (p && g_mutation != 6) ? p[u] : inv_n;
+    const double teleport = (g_mutation == 2) ? 0.0 : (1.0 - d) * pu;
+    const double fu = teleport + d * (s + D * inv_n);
+    if (y) y[u] = fu;
+    r += fabs(fu - x[u]);
+  }
+  free(W); free(acc);
+  return r;
 }
 
 /* ------------------------------------------------ adjoint ------------- */

@@ -95,8 +95,8 @@ def test_host_thread_scaling_leg():
     og = oracle.csr(1 << 10, s, t)
     rows = bench.host_scaling(oracle, og, 1e-10, 4)
     assert [r["threads"] for r in rows] == [1, 2, 4]
-    _, it_ec, _ = oracle.pagerank_ec(og, bench.D, tol=1e-10, max_iter=1000)
-    _, it_f, _ = oracle.pagerank_fused(og, bench.D, tol=1e-10, max_iter=1000, scaled=True)
+    _, it_ec, _ = oracle.jacobi(og, bench.D, tol=1e-10, max_iter=1000)
+    _, it_f, _ = oracle.gauss_seidel(og, bench.D, tol=1e-10, max_iter=1000, scaled=True)
     assert rows[0]["ec_sweeps"] == it_ec and rows[0]["fused_sweeps"] == it_f
     # the edge-centric form is deterministic at any thread count; the fused one
     # is asynchronous across threads but still reaches the tolerance

@@ -29,7 +29,7 @@ def l1(a, b):
 def _ppr_ref(og, n, s, tol=1e-14):
     p = np.zeros(n)
     p[s] = 1.0
-    x, _, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=5000, p=p, threads=8)
+    x, _, _ = oracle.jacobi(og, D, tol=tol, max_iter=5000, p=p, threads=8)
     return x
 
 
@@ -75,7 +75,7 @@ def test_batched_tile_widths_agree_and_linearity():
     og = oracle.csr(n, s, t)
     p = np.zeros(n)
     p[seeds.cpu().numpy()] = 1.0 / 20
-    xm, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=5000, p=p)
+    xm, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=5000, p=p)
     assert l1(outs[0][0].astype(np.float64).mean(axis=1), xm) <= 1e-5
     g.close()
 
@@ -238,7 +238,7 @@ def test_adjoint_weighted_rmat_matches_oracle():
     n, src, dst, w, gvec = _adj_case(13, 92, small=False)
     say("adjoint rmat13")
     og = oracle.csr(n, src, dst, w)
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=5000, threads=8)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-15, max_iter=5000, threads=8)
     lam_o, gp_o, gw_o, _, _ = oracle.adjoint(og, xr, gvec, D, tol=1e-14)
     g = fpr.Graph(n, src, dst, w, with_adjoint=True)
     x, it, res, ok = g.solve(d=D, tol=1e-14, max_iter=5000)

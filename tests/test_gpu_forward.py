@@ -57,7 +57,7 @@ PLANS = [None, dict(chunk=64, tile_max_row=9, tile_rows=5, steps=3, hot_slots=10
 
 def _ref(n, src, dst, w, p, tol=1e-15):
     og = oracle.csr(n, src, dst, w)
-    x, _, _ = oracle.pagerank_ec(og, D, tol=tol, max_iter=5000, p=p)
+    x, _, _ = oracle.jacobi(og, D, tol=tol, max_iter=5000, p=p)
     return og, x
 
 
@@ -178,7 +178,7 @@ def test_path_leak_mode_and_linf():
     x, it, res, ok = g.solve(d=D, tol=1e-17, max_iter=500, dangling="leak", norm="linf")
     assert ok and np.max(np.abs(x.cpu().numpy() - want)) <= 1e-15 * want.max()
     og = oracle.csr(n, s, t)
-    _, ito, _ = oracle.pagerank_ec(og, D, tol=1e-17, max_iter=500, dangling="leak", norm="linf")
+    _, ito, _ = oracle.jacobi(og, D, tol=1e-17, max_iter=500, dangling="leak", norm="linf")
     assert abs(it - ito) <= 1
     g.close()
 
@@ -191,7 +191,7 @@ def test_leak_mode_iterates_follow_the_oracle():
     say("leak trajectory")
     g = fpr.Graph(n, s, t, plan=PLANS[1])
     for sweeps in (1, 3, 10):
-        xr, _, _ = oracle.pagerank_ec(og, D, tol=0.0, max_iter=sweeps, dangling="leak")
+        xr, _, _ = oracle.jacobi(og, D, tol=0.0, max_iter=sweeps, dangling="leak")
         x = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
         g.iterate(x, sweeps, d=D, dangling="leak")
         assert np.max(np.abs(x.cpu().numpy() - xr)) <= 1e-14 * xr.max()
@@ -205,7 +205,7 @@ def test_edge_cases(n, edges):
     s = np.array(edges[0], np.int32)
     t = np.array(edges[1], np.int32)
     say("edge case n=%d m=%d" % (n, len(s)))
-    xr = oracle.pagerank_ec(oracle.csr(n, s, t), D, tol=1e-16, max_iter=500)[0]
+    xr = oracle.jacobi(oracle.csr(n, s, t), D, tol=1e-16, max_iter=500)[0]
     g = fpr.Graph(n, s, t)
     for mode in ("jacobi", "fused"):
         for prec in ("fp64", "fp32"):
@@ -326,7 +326,7 @@ def test_trace_and_warm_start():
     say("trace / warm start")
     g = fpr.Graph(n, s, t)
     x, it, res, ok, tr = g.solve(d=D, tol=1e-4, trace=True)
-    _, ito, _, tro, _ = oracle.pagerank_ec(og, D, tol=1e-4, max_iter=1000, trace=True)
+    _, ito, _, tro, _ = oracle.jacobi(og, D, tol=1e-4, max_iter=1000, trace=True)
     assert len(tr) == it and abs(it - ito) <= 1
     assert np.allclose(tr[:min(it, ito)], tro[:min(it, ito)], rtol=1e-9, atol=1e-18)
     # checkpoint at 1e-4, resume to 1e-12 == direct solve

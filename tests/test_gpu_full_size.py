@@ -41,8 +41,8 @@ def test_er10k_config():
     fpr = _fpr()
     d = gg.er_10k()
     og = oracle.csr(d["n"], d["src"], d["dst"])
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=1000)
-    _, it_o, _ = oracle.pagerank_ec(og, D, tol=1e-10, max_iter=200)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-15, max_iter=1000)
+    _, it_o, _ = oracle.jacobi(og, D, tol=1e-10, max_iter=200)
     say("er10k")
     g = fpr.Graph(d["n"], d["src"], d["dst"])
     x, it, res, ok = g.solve(d=D, tol=1e-10, max_iter=200, mode="jacobi")
@@ -55,7 +55,7 @@ def test_er10k_config():
 def rmat20():
     w = gg.rmat20()
     og = oracle.csr(w["n"], w["src"], w["dst"])
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=1000, threads=THREADS)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=1000, threads=THREADS)
     return w, og, xr
 
 
@@ -108,7 +108,7 @@ def test_rmat20_batched_k64(rmat20):
     for j in (0, 17, 41, 63):
         p = np.zeros(n)
         p[seeds[j]] = 1.0
-        xj, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=1000, p=p, threads=THREADS)
+        xj, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=1000, p=p, threads=THREADS)
         assert l1(Xh[:, j], xj) <= 1e-5, j
     g.close()
 
@@ -121,7 +121,7 @@ def test_rmat18_weighted_adjoint():
     gvec = np.zeros(n)
     gvec[w["targets"]] = 1.0
     og = oracle.csr(n, w["src"], w["dst"], w["w"])
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-15, max_iter=2000, threads=THREADS)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-15, max_iter=2000, threads=THREADS)
     lam_o, gp_o, gw_o, _, _ = oracle.adjoint(og, xr, gvec, D, tol=1e-14)
     say("rmat18 weighted adjoint")
     g = fpr.Graph(n, w["src"], w["dst"], w["w"], with_adjoint=True)
@@ -173,7 +173,7 @@ def test_road8m_forms():
     w = gg.road8m()
     n = w["n"]
     og = oracle.csr(n, w["src"], w["dst"])
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=2000, threads=THREADS)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=2000, threads=THREADS)
     say("road8m")
     g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1))
     for mode in ("jacobi", "fused", "edge_list"):
@@ -191,7 +191,7 @@ def test_rmat21_forms():
     w = gg.rmat_permuted(21, seed=21)
     n = w["n"]
     og = oracle.csr(n, w["src"], w["dst"])
-    xr, _, _ = oracle.pagerank_ec(og, D, tol=1e-14, max_iter=1000, threads=THREADS)
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=1000, threads=THREADS)
     say("rmat21")
     g = fpr.Graph(n, w["src"], w["dst"])
     assert g.m == og.m

@@ -2,7 +2,7 @@
 
 None of these compares the oracle with itself: each check uses an independent
 route (dense linear algebra, closed forms, brute-force sets, invariants of the
-fixed point, Eq. 9 written as a direct Gauss-Seidel recurrence, finite
+fixed point, Eq. 9 and Eq. 2 written as small pure-Python loops, finite
 differences).  test_pins_catch_planted_mistakes plants known mistakes in the
 oracle and shows that the pins fail on each.
 """
@@ -123,7 +123,7 @@ def _graphs():
 @pytest.mark.parametrize("name,n,src,dst,w,p", _graphs(), ids=[g[0] for g in _graphs()])
 def test_jacobi_matches_dense_solve(name, n, src, dst, w, p):
     g = oracle.csr(n, src, dst, w)
-    x, it, r = oracle.pagerank_ec(g, D, tol=1e-15, max_iter=2000, p=p)
+    x, it, r = oracle.jacobi(g, D, tol=1e-15, max_iter=2000, p=p)
     xd = dense.solve(n, src, dst, w, D, p)
     assert l1(x, xd) <= 1e-12
     assert it < 2000
@@ -132,7 +132,7 @@ def test_jacobi_matches_dense_solve(name, n, src, dst, w, p):
 @pytest.mark.parametrize("name,n,src,dst,w,p", _graphs(), ids=[g[0] for g in _graphs()])
 def test_fused_matches_dense_solve(name, n, src, dst, w, p):
     g = oracle.csr(n, src, dst, w)
-    x, it, r = oracle.pagerank_fused(g, D, tol=1e-15, max_iter=2000, p=p)
+    x, it, r = oracle.gauss_seidel(g, D, tol=1e-15, max_iter=2000, p=p)
     xd = dense.solve(n, src, dst, w, D, p)
     assert l1(x, xd) <= 1e-12
 
@@ -141,10 +141,63 @@ def test_leak_mode_matches_dense_leak():
     n = 300
     src, dst = gg.random_graph(n, 900, 21)
     g = oracle.csr(n, src, dst)
-    x, _, _ = oracle.pagerank_ec(g, D, tol=1e-16, max_iter=3000, dangling="leak")
+    x, _, _ = oracle.jacobi(g, D, tol=1e-16, max_iter=3000, dangling="leak")
     assert l1(x, dense.solve(n, src, dst, None, D, None, "leak")) <= 1e-12
-    xf, _, _ = oracle.pagerank_fused(g, D, tol=1e-16, max_iter=3000, dangling="leak")
+    xf, _, _ = oracle.gauss_seidel(g, D, tol=1e-16, max_iter=3000, dangling="leak")
     assert l1(xf, dense.solve(n, src, dst, None, D, None, "leak")) <= 1e-12
+
+
+# ------------------------------------------------ edge-list residual ----
+
+def _distinct_cases():
+    """Duplicate-free edge lists (the edge-list residual needs each pair once):
+    unweighted with dangling vertices, weighted, personalized."""
+    out = []
+    for name, n, src, dst, w, p in _graphs():
+        s2, t2 = gg.dedup(n, src, dst)
+        w2 = None if w is None else gg.weights(len(s2), 91)
+        out.append((name, n, s2, t2, w2, p))
+    return out
+
+
+@pytest.mark.parametrize("threads", [1, 3])
+@pytest.mark.parametrize("name,n,src,dst,w,p", _distinct_cases(), ids=[g[0] for g in _distinct_cases()])
+def test_residual_edges_is_dense_F(name, n, src, dst, w, p, threads):
+    """F(x) from the raw edge list equals (1-d) p + d P x with the dense P,
+    for a random x and at the dense fixed point (where the residual vanishes)."""
+    P = dense.transition(n, src, dst, w)
+    pv = np.full(n, 1.0 / n) if p is None else p
+    x = gg.uniforms(92, 1, n) + 0.1
+    x /= x.sum()
+    F = (1 - D) * pv + D * (P @ x)
+    r, y = oracle.residual_edges(n, src, dst, x, D, p=p, w=w, threads=threads, want_F=True)
+    assert np.max(np.abs(y - F)) <= 1e-15 * np.max(F) * n
+    assert abs(r - float(np.abs(F - x).sum())) <= 1e-13
+    xs = dense.solve(n, src, dst, w, D, p)
+    assert oracle.residual_edges(n, src, dst, xs, D, p=p, w=w, threads=threads) <= 1e-14
+
+
+def test_residual_edges_closed_forms():
+    """Zero residual at the closed-form fixed points of a cycle and an in-star."""
+    n = 50
+    s, t = gg.cycle(n)
+    assert oracle.residual_edges(n, s, t, np.full(n, 1.0 / n), D) <= 1e-16
+    s, t = gg.in_star(n)
+    assert oracle.residual_edges(n, s, t, _in_star(n), D) <= 1e-15
+
+
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 6])
+def test_residual_edges_catch_planted_mistakes(mutation):
+    """Each planted mistake moves F away from the dense fixed point's F."""
+    name, n, src, dst, w, p = _distinct_cases()[3]  # personalized, dangling vertices
+    assert (np.bincount(src, minlength=n) == 0).any()
+    xs = dense.solve(n, src, dst, w, D, p)
+    assert oracle.residual_edges(n, src, dst, xs, D, p=p, w=w) <= 1e-14
+    try:
+        oracle.set_mutation(mutation)
+        assert oracle.residual_edges(n, src, dst, xs, D, p=p, w=w) > 1e-6
+    finally:
+        oracle.set_mutation(0)
 
 
 CLOSED = []
@@ -183,7 +236,7 @@ for _n in (5, 64):
 def test_closed_forms(name, n, edges, formula):
     g = oracle.csr(n, edges[0], edges[1])
     want = formula(n)
-    for fn in (oracle.pagerank_ec, oracle.pagerank_fused):
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
         x, _, _ = fn(g, D, tol=1e-16, max_iter=500)
         assert np.max(np.abs(x - want)) <= 1e-15 * max(1.0, n * want.max())
 
@@ -198,14 +251,14 @@ def test_one_hot_teleport_on_a_cycle_closed_form(n, seed):
     want = (1 - D) * D ** k / (1 - D ** n)
     p = np.zeros(n)
     p[seed] = 1.0
-    for fn in (oracle.pagerank_ec, oracle.pagerank_fused):
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
         x, _, _ = fn(g, D, tol=1e-17, max_iter=2000, p=p)
         assert np.max(np.abs(x - want)) <= 1e-14 * want.max()
 
 
 def test_cycle_converges_after_one_sweep():
     g = oracle.csr(10, *gg.cycle(10))
-    x, it, r, tr, sums = oracle.pagerank_ec(g, D, tol=1e-30, max_iter=3, trace=True)
+    x, it, r, tr, sums = oracle.jacobi(g, D, tol=1e-30, max_iter=3, trace=True)
     assert tr[0] == 0.0
 
 
@@ -213,10 +266,10 @@ def test_cycle_converges_after_one_sweep():
 def test_path_leak_closed_form(n):
     g = oracle.csr(n, *gg.path(n))
     want = np.array([(1 - D ** (i + 1)) / n for i in range(n)])
-    x, _, _ = oracle.pagerank_ec(g, D, tol=1e-18, max_iter=500, dangling="leak")
+    x, _, _ = oracle.jacobi(g, D, tol=1e-18, max_iter=500, dangling="leak")
     assert np.max(np.abs(x - want)) <= 1e-15 * want.max()
     # Gauss-Seidel in topological order is forward substitution: exact after one sweep
-    x1, _, _, tr = oracle.pagerank_fused(g, D, tol=0.0, max_iter=2, dangling="leak", trace=True)
+    x1, _, _, tr = oracle.gauss_seidel(g, D, tol=0.0, max_iter=2, dangling="leak", trace=True)
     assert np.max(np.abs(x1 - want)) <= 1e-15 * want.max()
     assert tr[1] == 0.0
 
@@ -225,18 +278,18 @@ def test_dag_one_gauss_seidel_sweep_is_exact():
     n = 200
     src, dst = gg.random_dag(n, 1200, 31)
     g = oracle.csr(n, src, dst)
-    x, _, _, tr = oracle.pagerank_fused(g, D, tol=0.0, max_iter=2, dangling="leak", trace=True)
+    x, _, _, tr = oracle.gauss_seidel(g, D, tol=0.0, max_iter=2, dangling="leak", trace=True)
     assert tr[1] == 0.0
     assert l1(x, dense.solve(n, src, dst, None, D, None, "leak")) <= 1e-13
     # Jacobi needs about the longest-path length in sweeps on the same graph
-    _, itj, _ = oracle.pagerank_ec(g, D, tol=1e-16, max_iter=1000, dangling="leak")
+    _, itj, _ = oracle.jacobi(g, D, tol=1e-16, max_iter=1000, dangling="leak")
     assert itj > 2
 
 
 def test_sum_is_one_after_every_jacobi_sweep():
     d = gg.er_10k()
     g = oracle.csr(d["n"], d["src"], d["dst"])
-    x, it, r, tr, sums = oracle.pagerank_ec(g, D, tol=1e-13, max_iter=300, trace=True)
+    x, it, r, tr, sums = oracle.jacobi(g, D, tol=1e-13, max_iter=300, trace=True)
     assert np.max(np.abs(sums - 1.0)) <= 1e-12
     assert abs(x.sum() - 1.0) <= 1e-12
 
@@ -245,7 +298,7 @@ def test_contraction_and_iteration_bound():
     d = gg.er_10k()
     g = oracle.csr(d["n"], d["src"], d["dst"])
     tol = 1e-10
-    x, it, r, tr, _ = oracle.pagerank_ec(g, D, tol=tol, max_iter=200, trace=True)
+    x, it, r, tr, _ = oracle.jacobi(g, D, tol=tol, max_iter=200, trace=True)
     floor = 1e-14
     for k in range(1, len(tr)):
         assert tr[k] <= D * tr[k - 1] * (1 + 1e-9) + floor
@@ -265,7 +318,7 @@ def test_certificate_bounds_true_error():
     g = oracle.csr(n, src, dst)
     xs = dense.solve(n, src, dst, None, D)
     for tol in (1e-3, 1e-6, 1e-9):
-        x, _, _ = oracle.pagerank_ec(g, D, tol=tol, max_iter=1000)
+        x, _, _ = oracle.jacobi(g, D, tol=tol, max_iter=1000)
         assert l1(x, xs) <= oracle.certificate(g, x, D) * (1 + 1e-9) + 1e-15
 
 
@@ -276,14 +329,14 @@ def test_gauss_seidel_sweep_counts():
     needs more sweeps than Jacobi, and the mass-scaled variant needs fewer."""
     s, t = gg.rmat(14, 16, seed=2)
     g = oracle.csr(1 << 14, s, t)
-    _, itj_leak, _ = oracle.pagerank_ec(g, D, tol=1e-10, max_iter=1000, dangling="leak")
-    _, itf_leak, _ = oracle.pagerank_fused(g, D, tol=1e-10, max_iter=1000, dangling="leak")
+    _, itj_leak, _ = oracle.jacobi(g, D, tol=1e-10, max_iter=1000, dangling="leak")
+    _, itf_leak, _ = oracle.gauss_seidel(g, D, tol=1e-10, max_iter=1000, dangling="leak")
     assert itf_leak < itj_leak
-    xj, itj, _ = oracle.pagerank_ec(g, D, tol=1e-10, max_iter=1000)
-    xf, itf, _ = oracle.pagerank_fused(g, D, tol=1e-10, max_iter=1000)
-    xs, its, _ = oracle.pagerank_fused(g, D, tol=1e-10, max_iter=1000, scaled=True)
+    xj, itj, _ = oracle.jacobi(g, D, tol=1e-10, max_iter=1000)
+    xf, itf, _ = oracle.gauss_seidel(g, D, tol=1e-10, max_iter=1000)
+    xs, its, _ = oracle.gauss_seidel(g, D, tol=1e-10, max_iter=1000, scaled=True)
     assert its < itj < itf
-    x_ref, _, _ = oracle.pagerank_ec(g, D, tol=1e-15, max_iter=1000)
+    x_ref, _, _ = oracle.jacobi(g, D, tol=1e-15, max_iter=1000)
     for x in (xj, xf, xs):
         assert l1(x, x_ref) <= 1e-9
 
@@ -291,7 +344,7 @@ def test_gauss_seidel_sweep_counts():
 def test_mass_scaled_fused_matches_dense_solve():
     for name, n, src, dst, w, p in _graphs():
         g = oracle.csr(n, src, dst, w)
-        x, it, r = oracle.pagerank_fused(g, D, tol=1e-15, max_iter=2000, p=p, scaled=True)
+        x, it, r = oracle.gauss_seidel(g, D, tol=1e-15, max_iter=2000, p=p, scaled=True)
         assert l1(x, dense.solve(n, src, dst, w, D, p)) <= 1e-12, name
 
 
@@ -318,7 +371,7 @@ def _eq2_jacobi(n, ins, outdeg, sweeps):
     return np.array(x)
 
 
-def test_fused_oracle_is_eq9_and_ec_oracle_is_eq2():
+def test_gauss_seidel_oracle_is_eq9_and_jacobi_oracle_is_eq2():
     n = 60
     src, dst = gg.random_graph(n, 400, 51, self_loops=False)
     # add a cycle so no vertex is dangling (Eq. 9 / Eq. 2 have no dangling term)
@@ -329,26 +382,26 @@ def test_fused_oracle_is_eq9_and_ec_oracle_is_eq2():
     assert (g.out_deg > 0).all()
     ins = [g.in_src[g.in_ptr[u]:g.in_ptr[u + 1]].tolist() for u in range(n)]
     for sweeps in (1, 2, 5):
-        xf, _, _ = oracle.pagerank_fused(g, D, tol=0.0, max_iter=sweeps)
+        xf, _, _ = oracle.gauss_seidel(g, D, tol=0.0, max_iter=sweeps)
         assert np.array_equal(xf, _eq9_gauss_seidel(n, ins, g.out_deg.tolist(), sweeps))
-        xj, _, _ = oracle.pagerank_ec(g, D, tol=0.0, max_iter=sweeps)
+        xj, _, _ = oracle.jacobi(g, D, tol=0.0, max_iter=sweeps)
         assert np.array_equal(xj, _eq2_jacobi(n, ins, g.out_deg.tolist(), sweeps))
 
 
 def test_linf_norm_option():
     d = gg.er_10k()
     g = oracle.csr(d["n"], d["src"], d["dst"])
-    x1, it1, r1 = oracle.pagerank_ec(g, D, tol=1e-12, max_iter=500, norm="linf")
+    x1, it1, r1 = oracle.jacobi(g, D, tol=1e-12, max_iter=500, norm="linf")
     assert r1 < 1e-12
-    x2, it2, r2 = oracle.pagerank_ec(g, D, tol=1e-12, max_iter=500, norm="l1")
+    x2, it2, r2 = oracle.jacobi(g, D, tol=1e-12, max_iter=500, norm="l1")
     assert it1 <= it2  # max-norm <= L1 norm
 
 
 def test_threads_do_not_change_result():
     s, t = gg.rmat(12, 16, seed=61)
     g = oracle.csr(1 << 12, s, t)
-    x1, i1, r1 = oracle.pagerank_ec(g, D, tol=1e-10, threads=1)
-    x4, i4, r4 = oracle.pagerank_ec(g, D, tol=1e-10, threads=4)
+    x1, i1, r1 = oracle.jacobi(g, D, tol=1e-10, threads=1)
+    x4, i4, r4 = oracle.jacobi(g, D, tol=1e-10, threads=4)
     assert np.array_equal(x1, x4) and i1 == i4 and r1 == r4
 
 
@@ -367,7 +420,7 @@ def _adjoint_case(seed=71, n=150, m=700):
 def test_adjoint_matches_dense_gradient():
     n, src, dst, w, p, gvec = _adjoint_case()
     g = oracle.csr(n, src, dst, w)
-    x, _, _ = oracle.pagerank_ec(g, D, tol=1e-15, max_iter=3000)
+    x, _, _ = oracle.jacobi(g, D, tol=1e-15, max_iter=3000)
     lam, gp, gw, it, r = oracle.adjoint(g, x, gvec, D)
     lam_d = dense.adjoint(n, src, dst, w, D, gvec)
     assert l1(lam, lam_d) <= 1e-10 * np.abs(lam_d).sum()
@@ -382,7 +435,7 @@ def test_adjoint_matches_dense_gradient():
 def test_adjoint_matches_finite_differences():
     n, src, dst, w, p, gvec = _adjoint_case(seed=72, n=80, m=400)
     g = oracle.csr(n, src, dst, w)
-    x, _, _ = oracle.pagerank_ec(g, D, tol=1e-15, max_iter=3000)
+    x, _, _ = oracle.jacobi(g, D, tol=1e-15, max_iter=3000)
     lam, gp, gw, _, _ = oracle.adjoint(g, x, gvec, D)
     rng_edges = gg.sample_distinct(len(src), 12, 72, 5)
     for i in rng_edges.tolist():
@@ -399,7 +452,7 @@ def test_adjoint_matches_finite_differences():
 def test_adjoint_duality_and_homogeneity():
     n, src, dst, w, p, gvec = _adjoint_case(seed=73, n=400, m=2400)
     g = oracle.csr(n, src, dst, w)
-    x, _, _ = oracle.pagerank_ec(g, D, tol=1e-15, max_iter=3000)
+    x, _, _ = oracle.jacobi(g, D, tol=1e-15, max_iter=3000)
     lam, gp, gw, _, _ = oracle.adjoint(g, x, gvec, D)
     L = float(np.dot(gvec, x))
     assert abs(L - (1 - D) * float(np.dot(lam, p))) <= 1e-12 * abs(L)
@@ -416,19 +469,19 @@ def _pins_pass():
     """A quick subset of the pins above, returning False on the first failure."""
     n, src, dst, w, p, gvec = _adjoint_case(seed=81, n=120, m=500)
     g = oracle.csr(n, src, dst, w)
-    x, _, _ = oracle.pagerank_ec(g, D, tol=1e-15, max_iter=3000)
+    x, _, _ = oracle.jacobi(g, D, tol=1e-15, max_iter=3000)
     if l1(x, dense.solve(n, src, dst, w, D)) > 1e-12:
         return False
     rs, rt = gg.rmat(7, 4, seed=82)  # about half the vertices dangling
     gu = oracle.csr(128, rs, rt)
     assert (gu.out_deg == 0).sum() > 20
-    xu, _, _ = oracle.pagerank_ec(gu, D, tol=1e-15, max_iter=3000)
+    xu, _, _ = oracle.jacobi(gu, D, tol=1e-15, max_iter=3000)
     if l1(xu, dense.solve(128, rs, rt, None, D)) > 1e-12:
         return False
     cs, ct = gg.cycle(9)
     pc = np.zeros(9)
     pc[4] = 1.0
-    xc, _, _ = oracle.pagerank_ec(oracle.csr(9, cs, ct), D, tol=1e-17, max_iter=2000, p=pc)
+    xc, _, _ = oracle.jacobi(oracle.csr(9, cs, ct), D, tol=1e-17, max_iter=2000, p=pc)
     if np.max(np.abs(xc - (1 - D) * D ** ((np.arange(9) - 4) % 9) / (1 - D ** 9))) > 1e-14:
         return False
     lam, gp, gw, _, _ = oracle.adjoint(g, x, gvec, D)
@@ -458,11 +511,11 @@ def test_par_fused_host_variant():
     s, t = gg.random_graph(n, 1800, 31)
     og = oracle.csr(n, s, t)
     x_dense = dense.solve(n, s, t, None, 0.85, None)
-    xs, its, _ = oracle.pagerank_fused(og, 0.85, tol=1e-14, max_iter=2000, scaled=True)
-    x1, it1, _ = oracle.pagerank_fused_par(og, 0.85, tol=1e-14, max_iter=2000, scaled=True, threads=1)
+    xs, its, _ = oracle.gauss_seidel(og, 0.85, tol=1e-14, max_iter=2000, scaled=True)
+    x1, it1, _ = oracle.gauss_seidel_threads(og, 0.85, tol=1e-14, max_iter=2000, scaled=True, threads=1)
     assert it1 == its and np.array_equal(x1, xs)
     for th in (2, 4, 8):
         for scaled in (True, False):
-            x, it, r = oracle.pagerank_fused_par(og, 0.85, tol=1e-14, max_iter=5000, scaled=scaled, threads=th)
+            x, it, r = oracle.gauss_seidel_threads(og, 0.85, tol=1e-14, max_iter=5000, scaled=scaled, threads=th)
             assert r < 1e-14
             assert np.abs(x - x_dense).sum() <= 1e-12
