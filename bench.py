@@ -1,28 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the PageRank hot path on one MI355X.
 
-Headline workload: R-MAT scale 20 (2^20 vertices, edge factor 16, a=0.57,
-b=c=0.19, seed 2, randomly permuted ids), d = 0.85, stop at L1 < 1e-8.  A
-"step" is one full solve from x = 1/n to L1 < 1e-8 with the loop-fused form
-(the paper's method) in FP64: init, every sweep (pull + update + dangling /
-residual reductions + convergence test) and the host polls.  `value` = edges
-traversed per second over those sweeps, m' * sweeps / time, in GTEPS; inputs
-are resident in HBM before timing.
+Headline workload: R-MAT scale 24 (2^24 vertices, edge factor 16, a=0.57,
+b=c=0.19, seed 5, deduplicated, vertices relabelled in BFS order), d = 0.85,
+stop at L1 < 1e-8.  A "step" is one full solve from x = 1/n to L1 < 1e-8 with
+the loop-fused form (the paper's method) in FP64: init, every sweep (pull +
+update + dangling / residual reductions + convergence test) and the host
+polls.  `value` = edges traversed per second over those sweeps,
+m' * sweeps / time, in GTEPS; inputs are resident in HBM before timing.
 
 The same JSON line carries, on the same GPU:
-  forms       plain FP64 Jacobi, fused FP64 (mass-scaled and unscaled), FP32
-              Jacobi/fused with FP64 refinement to 1e-8, and the edge-centric
-              contributionList form of Algorithm 1 (scatter, then contiguous
-              row sums), each with its error against the oracle's fixed point;
-  batched     k = 64 one-hot personalized solves (FP32, per-column tol 1e-6)
-              against 64 sequential plain FP64 single-seed solves;
+  forms       at scale 24: plain FP64 Jacobi, fused FP64, FP32 Jacobi / fused
+              with FP64 refinement to 1e-8, and the edge-centric
+              contributionList form of Algorithm 1 (scatter, then contiguous row
+              sums), each with the oracle's certificate on its error;
+  roofline    of the dominant kernel, the fused FP64 sweep at scale 24 (the
+              FP32 sweep's beside it);
+  cpu_baseline the FP64 CPU oracle timed on the host cores: one application of
+              Eq. 1 over the same scale-24 edge list (one Jacobi sweep);
+  rmat20      R-MAT scale 20 (permuted ids; its working set fits the Infinity
+              Cache): the same forms against the oracle's fixed point, with the
+              oracle's full solves on 1..16 host threads (Seq/Par-EC against
+              Seq/Par-FusEd);
+  batched     k = 64 one-hot personalized solves on R-MAT-20 (FP32, per-column
+              tol 1e-6) against 64 sequential plain FP64 single-seed solves;
   er10k       directed Erdos-Renyi n=10,000, m=80,000, plain FP64, tol 1e-10;
   adjoint     weighted R-MAT scale 18: forward solve + adjoint + gradients;
-  road8m      a road-network-shaped street grid (8.4 M vertices, degree ~2.8);
-  rmat24      R-MAT scale 24 in BFS order: FP32 fused + FP64 refinement
-              against plain FP64 Jacobi, with the FP32 sweep's roofline;
-  roofline    of the dominant kernel (the fused FP64 sweep at scale 20);
-  cpu_baseline the FP64 CPU oracle (Jacobi iteration of Eq. 1) timed on the host cores.
+  road8m      a road-network-shaped street grid (8.4 M vertices, degree ~2.8).
 
     python bench.py [--steps K] [--warmup W] [--quick]
     python bench.py --profile FORM [--workload rmat20|rmat24]   (kernel-only driver
@@ -157,7 +161,10 @@ def sweep_kernel_us(g, mode, precision="fp64", sweeps=50, reps=3):
     return best[0] * 1e3, best[1] * 1e3
 
 
-def solve_legs(torch, g, m, tol, steps, warmup, names, x_ref=None):
+def solve_legs(torch, g, m, tol, steps, warmup, names, x_ref=None, cert=None):
+    """Time each form's solve to `tol`; state its error against the oracle:
+    the L1 distance to the oracle's fixed point (x_ref), or the oracle's
+    certificate ||F(x) - x||_1 / (1 - d), which bounds ||x - x*||_1 (cert)."""
     forms = {}
     for name in names:
         mode, prec = name.split("-")[:2]
@@ -166,10 +173,11 @@ def solve_legs(torch, g, m, tol, steps, warmup, names, x_ref=None):
             kw["fused_scaled"] = False
         t_ms, (x, it, r, ok) = timed(torch, lambda: g.solve(**kw), steps, warmup)
         f = dict(ms=t_ms, sweeps=it, resid=r, converged=bool(ok), gteps=m * it / (t_ms * 1e-3) / 1e9)
+        xh = x.cpu().numpy()
         if x_ref is not None:
-            f["l1_vs_oracle"] = float(np.abs(x.cpu().numpy() - x_ref).sum())
+            f["l1_vs_oracle"] = float(np.abs(xh - x_ref).sum())
         else:
-            f["certificate_bound"] = g.certificate(x, d=D) / (1 - D)
+            f["oracle_certificate"] = float(cert(xh))
         forms[name] = f
         log("%-20s %9.3f ms  sweeps=%3d  GTEPS=%8.2f  resid=%.2e" % (name, t_ms, it, f["gteps"], r))
     return forms
@@ -207,13 +215,22 @@ def host_cpu():
 
 # ----------------------------------------------------------------- legs --
 
-def leg_batched(torch, fpr, g, n, m, steps):
+def leg_batched(torch, fpr, oracle, og, g, n, m, steps):
     import graphgen as gg
     seeds_h = gg.ppr_seeds(n)
     seeds = torch.tensor(seeds_h, dtype=torch.int32, device="cuda")
     tune = g.autotune_batched(64)
     t_b, (X, its, res) = timed(torch, lambda: g.solve_batched(seeds, d=D, tol=1e-6), max(3, steps // 4), 1)
-    log("batched k=64 tile=%d: %.2f ms, sweeps max %d" % (tune, t_b, its.max()))
+    log("batched k=64 shape=%s: %.2f ms, sweeps max %d" % (tune, t_b, its.max()))
+    # the oracle's certificate of every column: ||F_j(x_j) - x_j||_1 / (1 - d)
+    # with the one-hot teleport of seed j (Eq. 1), on the FP32 result cast up
+    Xh = X.cpu().numpy().astype(np.float64)
+    certs = []
+    for j, s in enumerate(seeds_h):
+        p = np.zeros(n)
+        p[s] = 1.0
+        certs.append(oracle.certificate(og, Xh[:, j], D, p))
+    del Xh
 
     ps = torch.zeros((64, n), dtype=torch.float64, device="cuda")
     ps[torch.arange(64, device="cuda"), seeds.long()] = 1.0
@@ -226,14 +243,15 @@ def leg_batched(torch, fpr, g, n, m, steps):
     col = float(its.sum())
     # with all 64 columns in one launch, every sweep reads, per in-edge, the
     # source's 256-byte row (rate over the whole solve, init and output included)
-    row_bytes = float(m) * 4 * 64 * int(its.max()) if tune == 64 else None
+    row_bytes = float(m) * 4 * 64 * int(its.max()) if tune["tile"] == 64 else None
     traffic = traffic_record("batched_rmat20", BATCHED_SOURCES) if n == (1 << 20) else None
-    return rounded(dict(k=64, tol=1e-6, tile=tune, ms=t_b, max_sweeps=int(its.max()),
+    return rounded(dict(k=64, tol=1e-6, shape=tune, ms=t_b, max_sweeps=int(its.max()),
                         column_sweeps=int(col), column_gteps=m * col / (t_b * 1e-3) / 1e9,
                         row_read_gbs=row_bytes / (t_b * 1e-3) / 1e9 if row_bytes else None,
                         b_alg_per_sweep=b_alg(n, m, 4 * 64), traffic_per_sweep=traffic,
                         sequential_fp64_ms=t_s, sequential_sweeps=int(sum(its_s)),
-                        speedup_vs_sequential_fp64=t_s / t_b))
+                        speedup_vs_sequential_fp64=t_s / t_b,
+                        oracle_certificate_max=max(certs), oracle_certificate_median=float(np.median(certs))))
 
 
 def leg_er10k(torch, fpr, oracle, steps, warmup):
@@ -261,42 +279,53 @@ def leg_adjoint(torch, fpr, oracle, steps, warmup, threads):
     lam_o, gp_o, gw_o, _, _ = oracle.adjoint(og, xr, gvec, D, tol=1e-14)
     rel = lambda a, b: float(np.abs(a.cpu().numpy() - b).sum() / np.abs(b).sum())
     out = dict(workload="rmat18w", n=n, m=g.m, tol=1e-12, forward_ms=t_f, forward_sweeps=it,
-               adjoint_ms=t_a, adjoint_sweeps=it2, rel_l1_lambda=rel(lam, lam_o), rel_l1_dLdp=rel(gp, gp_o),
+               forward_l1_vs_oracle=float(np.abs(x.cpu().numpy() - xr).sum()), adjoint_ms=t_a, adjoint_sweeps=it2, rel_l1_lambda=rel(lam, lam_o), rel_l1_dLdp=rel(gp, gp_o),
                rel_l1_dLdw=rel(gw, gw_o))
     g.close()
     return rounded(out)
 
 
-def leg_road(torch, fpr, steps, warmup):
+def leg_road(torch, fpr, oracle, steps, warmup, threads):
     """Road-network-shaped graph (low degree, no hubs, long diameter): the
     regime where the paper reports its smallest gains."""
     w = workload("road8m")
-    g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1))
+    g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1, with_inplace=1))
     n, m = g.n, g.m
+    cert = lambda xh: oracle.residual_edges(n, w["src"], w["dst"], xh, D, threads=threads) / (1 - D)
     forms = solve_legs(torch, g, m, 1e-8, steps, warmup,
-                       ["jacobi-fp64", "fused-fp64", "jacobi-fp32", "fused-fp32", "edge_list-fp64"])
-    kern = {name: sweep_kernel_us(g, *name.split("-"), sweeps=20) for name in ("jacobi-fp64", "fused-fp64")}
+                       ["jacobi-fp64", "fused-fp64", "jacobi-fp32", "fused-fp32", "edge_list-fp64",
+                        "fused_edge_list-fp64", "inplace-fp64", "inplace-fp32"], cert=cert)
+    kern = {name: sweep_kernel_us(g, *name.split("-"), sweeps=20) for name in
+            ("jacobi-fp64", "fused-fp64", "inplace-fp64")}
     st = g.stats()
     out = dict(workload="road8m", graph=w["desc"], n=n, m=m, tol=1e-8, gs_blocks=st["gs_blocks"],
                forms={k: rounded(v) for k, v in forms.items()},
                kernel_us={k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
                alg_gbs_jacobi_fp64=sig(b_alg(n, m, 8) / (kern["jacobi-fp64"][0] * 1e-6) / 1e9))
-    log("road8m: jacobi %.3f ms (%d), fused %.3f ms (%d), sweep %.1f us" %
+    out["speedup_vs_jacobi_fp64"] = {k: sig(forms["jacobi-fp64"]["ms"] / f["ms"]) for k, f in forms.items()
+                                     if k != "jacobi-fp64"}
+    log("road8m: jacobi %.3f ms (%d), fused %.3f ms (%d), inplace %.3f ms (%d), sweep %.1f us" %
         (forms["jacobi-fp64"]["ms"], forms["jacobi-fp64"]["sweeps"], forms["fused-fp64"]["ms"],
-         forms["fused-fp64"]["sweeps"], kern["jacobi-fp64"][0]))
+         forms["fused-fp64"]["sweeps"], forms["inplace-fp64"]["ms"], forms["inplace-fp64"]["sweeps"],
+         kern["jacobi-fp64"][0]))
     g.close()
     return out
 
 
-def leg_scale(torch, fpr, name, steps, warmup):
+def leg_scale(torch, fpr, oracle, name, steps, warmup, threads):
     """One of the intermediate R-MAT sizes the paper's synthetic set covers
     (scales 21-23, Section 6.2), permuted ids: time to L1 < 1e-8 of the four
-    main forms and the sweep kernel's time per sweep."""
+    main forms, each with the oracle's certificate, and the sweep kernel's time
+    per sweep."""
+    import graphgen as gg
     w = workload(name)
     g = fpr.Graph(w["n"], w["src"], w["dst"])
     n, m = g.n, g.m
+    src, dst = gg.dedup(n, w["src"], w["dst"])
     del w
-    forms = solve_legs(torch, g, m, 1e-8, steps, warmup, ["jacobi-fp64", "fused-fp64", "jacobi-fp32", "fused-fp32"])
+    cert = lambda xh: oracle.residual_edges(n, src, dst, xh, D, threads=threads) / (1 - D)
+    forms = solve_legs(torch, g, m, 1e-8, steps, warmup, ["jacobi-fp64", "fused-fp64", "jacobi-fp32", "fused-fp32"],
+                       cert=cert)
     kern = {k: sweep_kernel_us(g, *k.split("-"), sweeps=20) for k in forms}
     out = dict(workload=name, n=n, m=m, tol=1e-8, gs_blocks=g.stats()["gs_blocks"],
                forms={k: rounded(v) for k, v in forms.items()},
@@ -309,31 +338,102 @@ def leg_scale(torch, fpr, name, steps, warmup):
     return out
 
 
-def leg_rmat24(torch, fpr, steps, warmup):
+def headline_rmat24(torch, fpr, oracle, steps, warmup, cores, cpu_baseline):
+    """The headline: R-MAT scale 24 in BFS order, every form to L1 < 1e-8 with
+    the oracle's certificate, the sweep kernels' device time, and the oracle's
+    own sweep over the same edge list on the host cores."""
     t0 = time.perf_counter()
     w = workload("rmat24")
-    n = w["n"]
+    n, src, dst = w["n"], w["src"], w["dst"]
     log("generated rmat24 in %.1fs" % (time.perf_counter() - t0))
     t0 = time.perf_counter()
-    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1))
-    del w
+    g = fpr.Graph(n, src, dst, plan=dict(with_cl=1, with_inplace=1))
+    setup_s = time.perf_counter() - t0
     m = g.m
-    log("rmat24 on device: m'=%d setup %.1fs" % (m, time.perf_counter() - t0))
-    forms = solve_legs(torch, g, m, 1e-8, steps, warmup, ["jacobi-fp64", "fused-fp32", "jacobi-fp32",
-                                                          "fused-fp64", "edge_list-fp32"])
-    k32, f32 = sweep_kernel_us(g, "fused", "fp32", sweeps=20)
-    k64, _ = sweep_kernel_us(g, "jacobi", "fp64", sweeps=20)
-    b32 = b_alg(n, m, 4)
-    ach = b32 / (k32 * 1e-6) / 1e9
-    log("rmat24 sweep kernel: fused fp32 %.1f us (%.0f GB/s alg) + finalize %.1f us, jacobi fp64 %.1f us"
-        % (k32, ach, f32, k64))
-    out = dict(workload="rmat24", n=n, m=m, tol=1e-8, fp32_tol=1e-7,
-               forms={k: rounded(v) for k, v in forms.items()},
-               speedup_fused_fp32_vs_jacobi_fp64=sig(forms["jacobi-fp64"]["ms"] / forms["fused-fp32"]["ms"]),
-               roofline=roofline(ach, traffic_record("fused_fp32_rmat24"), "k_sweep<float, fused>", b32, k32,
-                                 g.stats()["gs_blocks"], b32 + 4 * m),
-               finalize_us=round(f32, 2), jacobi_fp64_sweep_kernel_us=round(k64, 2))
+    st = g.stats()
+    log("rmat24 on device: m'=%d blocks=%d setup %.1fs" % (m, st["gs_blocks"], setup_s))
+    cert = lambda xh: oracle.residual_edges(n, src, dst, xh, D, threads=cores) / (1 - D)
+    forms = solve_legs(torch, g, m, 1e-8, steps, warmup, ["jacobi-fp64", "fused-fp64", "jacobi-fp32", "fused-fp32"],
+                       cert=cert)
+    forms.update(solve_legs(torch, g, m, 1e-8, 3, 1, ["edge_list-fp32", "fused_edge_list-fp32", "inplace-fp64",
+                                                      "inplace-fp32"], cert=cert))
+    kern = {name: sweep_kernel_us(g, *name.split("-"), sweeps=20) for name in
+            ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32", "inplace-fp32")}
+    for name, (ks, kf) in kern.items():
+        log("rmat24 %-12s sweep kernel %.1f us + finalize %.1f us per sweep" % (name, ks, kf))
+    cpu = None
+    if cpu_baseline:
+        # the oracle as it stands, on a bounded sample of this workload: one
+        # application of Eq. 1 over the whole edge list (one Jacobi sweep plus
+        # its residual), from x = 1/n; median of 3 on all host threads, once on 1
+        x0 = np.full(n, 1.0 / n)
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.residual_edges(n, src, dst, x0, D, threads=cores)
+            runs.append(time.perf_counter() - t0)
+        cpu_s = float(np.median(runs))
+        t0 = time.perf_counter()
+        oracle.residual_edges(n, src, dst, x0, D, threads=1)
+        one_s = time.perf_counter() - t0
+        cpu = dict(value=sig(m / cpu_s / 1e9), unit="GTEPS", cores=cores, kind="oracle",
+                   sample="one Jacobi sweep of Eq. 1 (F(x) and ||F(x) - x||_1) over the same scale-24 edge "
+                          "list, x = 1/n, FP64: median of 3 runs of %.2f s on %d threads; 1 thread: %.2f s"
+                          % (cpu_s, cores, one_s),
+                   single_thread_gteps=sig(m / one_s / 1e9))
+        cpu["cpu_model"], cpu["nproc"] = host_cpu()
+        log("cpu oracle sweep at rmat24: %.3f GTEPS on %d threads, %.3f on 1" %
+            (cpu["value"], cores, cpu["single_thread_gteps"]))
     g.close()
+    return dict(n=n, m=m, setup_s=setup_s, gs_blocks=st["gs_blocks"], forms=forms, kern=kern, cpu=cpu)
+
+
+def leg_rmat20(torch, fpr, oracle, steps, warmup, cores, args):
+    """R-MAT scale 20, permuted ids: every form against the oracle's fixed point,
+    the sweep kernels, the batched personalized solve on the same graph, and the
+    oracle's own full solves on the host (Seq/Par-EC against Seq/Par-FusEd)."""
+    w = workload("rmat20")
+    n, tol = w["n"], w["tol"]
+    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1, with_inplace=1))
+    m = g.m
+    st = g.stats()
+    og = oracle.csr(n, w["src"], w["dst"])
+    x_ref, _, _ = oracle.jacobi(og, D, tol=1e-13, max_iter=1000, threads=cores)
+    forms = solve_legs(torch, g, m, tol, steps, warmup,
+                       ["jacobi-fp64", "fused-fp64", "fused-fp64-unscaled", "jacobi-fp32", "fused-fp32",
+                        "edge_list-fp64", "fused_edge_list-fp64", "inplace-fp64", "inplace-fp32"], x_ref)
+    kern = {name: sweep_kernel_us(g, *name.split("-")) for name in
+            ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32", "edge_list-fp64")}
+    for name, (ks, kf) in kern.items():
+        log("rmat20 %-12s sweep kernel %.1f us + finalize %.1f us per sweep" % (name, ks, kf))
+    b64 = b_alg(n, m, 8)
+    kf = kern["fused-fp64"][0]
+    out = dict(workload="rmat20", graph=w["desc"], n=n, m=m, tol=tol, gs_blocks=st["gs_blocks"],
+               forms={k: rounded(f) for k, f in forms.items()},
+               kernel_us={k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
+               speedup_vs_jacobi_fp64_time_to_tol={
+                   k: sig(forms["jacobi-fp64"]["ms"] / f["ms"]) for k, f in forms.items() if k != "jacobi-fp64"},
+               roofline=dict(roofline(b64 / (kf * 1e-6) / 1e9, traffic_record("fused_fp64_rmat20"),
+                                      "k_sweep<double, fused>", b64, kf, st["gs_blocks"], b64 + 8 * m),
+                             note="cache-resident: the FP64 working set (94 MB) fits the 256 MB Infinity Cache"))
+    if not args.quick:
+        try:
+            out["batched"] = leg_batched(torch, fpr, oracle, og, g, n, m, args.steps)
+        except Exception as e:  # reported, not fatal
+            out["batched"] = dict(error=str(e)[:300])
+            log("batched leg failed: %s" % e)
+    g.close()
+    if not args.no_cpu_baseline:
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, it_cpu, _ = oracle.jacobi(og, D, tol=tol, max_iter=1000, threads=cores)
+            runs.append(time.perf_counter() - t0)
+        cpu_s = float(np.median(runs))
+        out["cpu_oracle_solve"] = dict(gteps=sig(og.m * it_cpu / cpu_s / 1e9), threads=cores, sweeps=it_cpu,
+                                       s=sig(cpu_s, 4))
+        if not args.quick:
+            out["cpu_thread_scaling"] = host_scaling(oracle, og, tol, cores)
     return out
 
 
@@ -511,12 +611,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--quick", action="store_true", help="headline workload only (no extra legs)")
+    ap.add_argument("--quick", action="store_true", help="headline workload and R-MAT-20 forms only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-rmat24", action="store_true")
     ap.add_argument("--profile", default=None, help="{jacobi,fused,edge_list}-{fp64,fp32} | batched")
     ap.add_argument("--profile-sweeps", type=int, default=20)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--workload", default="rmat24")
     ap.add_argument("--scales", nargs="*", type=int, default=None, metavar="SCALE",
                     help="add the permuted R-MAT legs of these scales (21-23) to the line")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("KEY", "FETCH_CSV", "WRITE_CSV", "DRIVER_LOG"))
@@ -546,83 +645,30 @@ def main():
         raise SystemExit("bench.py needs a GPU: the HIP library has no CPU path")
     torch.cuda.set_device(0)
     cores = min(os.cpu_count() or 1, 16)
-    t0 = time.perf_counter()
-    w = workload("rmat20")
-    n, tol = w["n"], w["tol"]
-    log("generated rmat20: n=%d raw m=%d in %.1fs" % (n, len(w["src"]), time.perf_counter() - t0))
-    t0 = time.perf_counter()
-    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1))
-    setup_s = time.perf_counter() - t0
-    st = g.stats()
-    m = g.m
-    log("graph on device: m'=%d items=%d grid=%d setup %.1fs" % (m, st["n_items"], st["grid"], setup_s))
-    og = oracle.csr(n, w["src"], w["dst"])
-    x_ref, _, _ = oracle.jacobi(og, D, tol=1e-13, max_iter=1000, threads=cores)
 
-    forms = solve_legs(torch, g, m, tol, args.steps, args.warmup,
-                       ["jacobi-fp64", "fused-fp64", "fused-fp64-unscaled", "jacobi-fp32", "fused-fp32",
-                        "edge_list-fp64"], x_ref)
-    kern = {name: sweep_kernel_us(g, *name.split("-")) for name in
-            ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32", "edge_list-fp64")}
-    for name, (ks, kf) in kern.items():
-        log("%-12s sweep kernel %.1f us + finalize %.1f us per sweep" % (name, ks, kf))
-    k_fused = kern["fused-fp64"][0]
+    h = headline_rmat24(torch, fpr, oracle, args.steps, args.warmup, cores, not args.no_cpu_baseline)
+    n, m, forms, kern = h["n"], h["m"], h["forms"], h["kern"]
 
     extra = {}
+    legs = [("rmat20", lambda: leg_rmat20(torch, fpr, oracle, args.steps, args.warmup, cores, args))]
     if not args.quick:
-        for name, fn in (("batched", lambda: leg_batched(torch, fpr, g, n, m, args.steps)),
-                         ("er10k", lambda: leg_er10k(torch, fpr, oracle, args.steps, args.warmup)),
-                         ("adjoint", lambda: leg_adjoint(torch, fpr, oracle, args.steps, args.warmup, cores)),
-                         ("road8m", lambda: leg_road(torch, fpr, max(3, args.steps // 4), 1))):
-            try:
-                extra[name] = fn()
-            except Exception as e:  # reported, not fatal: the headline stands on its own
-                extra[name] = dict(error=str(e)[:300])
-                log("%s leg failed: %s" % (name, e))
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        # the oracle as it stands: its Jacobi iteration of Eq. 1, FP64, the
-        # same graph and tolerance; median of three full solves
-        runs = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            _, it_cpu, _ = oracle.jacobi(og, D, tol=tol, max_iter=1000, threads=cores)
-            runs.append(time.perf_counter() - t0)
-        cpu_s = float(np.median(runs))
-        t0 = time.perf_counter()
-        _, it1, _ = oracle.jacobi(og, D, tol=tol, max_iter=1000, threads=1)
-        one_s = time.perf_counter() - t0
-        cpu = dict(value=sig(og.m * it_cpu / cpu_s / 1e9), unit="GTEPS", cores=cores, kind="oracle",
-                   sample="full solve of the same R-MAT-20 graph to L1<%g (%d sweeps): the oracle's Jacobi "
-                          "iteration of Eq. 1, FP64, median of 3 runs of %.2f s on %d threads; "
-                          "1 thread: %.2f s" % (tol, it_cpu, cpu_s, cores, one_s),
-                   single_thread_gteps=sig(og.m * it1 / one_s / 1e9))
-        cpu["cpu_model"], cpu["nproc"] = host_cpu()
-        if not args.quick:
-            cpu["thread_scaling"] = host_scaling(oracle, og, tol, cores)
-        log("cpu oracle: %.3f GTEPS on %d threads, %.3f on 1" % (cpu["value"], cores, cpu["single_thread_gteps"]))
-    g.close()
-    del og, w
-
-    for sc in args.scales or []:
-        name = "rmat%d" % sc
+        legs += [("er10k", lambda: leg_er10k(torch, fpr, oracle, args.steps, args.warmup)),
+                 ("adjoint", lambda: leg_adjoint(torch, fpr, oracle, args.steps, args.warmup, cores)),
+                 ("road8m", lambda: leg_road(torch, fpr, oracle, max(3, args.steps // 4), 1, cores))]
+    legs += [("rmat%d" % sc, (lambda sc=sc: leg_scale(torch, fpr, oracle, "rmat%d" % sc, max(3, args.steps // 4),
+                                                      1, cores))) for sc in args.scales or []]
+    for name, fn in legs:
         try:
-            extra[name] = leg_scale(torch, fpr, name, max(3, args.steps // 4), 1)
-        except Exception as e:
+            extra[name] = fn()
+        except Exception as e:  # reported, not fatal: the headline stands on its own
             extra[name] = dict(error=str(e)[:300])
             log("%s leg failed: %s" % (name, e))
-
-    if not args.quick and not args.no_rmat24:
-        try:
-            extra["rmat24"] = leg_rmat24(torch, fpr, max(3, args.steps // 4), 1)
-        except Exception as e:
-            extra["rmat24"] = dict(error=str(e)[:300])
-            log("rmat24 leg failed: %s" % e)
+    if "batched" in extra.get("rmat20", {}):
+        extra["batched"] = extra["rmat20"].pop("batched")
 
     head = forms["fused-fp64"]
-    bytes_sweep = b_alg(n, m, 8)
-    achieved = bytes_sweep / (k_fused * 1e-6) / 1e9
+    b64, b32 = b_alg(n, m, 8), b_alg(n, m, 4)
+    k64, k32 = kern["fused-fp64"][0], kern["fused-fp32"][0]
     out = {
         "metric": METRIC,
         "value": round(head["gteps"], 3),
@@ -636,23 +682,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "rmat20", "graph": w_desc("rmat20"), "n": n, "m": m, "d": D, "tol": tol,
-                   "form": "fused-fp64", "step": "one solve from 1/n to L1<tol"},
-        "roofline": roofline(achieved, traffic_record("fused_fp64_rmat20"), "k_sweep<double, fused>",
-                             bytes_sweep, k_fused, st["gs_blocks"], bytes_sweep + 8 * m),
-        "cpu_baseline": cpu,
+        "config": {"workload": "rmat24", "graph": w_desc("rmat24"), "n": n, "m": m, "d": D, "tol": 1e-8,
+                   "form": "fused-fp64", "gs_blocks": h["gs_blocks"], "step": "one solve from 1/n to L1<tol"},
+        "roofline": roofline(b64 / (k64 * 1e-6) / 1e9, traffic_record("fused_fp64_rmat24"), "k_sweep<double, fused>",
+                             b64, k64, h["gs_blocks"], b64 + 8 * m),
+        "roofline_fp32": roofline(b32 / (k32 * 1e-6) / 1e9, traffic_record("fused_fp32_rmat24"),
+                                  "k_sweep<float, fused>", b32, k32, h["gs_blocks"], b32 + 4 * m),
+        "cpu_baseline": h["cpu"],
         "forms": {k: rounded(f) for k, f in forms.items()},
         "kernel_us": {k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
         "speedup_vs_jacobi_fp64_time_to_tol": {
             k: sig(forms["jacobi-fp64"]["ms"] / f["ms"]) for k, f in forms.items() if k != "jacobi-fp64"},
-        "setup_s": round(setup_s, 2),
+        "setup_s": round(h["setup_s"], 2),
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
 
 
 def w_desc(name):
-    return {"rmat20": "R-MAT scale 20, edge factor 16, a=.57 b=c=.19, seed 2, permuted ids"}[name]
+    return {"rmat20": "R-MAT scale 20, edge factor 16, a=.57 b=c=.19, seed 2, permuted ids",
+            "rmat24": "R-MAT scale 24, edge factor 16, a=.57 b=c=.19, seed 5, deduplicated, BFS order"}[name]
 
 
 if __name__ == "__main__":

@@ -108,7 +108,8 @@ void pr_csr_free(pr_csr *csr);
  * wavefront per vertex; very long lists split over several wavefronts), the
  * in-edges are re-laid in bin order, and the gathered array is laid out by
  * gather count so its hottest part can sit in LDS.  The library owns that
- * device memory and the per-graph workspace; pr_graph_destroy releases them.
+ * device memory and the per-graph workspace; pr_graph_destroy releases them
+ * (pr_graph_bind below places the graph in the caller's memory instead).
  * ---------------------------------------------------------------------- */
 typedef struct pr_graph pr_graph;
 
@@ -142,6 +143,9 @@ typedef struct pr_plan_opts {
   int with_cl;           /* also build the edge-centric contributionList layout (Section 3:
                             contributionList + offsetList) for PR_EDGE_LIST: 8 B (16 B
                             weighted) per edge more on the device (default 0) */
+  int with_inplace;      /* also keep the in-edges in vertex order (offsets, sources, weights)
+                            for PR_INPLACE: 4 B (12 B weighted) per edge and 4 B per vertex
+                            more on the device (default 0) */
 } pr_plan_opts;
 
 void pr_plan_opts_default(pr_plan_opts *o);
@@ -160,14 +164,40 @@ typedef struct pr_graph_stats {
   int grid;                           /* workgroups of one sweep launch */
   int gs_blocks;                      /* Gauss-Seidel blocks (sweep launches of the fused form) */
   int chunk;                          /* hub threshold in edges, as resolved */
+  int64_t graph_captures;             /* hipGraphs of sweeps captured so far for this graph
+                                         (one per distinct launch configuration; not per
+                                         output or teleport vector) */
+  uint64_t signature;                 /* 64-bit hash of the stored graph (sizes, offsets,
+                                         neighbours, weights): the key of tuned settings */
 } pr_graph_stats;
 
 int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *out);
 
+/* Caller-owned device memory for the graph (the input G = (V, E) of
+ * Section 3, which the paper's Algorithm 1 takes as given).
+ *
+ * pr_graph_device_bytes runs the planning of pr_graph_create on csr and opts
+ * without touching the device and returns in *bytes the device memory the
+ * graph and its plan occupy (every array rounded up to 256 bytes).
+ * pr_graph_bind then builds the same graph with every one of those arrays
+ * placed in the caller's device buffer dev_mem (current device, 256-byte
+ * aligned, at least *bytes long; e.g. a torch uint8 tensor): the library
+ * allocates no device memory for the graph (only its stream, two events and
+ * a small pinned state block).  The buffer must outlive the graph and must
+ * not be written while the graph exists.  Workspace the solvers allocate on
+ * first use is still the library's unless a solve takes the caller's
+ * (pr_solve_ws).  PR_EINVAL on a misaligned or non-device dev_mem, PR_ENOMEM
+ * when it is too small.
+ * pr_graph_free releases what the library owns of a graph (created or bound);
+ * a bound graph's buffer stays the caller's. */
+int pr_graph_device_bytes(const pr_csr *csr, const pr_plan_opts *opts, size_t *bytes);
+int pr_graph_bind(const pr_csr *csr, const pr_plan_opts *opts, void *dev_mem, size_t bytes, pr_graph **out);
+void pr_graph_free(pr_graph *g);
+
 /* ------------------------------------------------------------------------
  * Solver options.
  * ---------------------------------------------------------------------- */
-enum pr_mode { PR_JACOBI = 0, PR_FUSED = 1, PR_EDGE_LIST = 2 };
+enum pr_mode { PR_JACOBI = 0, PR_FUSED = 1, PR_EDGE_LIST = 2, PR_INPLACE = 3, PR_FUSED_EDGE_LIST = 4 };
 enum pr_precision { PR_FP64 = 0, PR_FP32 = 1 };
 enum pr_dangling { PR_DANGLING_UNIFORM = 0, PR_DANGLING_LEAK = 1 };
 enum pr_norm { PR_NORM_L1 = 0, PR_NORM_LINF = 1 };
@@ -177,7 +207,22 @@ typedef struct pr_opts {
                             Gauss-Seidel) or PR_EDGE_LIST (Algorithm 1 with the paper's
                             edge-ordered contributionList: a scatter through offsetList, then
                             contiguous row sums; needs a graph planned with with_cl; same
-                            values, same summation order, same results as PR_JACOBI) */
+                            values, same summation order, same results as PR_JACOBI), or
+                            PR_INPLACE (Algorithm 2 / Eq. 9 swept in place: each wavefront
+                            stages a block of consecutive vertices' contributions in LDS
+                            and updates the block in order, each lane walking its own run
+                            of consecutive vertices, so a source inside the block that is
+                            already updated is read fresh; the blocks run asynchronously,
+                            reading the other blocks' contributions from one shared array
+                            in whatever state it is (Section 4.3); needs a graph planned
+                            with with_inplace; not bit-reproducible across runs, same fixed
+                            point), or
+                            PR_FUSED_EDGE_LIST (Algorithm 2 with the paper's contributionList:
+                            per Gauss-Seidel block, the rows sum their contiguous list slices
+                            and update, then the block's vertices scatter their new
+                            contributions through offsetList; the list is filled once from
+                            the start vector; needs with_cl; same values, same summation
+                            order, same results as PR_FUSED) */
   int precision;        /* PR_FP64, or PR_FP32: ranks and contributions stored and summed
                            in FP32 with compensated sums; residual and dangling mass in FP64 */
   int dangling;         /* PR_DANGLING_UNIFORM, or PR_DANGLING_LEAK (the paper's literal
@@ -218,6 +263,18 @@ void pr_opts_default(pr_opts *o);
  * ---------------------------------------------------------------------- */
 int pr_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, const double *p,
              double *x, int *iters, double *resid, void *stream);
+
+/* pr_solve in a workspace the caller owns: the damping d and tolerance tol of
+ * Section 5's experiments and the stop rule of Section 3, with the
+ * contribution arrays (and the FP32 copy of the ranks) in ws, a device buffer
+ * of at least pr_workspace_bytes(g, tol, o) bytes (256-byte aligned), so the
+ * call allocates no workspace.  Same checks and results as pr_solve; refuses
+ * the edge-list forms and a residual trace (PR_EINVAL), whose buffers stay
+ * the library's.  ws may be reused by later calls on any graph that fits;
+ * calls that share one ws must not overlap. */
+int pr_workspace_bytes(const pr_graph *g, double tol, const pr_opts *o, size_t *bytes);
+int pr_solve_ws(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, const double *p, double *x,
+                void *ws, size_t ws_bytes, int *iters, double *resid, void *stream);
 
 /* Exactly `sweeps` sweeps from the x passed in (no convergence test), in the
  * form o->mode and the precision o->precision select: the body of
@@ -260,27 +317,48 @@ int pr_certificate(pr_graph *g, double d, const double *p, const double *x, doub
  * Ranks are FP32 (compensated sums), per-column residual and dangling mass
  * FP64; a column is frozen once its L1 residual is below tol.  Unweighted
  * graphs only: a graph created with edge weights gives PR_EINVAL.
+ *
+ * Launch shape: `tile` columns advance per launch (a multiple of 4, at most
+ * 64; inside a launch the columns of a vertex form one contiguous row, read
+ * whole per in-edge), each sweep wavefront takes `items_per_grab` consecutive
+ * work items (runs of rows, long rows, hub chunks) at a time (1..16), and the
+ * sweep kernel runs `wg_per_cu` workgroups per compute unit (1 or 2).  The
+ * shape changes only the time: every column is summed in the same order and
+ * every per-column reduction runs over work items in item order, so all
+ * shapes give the same bits.
+ * ---------------------------------------------------------------------- */
+typedef struct pr_batch_shape {
+  int tile;
+  int items_per_grab;
+  int wg_per_cu;
+} pr_batch_shape;
+
+/* tile 64, items_per_grab 1, wg_per_cu 2 */
+void pr_batch_shape_default(pr_batch_shape *s);
+
+/* k personalized solves of Eq. 1 (teleport e_{seeds[j]} for column j), as above.
  *   seeds   device int32[k], ids in [0, n) (checked: PR_EINVAL);  1 <= k <= 1024
+ *   shape   launch shape (host), or NULL: the autotuned one (pr_autotune_batched,
+ *           cache file from the FUSEDPR_TUNE_CACHE environment variable)
  *   X       device float[n * k], row-major (vertex-major): X[v * k + j]
  *   iters   host int[k]: sweeps until column j froze (or max_iter)
  *   resid   host double[k]: last residual of each column
- *   tile    columns advanced per launch (a multiple of 4, at most 64); 0 =
- *           autotuned (pr_autotune_batched, cache file from the
- *           FUSEDPR_TUNE_CACHE environment variable).  Inside a launch the
- *           columns of a vertex form one contiguous row, read whole per
- *           in-edge.  The results do not depend on the tile width.
- * Stream order: runs on the graph's work stream after the work queued on
- * `stream`, and returns once the results are in X, iters and resid.
- * ---------------------------------------------------------------------- */
+ * The sweeps of each launch of columns run as hipGraphs of 8 sweeps (the
+ * host polls the per-column state between them; sweeps after every column
+ * froze exit at once).  Stream order: runs on the graph's work stream after
+ * the work queued on `stream`, and returns once the results are in X, iters
+ * and resid. */
 int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter, int k, const int32_t *seeds,
-                     int tile, float *X, int *iters, double *resid, void *stream);
+                     const pr_batch_shape *shape, float *X, int *iters, double *resid, void *stream);
 
 /* Autotuner for pr_solve_batched (Eq. 1 with one-hot teleports; not in the
- * paper, which solves one vector at a time): times the candidate tile widths
- * on this graph and device and returns the fastest in *tile.  When cache_path is not
- * NULL the choice is read from / appended to that JSON-lines file, keyed by
- * the graph's size signature, k and the device name. */
-int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, int *tile, void *stream);
+ * paper, which solves one vector at a time): times every tile width from 8
+ * to 64 (4 when k is smaller), with 1, 2 or 4 items per grab and 1 or 2
+ * workgroups per compute unit, on this graph and device (4 sweeps each), and
+ * returns the fastest per column in *shape.  When cache_path is not NULL the
+ * choice is read from / appended to that JSON-lines file, keyed by the graph's
+ * signature (pr_graph_stats.signature), its size, k and the device name. */
+int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, pr_batch_shape *shape, void *stream);
 
 /* ------------------------------------------------------------------------
  * Adjoint (implicit differentiation of the fixed point).

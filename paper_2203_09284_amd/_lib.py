@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfusedpr.so")
 
 PR_OK, PR_NOT_CONVERGED, PR_EINVAL, PR_ENOMEM, PR_EDEVICE = 0, 1, -1, -2, -3
-PR_JACOBI, PR_FUSED, PR_EDGE_LIST = 0, 1, 2
+PR_JACOBI, PR_FUSED, PR_EDGE_LIST, PR_INPLACE, PR_FUSED_EDGE_LIST = 0, 1, 2, 3, 4
 PR_FP64, PR_FP32 = 0, 1
 PR_DANGLING_UNIFORM, PR_DANGLING_LEAK = 0, 1
 PR_NORM_L1, PR_NORM_LINF = 0, 1
@@ -31,7 +31,7 @@ class PrPlanOpts(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int), ("tile_max_row", ctypes.c_int), ("tile_rows", ctypes.c_int),
                 ("steps", ctypes.c_int), ("hot_slots", ctypes.c_int),
                 ("gather_layout", ctypes.c_int), ("with_adjoint", ctypes.c_int), ("gs_blocks", ctypes.c_int),
-                ("with_cl", ctypes.c_int)]
+                ("with_cl", ctypes.c_int), ("with_inplace", ctypes.c_int)]
 
 
 class PrGraphStats(ctypes.Structure):
@@ -40,7 +40,11 @@ class PrGraphStats(ctypes.Structure):
                 ("e_light", ctypes.c_int64), ("e_medium", ctypes.c_int64), ("e_heavy", ctypes.c_int64),
                 ("n_items", ctypes.c_int64), ("n_dangling", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("grid", ctypes.c_int), ("gs_blocks", ctypes.c_int),
-                ("chunk", ctypes.c_int)]
+                ("chunk", ctypes.c_int), ("graph_captures", ctypes.c_int64), ("signature", ctypes.c_uint64)]
+
+
+class PrBatchShape(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int), ("items_per_grab", ctypes.c_int), ("wg_per_cu", ctypes.c_int)]
 
 
 class PrOpts(ctypes.Structure):
@@ -59,6 +63,15 @@ SIGNATURES = {
     "pr_plan_opts_default": (None, [ctypes.POINTER(PrPlanOpts)]),
     "pr_graph_create": (ctypes.c_int, [ctypes.POINTER(PrCsr), ctypes.POINTER(PrPlanOpts), ctypes.POINTER(vp)]),
     "pr_graph_destroy": (None, [vp]),
+    "pr_graph_device_bytes": (ctypes.c_int, [ctypes.POINTER(PrCsr), ctypes.POINTER(PrPlanOpts),
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "pr_graph_bind": (ctypes.c_int, [ctypes.POINTER(PrCsr), ctypes.POINTER(PrPlanOpts), vp, ctypes.c_size_t,
+                                     ctypes.POINTER(vp)]),
+    "pr_graph_free": (None, [vp]),
+    "pr_workspace_bytes": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "pr_solve_ws": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(PrOpts), vp,
+                                   vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
     "pr_graph_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(PrGraphStats)]),
     "pr_opts_default": (None, [ctypes.POINTER(PrOpts)]),
     "pr_solve": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(PrOpts),
@@ -68,14 +81,18 @@ SIGNATURES = {
     "pr_certificate": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, c_f64p, vp]),
     "pr_profile_sweeps": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts), vp, ctypes.c_int, c_f64p,
                                          c_f64p, vp]),
+    "pr_batch_shape_default": (None, [ctypes.POINTER(PrBatchShape)]),
     "pr_solve_batched": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
-                                        ctypes.c_int, vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
-    "pr_autotune_batched": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), vp]),
+                                        ctypes.POINTER(PrBatchShape), vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
+    "pr_autotune_batched": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(PrBatchShape), vp]),
     "pr_adjoint": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, ctypes.c_double, ctypes.c_int, vp, vp, vp,
                                   ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
 }
 
-_LIB = None
+_LIBS: dict = {}
+# library builds: the product, and a variant whose FP32 sums carry no
+# compensation term (tests compare the two)
+VARIANTS = {"": LIB_PATH, "naive": os.path.join(HERE, "libfusedpr_naive.so")}
 
 
 class FusedPRError(RuntimeError):
@@ -84,25 +101,26 @@ class FusedPRError(RuntimeError):
         self.code = code
 
 
-def lib():
-    """Load the in-tree HIP library; fail loudly when it is missing (no fallback)."""
-    global _LIB
-    if _LIB is not None:
-        return _LIB
-    if not os.path.exists(LIB_PATH):
-        raise ImportError("libfusedpr.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
-    L = ctypes.CDLL(LIB_PATH)
+def lib(variant: str = ""):
+    """Load the in-tree HIP library (or one of its test variants); fail loudly
+    when it is missing (no fallback)."""
+    if variant in _LIBS:
+        return _LIBS[variant]
+    path = VARIANTS[variant]
+    if not os.path.exists(path):
+        raise ImportError("%s is not built; run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(L, name, None)
         if fn is None:
             continue
         fn.restype = res
         fn.argtypes = args
-    _LIB = L
+    _LIBS[variant] = L
     return L
 
 
-def check(code: int, allow_not_converged: bool = True) -> int:
+def check(code: int, allow_not_converged: bool = True, library=None) -> int:
     if code == PR_OK or (code == PR_NOT_CONVERGED and allow_not_converged):
         return code
-    raise FusedPRError(code, lib().pr_last_error().decode(errors="replace"))
+    raise FusedPRError(code, (library or lib()).pr_last_error().decode(errors="replace"))

@@ -4,6 +4,8 @@ Every HIP source is compiled with packed-FP32 instruction selection disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``); the host-only C++
 sources go through the same driver.  The library lands next to this file as
 ``libfusedpr.so``; objects go to ``_build/`` (not part of the source tree).
+``build_all`` also builds the test variant ``libfusedpr_naive.so`` (FP32 sums
+without compensation).
 """
 from __future__ import annotations
 
@@ -69,5 +71,19 @@ def build(extra: list[str] | None = None, verbose: bool = False, out: str | None
     return lib_path
 
 
+NAIVE_LIB = os.path.join(HERE, "libfusedpr_naive.so")
+
+
+def build_all(verbose: bool = False) -> None:
+    """The library, and its test variant with uncompensated FP32 sums
+    (FPR_NAIVE_SUM=1, libfusedpr_naive.so), which the precision tests compare
+    against."""
+    build(verbose=verbose)
+    build(["-DFPR_NAIVE_SUM=1"], verbose=verbose, out=NAIVE_LIB)
+
+
 if __name__ == "__main__":
-    build(sys.argv[1:], verbose=True)
+    if sys.argv[1:]:
+        build(sys.argv[1:], verbose=True)
+    else:
+        build_all(verbose=True)

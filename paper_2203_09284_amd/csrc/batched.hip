@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -67,18 +68,20 @@ struct VArgs {
   const uint32_t *gpos;
   const double *inv_w;
   const int32_t *seeds;  // [T], -1 for padding columns
-  float4 *x;             // [n][Q] vertex order
+  float4 *x;             // [n][Q] vertex order (the kernels take it from io)
+  const IoPtrs *io;      // io->x: where x lives (the caller's X when one launch holds all k columns)
   float4 *c0;            // [n][Q] gather-layout order
   float4 *c1;
   double *hpart;         // [n_chunks][T]
-  double *wg_part;       // [2][T][n_wg]: change and dangling mass per column and workgroup
+  double *item_part;     // [n_items][2][T]: change and dangling mass per item and column
   VState *st;
   double d;
   double inv_n;
   int64_t n;
   int n_items;
   int n_split;
-  int n_wg;
+  int n_wg;    // workgroups of the sweep launch
+  int ipg;     // consecutive items a wavefront takes at a time
   int chunk;
   int T;    // columns of this launch
   int Q;    // T / 4: float4 per row
@@ -275,8 +278,33 @@ __device__ __forceinline__ Sum4 quarter_sum(const VArgs &a, const VCtx &C, uint3
   return tot;
 }
 
-__global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_vsweep(VArgs a) {
-  __shared__ double s_part[kVWaves][2][kVMaxT];
+// The change and dangling mass of one item, per column: the four groups in
+// order, written by group 0 to the item's partial slots.  Every item gets a
+// record (zeros for hub chunks), so the per-column totals are sums over items
+// in item order, whichever wavefront ran which item.
+__device__ __forceinline__ void flush_item(const VArgs &a, const VCtx &C, int item, VRed &red) {
+  double ch[4], dg[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ch[q] = red.chg[q];
+    dg[q] = red.dang[q];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      ch[q] += __shfl(red.chg[q], C.j + kVGroup * k, 64);
+      dg[q] += __shfl(red.dang[q], C.j + kVGroup * k, 64);
+    }
+  }
+  if (C.g == 0 && C.act) {
+    double *rec = a.item_part + (size_t)item * 2 * a.T + 4 * C.j;
+    *reinterpret_cast<double4 *>(rec) = make_double4(ch[0], ch[1], ch[2], ch[3]);
+    *reinterpret_cast<double4 *>(rec + a.T) = make_double4(dg[0], dg[1], dg[2], dg[3]);
+  }
+  red = VRed();
+}
+
+__global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_vsweep(VArgs a0) {
+  VArgs a = a0;
+  a.x = static_cast<float4 *>(a0.io->x);
   const VCtx C = make_vctx(a);
   // every group holds the same columns: the vote is uniform over the workgroup
   const bool all_frozen = C.frozen[0] && C.frozen[1] && C.frozen[2] && C.frozen[3];
@@ -285,67 +313,50 @@ __global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kVWaves + wave));
   const int n_waves = a.n_wg * kVWaves;
   VRed red;
-  for (int item = gw; item < a.n_items; item += n_waves) {
-    const int4 wi = a.items[item];
-    if (wi.x == kVQuad) {
-      if (C.g < wi.z) {
-        const int2 rr = a.vrun[wi.y + C.g];
-        run_rows(a, C, rr.x, rr.y, red);
+  for (int first = gw * a.ipg; first < a.n_items; first += n_waves * a.ipg) {
+    const int last = min(first + a.ipg, a.n_items);
+    for (int item = first; item < last; ++item) {
+      const int4 wi = a.items[item];
+      if (wi.x == kVQuad) {
+        if (C.g < wi.z) {
+          const int2 rr = a.vrun[wi.y + C.g];
+          run_rows(a, C, rr.x, rr.y, red);
+        }
+      } else if (wi.x == kVLong) {
+        const int r = wi.y;
+        const uint32_t u = a.rows[r];
+        const uint32_t slot = a.rowpos[r];
+        const double iw = a.inv_w[u];
+        const float4 xo = (C.g == 0 && C.act) ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const Sum4 tot = quarter_sum(a, C, a.rptr[r], a.rptr[r + 1]);
+        if (C.g == 0 && C.act) {
+          double s[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) s[q] = tot.v[q].value();
+          vupdate(a, C, u, slot, iw, xo, s, red);
+        }
+      } else {  // kHeavy: chunk wi.z of hub row wi.y, partial sums to hpart[wi.w + wi.z]
+        const uint32_t rb = a.rptr[wi.y], re = a.rptr[wi.y + 1];
+        const uint32_t c0 = rb + (uint32_t)wi.z * (uint32_t)a.chunk;
+        const uint32_t c1 = min(re, c0 + (uint32_t)a.chunk);
+        const Sum4 tot = quarter_sum(a, C, c0, c1);
+        if (C.g == 0 && C.act) {
+          double *hp = a.hpart + (size_t)(wi.w + wi.z) * a.T + 4 * C.j;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) hp[q] = tot.v[q].value();
+        }
       }
-    } else if (wi.x == kVLong) {
-      const int r = wi.y;
-      const uint32_t u = a.rows[r];
-      const uint32_t slot = a.rowpos[r];
-      const double iw = a.inv_w[u];
-      const float4 xo = (C.g == 0 && C.act) ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const Sum4 tot = quarter_sum(a, C, a.rptr[r], a.rptr[r + 1]);
-      if (C.g == 0 && C.act) {
-        double s[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] = tot.v[q].value();
-        vupdate(a, C, u, slot, iw, xo, s, red);
-      }
-    } else {  // kHeavy: chunk wi.z of hub row wi.y, partial sums to hpart[wi.w + wi.z]
-      const uint32_t rb = a.rptr[wi.y], re = a.rptr[wi.y + 1];
-      const uint32_t c0 = rb + (uint32_t)wi.z * (uint32_t)a.chunk;
-      const uint32_t c1 = min(re, c0 + (uint32_t)a.chunk);
-      const Sum4 tot = quarter_sum(a, C, c0, c1);
-      if (C.g == 0 && C.act) {
-        double *hp = a.hpart + (size_t)(wi.w + wi.z) * a.T + 4 * C.j;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) hp[q] = tot.v[q].value();
-      }
+      flush_item(a, C, item, red);
     }
-  }
-  // per column: the four groups in order, then the waves of the workgroup in order
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double ch = red.chg[q], dg = red.dang[q];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-      const double oc = __shfl(red.chg[q], C.j + kVGroup * k, 64);
-      const double od = __shfl(red.dang[q], C.j + kVGroup * k, 64);
-      ch += oc;
-      dg += od;
-    }
-    if (C.g == 0 && C.act) {
-      s_part[wave][0][4 * C.j + q] = ch;
-      s_part[wave][1][4 * C.j + q] = dg;
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < 2 * a.T) {
-    const int kind = threadIdx.x / a.T, col = threadIdx.x % a.T;
-    double v = s_part[0][kind][col];
-    for (int w = 1; w < kVWaves; ++w) v += s_part[w][kind][col];
-    a.wg_part[((size_t)kind * a.T + col) * a.n_wg + blockIdx.x] = v;
   }
 }
 
 // One workgroup per column: completes the split hubs, sums the workgroup
 // partials in a fixed order, and updates the column's state.
-__global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a) {
+__global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a0) {
   __shared__ double s_red[2][kVFin / 64];
+  VArgs a = a0;
+  a.x = static_cast<float4 *>(a0.io->x);
   const int col = blockIdx.x;
   VState *st = a.st;
   if (st->done[col]) return;
@@ -354,9 +365,9 @@ __global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a) {
   float *xf = reinterpret_cast<float *>(a.x);
   float *cf = reinterpret_cast<float *>(a.par ? a.c0 : a.c1);
   double chg = 0.0, dang = 0.0;
-  for (int i = threadIdx.x; i < a.n_wg; i += kVFin) {
-    chg += a.wg_part[(size_t)col * a.n_wg + i];
-    dang += a.wg_part[((size_t)a.T + col) * a.n_wg + i];
+  for (int i = threadIdx.x; i < a.n_items; i += kVFin) {
+    chg += a.item_part[(size_t)i * 2 * a.T + col];
+    dang += a.item_part[((size_t)i * 2 + 1) * a.T + col];
   }
   for (int h = threadIdx.x; h < a.n_split; h += kVFin) {
     const int4 hs = a.hsplit[h];
@@ -452,6 +463,8 @@ __global__ void k_vseeds(const int32_t *seeds, int k, int32_t *out, int total) {
   if (i < total) out[i] = i < k ? seeds[i] : -1;
 }
 
+__global__ void k_vclear(int *flag) { *flag = 0; }
+
 __global__ void k_vcheck(const int32_t *seeds, int k, int64_t n, int *bad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k && (seeds[i] < 0 || seeds[i] >= n)) *bad = 1;
@@ -462,21 +475,21 @@ __global__ void k_vcheck(const int32_t *seeds, int k, int64_t n, int *bad) {
 struct VWork {
   int64_t cols_cap = 0;  // columns the row arrays hold
   float4 *x = nullptr, *c0 = nullptr, *c1 = nullptr;
-  double *hpart = nullptr, *wg_part = nullptr;
+  double *hpart = nullptr, *item_part = nullptr;
   VState *st = nullptr;
   VState *host_st = nullptr;
+  IoPtrs *io = nullptr;  // where the sweep kernels find x
+  void *io_last = nullptr;
   int32_t *seeds = nullptr;
   int seeds_cap = 0;
   int *flag = nullptr;
 };
 
-std::vector<std::pair<const pr_graph *, VWork>> g_vwork;
-
+// The batched workspace of a graph hangs off the graph (calls on one graph
+// never overlap, so no lock is needed).
 VWork *vwork_for(pr_graph *g) {
-  for (auto &e : g_vwork)
-    if (e.first == g) return &e.second;
-  g_vwork.emplace_back(g, VWork());
-  return &g_vwork.back().second;
+  if (!g->vwork) g->vwork = new VWork();
+  return static_cast<VWork *>(g->vwork);
 }
 
 int ensure_vwork(pr_graph *g, VWork &w, int T) {
@@ -490,11 +503,12 @@ int ensure_vwork(pr_graph *g, VWork &w, int T) {
     if ((rc = fpr_dev_alloc(g, (void **)&w.c1, sizeof(float4) * rows))) return rc;
     if ((rc = fpr_dev_alloc(g, (void **)&w.hpart, sizeof(double) * (size_t)T * (size_t)std::max(1, P.n_chunks))))
       return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.wg_part, sizeof(double) * 2 * (size_t)T * (size_t)(P.n_waves / kVWaves))))
+    if ((rc = fpr_dev_alloc(g, (void **)&w.item_part, sizeof(double) * 2 * (size_t)T * (size_t)std::max(1, P.n_bitems))))
       return rc;
     w.cols_cap = T;
   }
   if (!w.st && (rc = fpr_dev_alloc(g, (void **)&w.st, sizeof(VState)))) return rc;
+  if (!w.io && (rc = fpr_dev_alloc(g, (void **)&w.io, sizeof(IoPtrs)))) return rc;
   if (!w.host_st && hipHostMalloc((void **)&w.host_st, sizeof(VState)) != hipSuccess)
     return pr_fail(PR_ENOMEM, "pinned allocation failed");
   if (!w.flag && (rc = fpr_dev_alloc(g, (void **)&w.flag, sizeof(int)))) return rc;
@@ -509,7 +523,25 @@ int ensure_seeds(pr_graph *g, VWork &w, int total) {
   return PR_OK;
 }
 
-VArgs make_vargs(pr_graph *g, VWork &w, double d, int T, int col0) {
+__global__ void k_vset_io(IoPtrs *io, void *x) { io->x = x; }
+
+// Points the sweep kernels at x (queued on the work stream); skipped when
+// the block already holds it.
+int set_vio(pr_graph *g, VWork &w, void *x) {
+  if (w.io_last == x) return PR_OK;
+  hipLaunchKernelGGL(k_vset_io, dim3(1), dim3(1), 0, g->work, w.io, x);
+  PR_HIP(hipGetLastError());
+  w.io_last = x;
+  return PR_OK;
+}
+
+bool shape_ok(const pr_batch_shape &s) {
+  return s.tile >= 4 && s.tile <= kVMaxT && s.tile % 4 == 0 && s.items_per_grab >= 1 && s.items_per_grab <= 16 &&
+         s.wg_per_cu >= 1 && s.wg_per_cu <= 2;
+}
+
+// Launch arguments of T columns from col0; x goes through w.io (left null here).
+VArgs make_vargs(pr_graph *g, VWork &w, double d, int T, int col0, const pr_batch_shape &sh) {
   const DevPlan &P = g->fwd;
   VArgs a;
   memset(&a, 0, sizeof(a));
@@ -523,18 +555,20 @@ VArgs make_vargs(pr_graph *g, VWork &w, double d, int T, int col0) {
   a.gpos = P.gpos;
   a.inv_w = g->inv_w;
   a.seeds = w.seeds + col0;
-  a.x = w.x;
+  a.x = nullptr;
+  a.io = w.io;
   a.c0 = w.c0;
   a.c1 = w.c1;
   a.hpart = w.hpart;
-  a.wg_part = w.wg_part;
+  a.item_part = w.item_part;
   a.st = w.st;
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
   a.n = g->n;
   a.n_items = P.n_bitems;
   a.n_split = P.n_split;
-  a.n_wg = P.n_waves / kVWaves;
+  a.n_wg = std::max(1, g->n_cu) * sh.wg_per_cu;
+  a.ipg = sh.items_per_grab;
   a.chunk = P.chunk;
   a.T = T;
   a.Q = T / 4;
@@ -542,35 +576,81 @@ VArgs make_vargs(pr_graph *g, VWork &w, double d, int T, int col0) {
   return a;
 }
 
+void launch_vsweeps(pr_graph *g, VArgs a, int par0, int cnt) {
+  for (int s = 0; s < cnt; ++s) {
+    a.par = (par0 + s) & 1;
+    hipLaunchKernelGGL(k_vsweep, dim3(a.n_wg), dim3(kVBlock), 0, g->work, a);
+    hipLaunchKernelGGL(k_vfinal, dim3(a.T), dim3(kVFin), 0, g->work, a);
+  }
+}
+
+// `cnt` sweeps from a hipGraph cached with the graph's sweep graphs, keyed by
+// the launch arguments (which hold no caller pointer), the first sweep's
+// parity and the count.  Launches after every column froze exit at once.
+int run_vsweeps(pr_graph *g, const VArgs &a, int par0, int cnt, bool use_graph) {
+  if (!use_graph) {
+    launch_vsweeps(g, a, par0, cnt);
+    PR_HIP(hipGetLastError());
+    return PR_OK;
+  }
+  std::vector<unsigned char> key(1 + sizeof(a) + 2 * sizeof(int));
+  key[0] = 'B';
+  memcpy(key.data() + 1, &a, sizeof(a));
+  const int extra[2] = {par0 & 1, cnt};
+  memcpy(key.data() + 1 + sizeof(a), extra, sizeof(extra));
+  for (auto &e : g->graph_cache)
+    if (e.key == key) {
+      PR_HIP(hipGraphLaunch(e.exec, g->work));
+      return PR_OK;
+    }
+  if (g->graph_cache.size() >= 32) {
+    for (auto &e : g->graph_cache) (void)hipGraphExecDestroy(e.exec);
+    g->graph_cache.clear();
+  }
+  hipGraph_t graph;
+  PR_HIP(hipStreamBeginCapture(g->work, hipStreamCaptureModeThreadLocal));
+  launch_vsweeps(g, a, par0, cnt);
+  hipError_t le = hipGetLastError();
+  hipError_t ce = hipStreamEndCapture(g->work, &graph);
+  if (le != hipSuccess) return pr_fail(PR_EDEVICE, "batched launch during capture: %s", hipGetErrorString(le));
+  if (ce != hipSuccess) return pr_fail(PR_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+  hipGraphExec_t exec;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return pr_fail(PR_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+  g->graph_cache.push_back(GraphEntry{key, exec});
+  g->graph_captures++;
+  PR_HIP(hipGraphLaunch(exec, g->work));
+  return PR_OK;
+}
+
 // Runs the T columns starting at col0 of the padded seed list to convergence
 // (or exactly fixed_sweeps sweeps when > 0); writes their columns of X.
 int run_columns(pr_graph *g, VWork &w, double d, double tol, int max_iter, int T, int col0, float *X, int k,
-                int *iters, double *resid, bool write_out, int fixed_sweeps) {
+                int *iters, double *resid, bool write_out, int fixed_sweeps, const pr_batch_shape &sh) {
   if (T < 4 || T > kVMaxT || (T % 4) != 0 || T > w.cols_cap)
     return pr_fail(PR_EDEVICE, "batched: %d columns per launch", T);
-  if (g->fwd.n_waves % kVWaves != 0) return pr_fail(PR_EDEVICE, "batched: wave count mismatch");
-  VArgs a = make_vargs(g, w, d, T, col0);
+  VArgs a = make_vargs(g, w, d, T, col0, sh);
   // one launch holding all k columns keeps its ranks in the caller's X (same
   // row-major layout), with no copy at the end
   const bool direct = write_out && T == k && ((uintptr_t)X % sizeof(float4)) == 0;
-  if (direct) a.x = reinterpret_cast<float4 *>(X);
+  float4 *xp = direct ? reinterpret_cast<float4 *>(X) : w.x;
+  VArgs ax = a;  // the kernels launched outside graphs take x directly
+  ax.x = xp;
   const int64_t rows = g->n * (int64_t)(T / 4);
   const int zgrid = (int)std::min<int64_t>(4096, (rows + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_vzero, dim3(zgrid), dim3(kBlock), 0, g->work, a.x, a.c0, rows);
-  hipLaunchKernelGGL(k_vseed, dim3(1), dim3(kVMaxT), 0, g->work, a, fixed_sweeps > 0 ? -1.0 : tol,
+  hipLaunchKernelGGL(k_vzero, dim3(zgrid), dim3(kBlock), 0, g->work, xp, a.c0, rows);
+  hipLaunchKernelGGL(k_vseed, dim3(1), dim3(kVMaxT), 0, g->work, ax, fixed_sweeps > 0 ? -1.0 : tol,
                      fixed_sweeps > 0 ? fixed_sweeps : max_iter);
   PR_HIP(hipGetLastError());
+  int rc;
+  if ((rc = set_vio(g, w, xp))) return rc;
   const int G = 8;
   int done_sweeps = 0;
   const int limit = fixed_sweeps > 0 ? fixed_sweeps : max_iter;
   for (;;) {
     const int cnt = std::min(G, limit - done_sweeps);
-    for (int s = 0; s < cnt; ++s) {
-      a.par = (done_sweeps + s) & 1;
-      hipLaunchKernelGGL(k_vsweep, dim3(a.n_wg), dim3(kVBlock), 0, g->work, a);
-      hipLaunchKernelGGL(k_vfinal, dim3(T), dim3(kVFin), 0, g->work, a);
-    }
-    PR_HIP(hipGetLastError());
+    if ((rc = run_vsweeps(g, a, done_sweeps, cnt, fixed_sweeps == 0))) return rc;
     PR_HIP(hipMemcpyAsync(w.host_st, w.st, sizeof(VState), hipMemcpyDeviceToHost, g->work));
     PR_HIP(hipStreamSynchronize(g->work));
     done_sweeps += cnt;
@@ -580,7 +660,7 @@ int run_columns(pr_graph *g, VWork &w, double d, double tol, int max_iter, int T
   }
   if (write_out && !direct) {
     const int ogrid = (int)std::min<int64_t>(4096, (g->n * T + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_vout, dim3(ogrid), dim3(kBlock), 0, g->work, a, X, k, col0);
+    hipLaunchKernelGGL(k_vout, dim3(ogrid), dim3(kBlock), 0, g->work, ax, X, k, col0);
     PR_HIP(hipGetLastError());
   }
   if (iters && resid) {
@@ -600,69 +680,80 @@ std::string tune_key(pr_graph *g, int k) {
   char dev[256] = "unknown";
   if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) snprintf(dev, sizeof(dev), "%s", prop.gcnArchName);
   char buf[512];
-  snprintf(buf, sizeof(buf), "n=%lld,m=%lld,k=%d,dev=%s", (long long)g->n, (long long)g->m, k, dev);
+  snprintf(buf, sizeof(buf), "n=%lld,m=%lld,sig=%016llx,k=%d,dev=%s", (long long)g->n, (long long)g->m,
+           (unsigned long long)g->signature, k, dev);
   return buf;
 }
 
-int tune_lookup(const char *path, const std::string &key) {
-  if (!path) return 0;
+// The launch shape recorded for `key` in the JSON-lines cache file, if any.
+bool tune_lookup(const char *path, const std::string &key, pr_batch_shape *out) {
+  if (!path) return false;
   FILE *f = fopen(path, "r");
-  if (!f) return 0;
+  if (!f) return false;
   char line[1024];
-  int best = 0;
+  bool found = false;
   const std::string pat = "\"key\": \"" + key + "\"";
   while (fgets(line, sizeof(line), f)) {
-    if (strstr(line, pat.c_str())) {
-      const char *t = strstr(line, "\"tile\": ");
-      if (t) best = atoi(t + 8);
+    if (!strstr(line, pat.c_str())) continue;
+    const char *t = strstr(line, "\"tile\": ");
+    const char *i = strstr(line, "\"items_per_grab\": ");
+    const char *w = strstr(line, "\"wg_per_cu\": ");
+    if (!t || !i || !w) continue;
+    pr_batch_shape s{atoi(t + 8), atoi(i + 18), atoi(w + 13)};
+    if (shape_ok(s)) {
+      *out = s;
+      found = true;
     }
   }
   fclose(f);
-  return best;
+  return found;
 }
 
-struct TuneMemo {
-  const pr_graph *g;
-  int k;
-  int tile;
-};
-std::vector<TuneMemo> g_tune_memo;
+// The tuning cache file is shared by every graph of the process.
+std::mutex g_tune_file;
 
 }  // namespace
 
 void fpr_batched_release(pr_graph *g) {
-  for (size_t i = 0; i < g_vwork.size();) {
-    if (g_vwork[i].first == g) {
-      if (g_vwork[i].second.host_st) (void)hipHostFree(g_vwork[i].second.host_st);
-      g_vwork.erase(g_vwork.begin() + i);
-    } else {
-      ++i;
-    }
+  VWork *w = static_cast<VWork *>(g->vwork);
+  if (w) {
+    if (w->host_st) (void)hipHostFree(w->host_st);
+    delete w;
+    g->vwork = nullptr;
   }
-  for (size_t i = 0; i < g_tune_memo.size();) {
-    if (g_tune_memo[i].g == g) g_tune_memo.erase(g_tune_memo.begin() + i);
-    else ++i;
-  }
+  g->tune_memo.clear();
 }
 
-extern "C" int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, int *tile, void *stream) {
+extern "C" void pr_batch_shape_default(pr_batch_shape *s) {
+  if (!s) return;
+  s->tile = kVMaxT;
+  s->items_per_grab = 1;
+  s->wg_per_cu = 2;
+}
+
+extern "C" int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, pr_batch_shape *shape, void *stream) {
   pr_clear_error();
-  if (!g || !tile) return pr_fail(PR_EINVAL, "pr_autotune_batched: NULL argument");
+  if (!g || !shape) return pr_fail(PR_EINVAL, "pr_autotune_batched: NULL argument");
   if (k < 1 || k > 1024) return pr_fail(PR_EINVAL, "k=%d outside [1, 1024]", k);
   if (g->weighted) return pr_fail(PR_EINVAL, "pr_autotune_batched: the graph has edge weights (unweighted graphs only)");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != g->device)
     return pr_fail(PR_EINVAL, "the graph lives on device %d but device %d is current", g->device, cur);
   const std::string key = tune_key(g, k);
-  for (auto &m : g_tune_memo)
-    if (m.g == g && m.k == k) {
-      *tile = m.tile;
+  for (auto &m : g->tune_memo)
+    if (m.k == k) {
+      *shape = pr_batch_shape{m.tile, m.ipw, m.wg};
       return PR_OK;
     }
-  int cached = tune_lookup(cache_path, key);
-  if (cached > 0) {
-    *tile = cached;
-    g_tune_memo.push_back(TuneMemo{g, k, cached});
+  pr_batch_shape cached;
+  bool hit;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_file);
+    hit = tune_lookup(cache_path, key, &cached);
+  }
+  if (hit) {
+    *shape = cached;
+    g->tune_memo.push_back(pr_graph::TuneMemo{k, cached.tile, cached.items_per_grab, cached.wg_per_cu});
     return PR_OK;
   }
   hipStream_t user = (hipStream_t)stream;
@@ -680,35 +771,46 @@ extern "C" int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, i
   PR_HIP(hipEventCreate(&e0));
   PR_HIP(hipEventCreate(&e1));
   double best_t = INFINITY;
-  int best = 4;
+  pr_batch_shape best{4, 1, 2};
   const int sweeps = 4;
-  for (int t = 4; t <= std::max(4, std::min(kVMaxT, kpad)); t *= 2) {
+  // tile widths 8..64 (4 when k is that small), items per grab 1/2/4,
+  // one or two sweep workgroups per compute unit: the results are the same
+  // bits for every shape, only the time differs
+  for (int t = std::min(8, std::max(4, kpad)); t <= std::max(4, std::min(kVMaxT, kpad)); t *= 2) {
     if ((rc = ensure_vwork(g, w, t))) return rc;
-    // one warm-up, one timed run of `sweeps` sweeps on t columns
-    if ((rc = run_columns(g, w, 0.85, 1.0, sweeps, t, 0, nullptr, k, nullptr, nullptr, false, sweeps))) return rc;
-    PR_HIP(hipEventRecord(e0, g->work));
-    if ((rc = run_columns(g, w, 0.85, 1.0, sweeps, t, 0, nullptr, k, nullptr, nullptr, false, sweeps))) return rc;
-    PR_HIP(hipEventRecord(e1, g->work));
-    PR_HIP(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    PR_HIP(hipEventElapsedTime(&ms, e0, e1));
-    const double per_col = ms / (double)t;
-    if (per_col < best_t) {
-      best_t = per_col;
-      best = t;
-    }
+    for (int ipg : {1, 2, 4})
+      for (int wg : {1, 2}) {
+        const pr_batch_shape sh{t, ipg, wg};
+        // one warm-up, one timed run of `sweeps` sweeps on t columns
+        if ((rc = run_columns(g, w, 0.85, 1.0, sweeps, t, 0, nullptr, k, nullptr, nullptr, false, sweeps, sh)))
+          return rc;
+        PR_HIP(hipEventRecord(e0, g->work));
+        if ((rc = run_columns(g, w, 0.85, 1.0, sweeps, t, 0, nullptr, k, nullptr, nullptr, false, sweeps, sh)))
+          return rc;
+        PR_HIP(hipEventRecord(e1, g->work));
+        PR_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        PR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double per_col = ms / (double)t;
+        if (per_col < best_t) {
+          best_t = per_col;
+          best = sh;
+        }
+      }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipEventRecord(g->ev_out, g->work);
   (void)hipStreamWaitEvent(user, g->ev_out, 0);
-  *tile = best;
-  g_tune_memo.push_back(TuneMemo{g, k, best});
+  *shape = best;
+  g->tune_memo.push_back(pr_graph::TuneMemo{k, best.tile, best.items_per_grab, best.wg_per_cu});
   if (cache_path) {
+    std::lock_guard<std::mutex> lock(g_tune_file);
     FILE *f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "{\"key\": \"%s\", \"tile\": %d, \"ms_per_column_sweep\": %.6f}\n", key.c_str(), best,
-              best_t / sweeps);
+      fprintf(f, "{\"key\": \"%s\", \"tile\": %d, \"items_per_grab\": %d, \"wg_per_cu\": %d, "
+                 "\"ms_per_column_sweep\": %.6f}\n",
+              key.c_str(), best.tile, best.items_per_grab, best.wg_per_cu, best_t / sweeps);
       fclose(f);
     }
   }
@@ -716,8 +818,8 @@ extern "C" int pr_autotune_batched(pr_graph *g, int k, const char *cache_path, i
 }
 
 extern "C" int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter, int k,
-                                const int32_t *seeds, int tile, float *X, int *iters, double *resid,
-                                void *stream) {
+                                const int32_t *seeds, const pr_batch_shape *shape, float *X, int *iters,
+                                double *resid, void *stream) {
   pr_clear_error();
   if (!g) return pr_fail(PR_EINVAL, "graph is NULL");
   if (!(d > 0.0 && d < 1.0)) return pr_fail(PR_EINVAL, "d=%g is not in (0, 1)", d);
@@ -726,25 +828,31 @@ extern "C" int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter,
   if (k < 1 || k > 1024) return pr_fail(PR_EINVAL, "k=%d outside [1, 1024]", k);
   if (!seeds || !X || !iters || !resid) return pr_fail(PR_EINVAL, "NULL argument");
   if (g->weighted) return pr_fail(PR_EINVAL, "pr_solve_batched: the graph has edge weights (unweighted graphs only)");
-  if (tile < 0 || tile > kVMaxT || (tile % 4) != 0)
-    return pr_fail(PR_EINVAL, "tile=%d must be 0 (autotune) or a multiple of 4 up to %d", tile, kVMaxT);
+  if (shape && !shape_ok(*shape))
+    return pr_fail(PR_EINVAL,
+                   "shape {tile %d, items_per_grab %d, wg_per_cu %d}: need a tile that is a multiple of 4 up to "
+                   "%d, 1..16 items per grab, 1 or 2 workgroups per compute unit",
+                   shape->tile, shape->items_per_grab, shape->wg_per_cu, kVMaxT);
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != g->device)
     return pr_fail(PR_EINVAL, "the graph lives on device %d but device %d is current", g->device, cur);
   int rc;
-  if (tile == 0) {
-    if ((rc = pr_autotune_batched(g, k, getenv("FUSEDPR_TUNE_CACHE"), &tile, stream))) return rc;
+  pr_batch_shape sh;
+  if (shape) {
+    sh = *shape;
+  } else if ((rc = pr_autotune_batched(g, k, getenv("FUSEDPR_TUNE_CACHE"), &sh, stream))) {
+    return rc;
   }
   hipStream_t user = (hipStream_t)stream;
   (void)hipEventRecord(g->ev_in, user);
   (void)hipStreamWaitEvent(g->work, g->ev_in, 0);
   VWork &w = *vwork_for(g);
   const int kpad = (k + 3) / 4 * 4;
-  const int per_launch = std::min(kpad, tile);
+  const int per_launch = std::min(kpad, sh.tile);
   if ((rc = ensure_seeds(g, w, kpad))) return rc;
   if ((rc = ensure_vwork(g, w, per_launch))) return rc;
   hipLaunchKernelGGL(k_vseeds, dim3((kpad + 255) / 256), dim3(256), 0, g->work, seeds, k, w.seeds, kpad);
-  PR_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), g->work));
+  hipLaunchKernelGGL(k_vclear, dim3(1), dim3(1), 0, g->work, w.flag);
   hipLaunchKernelGGL(k_vcheck, dim3((k + 255) / 256), dim3(256), 0, g->work, seeds, k, (int64_t)g->n, w.flag);
   int bad = 0;
   PR_HIP(hipMemcpyAsync(&bad, w.flag, sizeof(int), hipMemcpyDeviceToHost, g->work));
@@ -752,7 +860,7 @@ extern "C" int pr_solve_batched(pr_graph *g, double d, double tol, int max_iter,
   if (bad) return pr_fail(PR_EINVAL, "a seed vertex is outside [0, %lld)", (long long)g->n);
   for (int c0 = 0; c0 < kpad; c0 += per_launch) {
     const int T = std::min(per_launch, kpad - c0);
-    if ((rc = run_columns(g, w, d, tol, max_iter, T, c0, X, k, iters, resid, true, 0))) return rc;
+    if ((rc = run_columns(g, w, d, tol, max_iter, T, c0, X, k, iters, resid, true, 0, sh))) return rc;
   }
   PR_HIP(hipStreamSynchronize(g->work));
   (void)hipEventRecord(g->ev_out, g->work);

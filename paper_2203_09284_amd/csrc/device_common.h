@@ -101,11 +101,22 @@ struct LaneSum<double> {
   }
 };
 
+// FPR_NAIVE_SUM=1 builds a variant of the library whose FP32 sums are plain
+// (no compensation term): a test compares its error against the compensated
+// build's on a graph where a lane adds many terms far below its running sum.
+#ifndef FPR_NAIVE_SUM
+#define FPR_NAIVE_SUM 0
+#endif
+
 template <>
 struct LaneSum<float> {
   float s = 0.0f, c = 0.0f;
   __device__ __forceinline__ void add(float v) {
 #pragma clang fp contract(off)
+    if constexpr (FPR_NAIVE_SUM) {
+      s = s + v;
+      return;
+    }
     float t = s + v;
     if (fabsf(s) >= fabsf(v)) c += (s - t) + v;
     else c += (v - t) + s;
@@ -127,6 +138,10 @@ struct LaneSum<float> {
   // TwoSum of the leading parts, compensations added
   __device__ __forceinline__ void combine(float s2, float c2) {
 #pragma clang fp contract(off)
+    if constexpr (FPR_NAIVE_SUM) {
+      s = s + s2;
+      return;
+    }
     float t = s + s2;
     float bp = t - s;
     float err = (s - (t - bp)) + (s2 - bp);

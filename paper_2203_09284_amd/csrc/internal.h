@@ -67,6 +67,15 @@ struct SweepState {
   double raw;    // unscaled L1 (or max) change of the last sweep
 };
 
+// Where the sweeps of one plan find the caller's vectors: the rank vector x
+// (FP64 or FP32) and the teleport vector p (null = 1/n).  The block lives in
+// device memory and the kernels read it when they start, so a captured
+// hipGraph of sweeps serves every x and p without capturing again.
+struct IoPtrs {
+  void *x;
+  const double *p;
+};
+
 // One binned pull layout: vertices grouped by degree, neighbours re-laid in
 // bin order.  Used for the forward pull over in-edges and the transposed
 // pull over out-edges.
@@ -95,6 +104,9 @@ struct DevPlan {
   double *wave_part = nullptr;  // [3][part_stride] per-workgroup change, dangling mass, total mass;
                                 // block b's launch writes from b * (workgroups per launch)
   SweepState *st = nullptr;
+  IoPtrs *io = nullptr;           // device block read by the sweep kernels
+  IoPtrs io_last{nullptr, nullptr};  // what the last queued write put there
+  bool io_valid = false;
   int n_items = 0;
   int n_bitems = 0;
   int n_vrun = 0;
@@ -112,11 +124,19 @@ struct DevPlan {
   int *wave_cnt = nullptr;        // [n_blocks * n_waves] list length of each wavefront per block
   // contributionList layout (plan option with_cl): list position of every
   // edge = its position in tidx (tile rows) or cl_rows + its idx position
-  int32_t *cl_src = nullptr;      // [m] source of each out-edge (out-CSR order)
+  int32_t *cl_src = nullptr;      // [m] source of each out-edge, grouped by the launch that
+                                  // updates the source (cl_group), out-CSR order inside a group
   int32_t *cl_pos = nullptr;      // [m] its list position
   double *cl_w = nullptr;         // [m] its weight (weighted graphs)
   int64_t cl_size = 0;            // list positions (tiles * 512 + m)
   uint32_t cl_rows = 0;           // first position of the idx region
+  // in-place form (plan option with_inplace): the in-edges in vertex order
+  uint32_t *ip_ptr = nullptr;     // [n+1] offsets
+  int32_t *ip_src = nullptr;      // [m] source vertex ids
+  double *ip_w = nullptr;         // [m] weights (weighted graphs)
+  std::vector<int64_t> cl_group;  // [n_blocks + 2] first scatter entry of each group: sources
+                                  // updated by block b's launch, then by the finalize kernel
+  std::vector<uint8_t> upd_launch;  // host, during planning: the launch that updates each vertex
   std::vector<int64_t> inpos;     // host, during planning: in-CSR edge -> list position
   std::vector<int> block_slots;   // [n_blocks + 1] first gather slot of each block's non-hub
                                   // vertices (the hubs' slots come before block 0's)
@@ -126,6 +146,12 @@ struct DevPlan {
 };
 
 }  // namespace fpr
+
+// A hipGraph of queued sweeps, keyed by the bytes of its launch arguments.
+struct GraphEntry {
+  std::vector<unsigned char> key;
+  hipGraphExec_t exec;
+};
 
 struct pr_graph {
   int device = 0;
@@ -162,9 +188,28 @@ struct pr_graph {
   double *bpart = nullptr;   // per-item per-column partials
   size_t bpart_elems = 0;
   int *bhost = nullptr;
+  void *vwork = nullptr;  // batched workspace bookkeeping (batched.hip)
+  struct TuneMemo {
+    int k, tile, ipw, wg;
+  };
+  std::vector<TuneMemo> tune_memo;  // autotuned batched launch shapes of this graph
+  uint64_t signature = 0;           // hash of the graph (size, offsets, neighbours, weights)
+  // hipGraphs of sweeps captured for this graph; calls on one graph never
+  // overlap, so they need no lock
+  std::vector<GraphEntry> graph_cache;
+  int64_t graph_captures = 0;
   int64_t device_bytes = 0;
   std::vector<void *> owned;  // device allocations released by pr_graph_destroy
+  // Where fpr_dev_alloc takes device memory from: the library's own hipMalloc
+  // (kMemOwn), a count of the bytes only, with no device work (kMemCount; the
+  // planning run behind pr_graph_device_bytes), or the caller's buffer
+  // (kMemArena; pr_graph_bind), carved in 256-byte aligned pieces.
+  int mem_mode = 0;
+  unsigned char *arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
 };
+
+enum { kMemOwn = 0, kMemCount = 1, kMemArena = 2 };
 
 // plan.hip
 int fpr_dev_alloc(pr_graph *g, void **p, size_t bytes);

@@ -50,11 +50,23 @@ extern "C" void pr_plan_opts_default(pr_plan_opts *o) {
   o->with_adjoint = 0;
   o->gs_blocks = 0;
   o->with_cl = 0;
+  o->with_inplace = 0;
 }
 
 int fpr_dev_alloc(pr_graph *g, void **p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 8;
+  if (g->mem_mode != kMemOwn) {
+    const size_t piece = (bytes + 255) & ~(size_t)255;
+    if (g->mem_mode == kMemArena && g->arena_used + piece > g->arena_bytes)
+      return pr_fail(PR_ENOMEM, "pr_graph_bind: the device buffer (%zu bytes) is too small (%zu more needed)",
+                     g->arena_bytes, g->arena_used + piece - g->arena_bytes);
+    // counting: a distinct dummy address per piece (never dereferenced)
+    *p = g->mem_mode == kMemArena ? (void *)(g->arena + g->arena_used) : (void *)(uintptr_t)(4096 + g->arena_used);
+    g->arena_used += piece;
+    g->device_bytes += (int64_t)bytes;
+    return PR_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -70,7 +82,7 @@ template <typename T>
 static int upload(pr_graph *g, T **dst, const T *src, size_t count) {
   int rc = fpr_dev_alloc(g, (void **)dst, sizeof(T) * count);
   if (rc) return rc;
-  if (count) PR_HIP(hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice));
+  if (count && g->mem_mode != kMemCount) PR_HIP(hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice));
   return PR_OK;
 }
 
@@ -163,7 +175,12 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
     if (w) memcpy(&wv[rptr[i]], w + ptr[v], sizeof(double) * L);
   }
 
-  if (want_cl) P.inpos.assign((size_t)m, -1);
+  if (want_cl) {
+    P.inpos.assign((size_t)m, -1);
+    // the launch that updates each vertex: its block's, or the finalize
+    // kernel's (B) for the hubs split into chunks (set below)
+    P.upd_launch.assign(blk.begin(), blk.end());
+  }
   // Work items.  Per block, in launch order: hubs, one-wavefront rows (longest
   // first), tiles, zero rows.  Two lists share the rows and tiles:
   //  * the sweep list: a hub of at most 8 * chunk edges is one item of a
@@ -204,7 +221,10 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
       int64_t nch = (L + piece - 1) / piece;
       int slot = (int)chunks;
       hsplit.push_back(make_int4((int)i, slot, (int)nch, 0));
-      if (L > wg_max) msplit.push_back(make_int4((int)i, slot, (int)nch, 0));
+      if (L > wg_max) {
+        msplit.push_back(make_int4((int)i, slot, (int)nch, 0));
+        if (want_cl) P.upd_launch[rows[i]] = (uint8_t)B;
+      }
       chunks += nch;
       for (int64_t c = 0; c < nch; ++c) {
         bitems.push_back(make_int4(kHeavy, (int)i, (int)c, slot));
@@ -456,9 +476,30 @@ static int build_plan(pr_graph *g, DevPlan &P, int64_t n, const int64_t *ptr, co
   P.part_stride = B * g->grid;  // one partial per sweep workgroup and block
   if ((rc = fpr_dev_alloc(g, (void **)&P.wave_part, sizeof(double) * 3 * (size_t)P.part_stride))) return rc;
   if ((rc = fpr_dev_alloc(g, (void **)&P.st, sizeof(SweepState)))) return rc;
-  PR_HIP(hipMemset(P.st, 0, sizeof(SweepState)));
+  if (g->mem_mode != kMemCount) PR_HIP(hipMemset(P.st, 0, sizeof(SweepState)));
+  if ((rc = fpr_dev_alloc(g, (void **)&P.io, sizeof(IoPtrs)))) return rc;
+  if (g->mem_mode != kMemCount) PR_HIP(hipMemset(P.io, 0, sizeof(IoPtrs)));
   P.bytes = g->device_bytes - before;
   return PR_OK;
+}
+
+// 64-bit FNV-1a over 8-byte words of the stored graph: n, m, the in-edge
+// offsets, neighbours and weights.  Graphs of equal size but different edges
+// get different keys for their tuned settings.
+static uint64_t graph_signature(const pr_csr *c) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  auto mix = [&](uint64_t v) { h = (h ^ v) * 0x100000001b3ull; };
+  mix((uint64_t)c->n);
+  mix((uint64_t)c->m);
+  for (int64_t v = 0; v <= c->n; ++v) mix((uint64_t)c->in_ptr[v]);
+  for (int64_t e = 0; e < c->m; ++e) mix((uint64_t)(uint32_t)c->in_src[e] | ((uint64_t)e << 32));
+  if (c->in_w)
+    for (int64_t e = 0; e < c->m; ++e) {
+      uint64_t b;
+      memcpy(&b, &c->in_w[e], sizeof(b));
+      mix(b);
+    }
+  return h;
 }
 
 static void destroy(pr_graph *g) {
@@ -482,11 +523,15 @@ static void destroy(pr_graph *g) {
 
 extern "C" void pr_graph_destroy(pr_graph *g) { destroy(g); }
 
-extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_graph **out) {
-  pr_clear_error();
+// pr_graph_create (kMemOwn), the sizing run of pr_graph_device_bytes
+// (kMemCount: *out receives a graph holding only the count) and pr_graph_bind
+// (kMemArena: the device arrays in the caller's buffer).
+static int create_impl(const pr_csr *csr, const pr_plan_opts *opts, int mem_mode, void *arena, size_t arena_bytes,
+                       pr_graph **out) {
   if (!out) return pr_fail(PR_EINVAL, "pr_graph_create: out is NULL");
   *out = nullptr;
-  if (!csr || !csr->in_ptr || !csr->out_ptr || !csr->out_deg || csr->n < 1)
+  if (!csr || !csr->in_ptr || !csr->out_ptr || !csr->out_deg || csr->n < 1 || csr->m < 0 ||
+      (csr->m > 0 && (!csr->in_src || !csr->out_dst || !csr->out_to_in)) || (!csr->in_w != !csr->out_w))
     return pr_fail(PR_EINVAL, "pr_graph_create: csr is not a pr_build_csr result");
   if (csr->m > (int64_t)UINT32_MAX - 2)
     return pr_fail(PR_EINVAL, "pr_graph_create: %lld edges exceed the per-graph limit",
@@ -500,16 +545,36 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
     return pr_fail(PR_EINVAL,
                    "pr_graph_create: need chunk = 0 or 64 <= chunk <= 2^20, 0 <= tile_max_row <= 512, "
                    "1 <= tile_rows <= 128, 1 <= steps <= 64, 0 <= gs_blocks <= 64, gather_layout 0..2");
+  {
+    // the plan indexes with these arrays: offsets must be a monotone cover of
+    // [0, m] and every id must be a vertex, else the graph is refused
+    const int64_t n = csr->n, m = csr->m;
+    if (csr->in_ptr[0] != 0 || csr->in_ptr[n] != m || csr->out_ptr[0] != 0 || csr->out_ptr[n] != m)
+      return pr_fail(PR_EINVAL, "pr_graph_create: in_ptr / out_ptr do not span [0, m]");
+    for (int64_t v = 0; v < n; ++v) {
+      if (csr->in_ptr[v + 1] < csr->in_ptr[v] || csr->out_ptr[v + 1] < csr->out_ptr[v])
+        return pr_fail(PR_EINVAL, "pr_graph_create: decreasing offsets at vertex %lld", (long long)v);
+      if (csr->out_deg[v] != csr->out_ptr[v + 1] - csr->out_ptr[v])
+        return pr_fail(PR_EINVAL, "pr_graph_create: out_deg[%lld] disagrees with out_ptr", (long long)v);
+    }
+    for (int64_t e = 0; e < m; ++e)
+      if ((uint32_t)csr->in_src[e] >= (uint64_t)n || (uint32_t)csr->out_dst[e] >= (uint64_t)n)
+        return pr_fail(PR_EINVAL, "pr_graph_create: edge %lld names a vertex outside [0, n)", (long long)e);
+  }
   int dev_count = 0;
   hipError_t he = hipGetDeviceCount(&dev_count);
   if (he != hipSuccess || dev_count < 1)
     return pr_fail(PR_EDEVICE, "pr_graph_create: no HIP device (%s)", hipGetErrorString(he));
 
   pr_graph *g = new pr_graph();
+  g->mem_mode = mem_mode;
+  g->arena = static_cast<unsigned char *>(arena);
+  g->arena_bytes = arena_bytes;
   g->popts = o;
   g->n = csr->n;
   g->m = csr->m;
   g->weighted = csr->in_w != nullptr;
+  g->signature = graph_signature(csr);
   int rc = PR_OK;
   hipDeviceProp_t prop;
   if (hipGetDevice(&g->device) != hipSuccess || hipGetDeviceProperties(&prop, g->device) != hipSuccess) {
@@ -564,17 +629,52 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
       for (int64_t v = 0; v < n; ++v)
         for (int64_t e = csr->out_ptr[v]; e < csr->out_ptr[v + 1]; ++e) {
           const int64_t ie = csr->out_to_in[e];
+          if (ie < 0 || ie >= m)
+            return pr_fail(PR_EINVAL, "pr_graph_create: out_to_in[%lld] = %lld is not an in-edge position",
+                           (long long)e, (long long)ie);
           const int64_t p = g->fwd.inpos[(size_t)ie];
-          if (ie < 0 || ie >= m || p < 0 || p >= g->fwd.cl_size)
+          if (p < 0 || p >= g->fwd.cl_size)
             return pr_fail(PR_EDEVICE, "pr_graph_create: internal plan check failed (list position)");
           src[(size_t)e] = (int32_t)v;
           pos[(size_t)e] = (int32_t)p;
           if (csr->in_w) wv[(size_t)e] = csr->in_w[ie];
         }
       std::vector<int64_t>().swap(g->fwd.inpos);
+      // grouped by the launch that updates the source (stable, so out-edge
+      // order inside a group): the loop-fused list form scatters group b
+      // right after block b's launch, the split hubs' group after the
+      // finalize kernel
+      {
+        const int B = g->fwd.n_blocks;
+        const std::vector<uint8_t> &ul = g->fwd.upd_launch;
+        std::vector<int64_t> off(B + 2, 0);
+        for (int64_t e = 0; e < m; ++e) off[ul[(size_t)src[(size_t)e]] + 1]++;
+        for (int b = 0; b <= B; ++b) off[b + 1] += off[b];
+        g->fwd.cl_group = off;
+        std::vector<int32_t> s2((size_t)m), p2((size_t)m);
+        std::vector<double> w2(wv.size());
+        for (int64_t e = 0; e < m; ++e) {
+          const int64_t at = off[ul[(size_t)src[(size_t)e]]]++;
+          s2[(size_t)at] = src[(size_t)e];
+          p2[(size_t)at] = pos[(size_t)e];
+          if (!wv.empty()) w2[(size_t)at] = wv[(size_t)e];
+        }
+        src.swap(s2);
+        pos.swap(p2);
+        wv.swap(w2);
+        std::vector<uint8_t>().swap(g->fwd.upd_launch);
+      }
       if ((rc2 = upload(g, &g->fwd.cl_src, src.data(), src.size()))) return rc2;
       if ((rc2 = upload(g, &g->fwd.cl_pos, pos.data(), pos.size()))) return rc2;
       if (csr->in_w && (rc2 = upload(g, &g->fwd.cl_w, wv.data(), wv.size()))) return rc2;
+    }
+    if (o.with_inplace) {
+      // the in-place form reads the canonical in-lists as they are
+      std::vector<uint32_t> ip(n + 1);
+      for (int64_t v = 0; v <= n; ++v) ip[v] = (uint32_t)csr->in_ptr[v];
+      if ((rc2 = upload(g, &g->fwd.ip_ptr, ip.data(), ip.size()))) return rc2;
+      if ((rc2 = upload(g, &g->fwd.ip_src, csr->in_src, (size_t)csr->m))) return rc2;
+      if (csr->in_w && (rc2 = upload(g, &g->fwd.ip_w, csr->in_w, (size_t)csr->m))) return rc2;
     }
     if (o.with_adjoint) {
       if ((rc2 = build_plan(g, g->adj, n, csr->out_ptr, csr->out_dst, csr->out_w, o, false))) return rc2;
@@ -585,21 +685,59 @@ extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_g
       if (csr->out_w && (rc2 = upload(g, &g->out_w, csr->out_w, (size_t)csr->m))) return rc2;
       g->has_adj = true;
     }
+    if ((rc2 = fpr_dev_alloc(g, (void **)&g->red_tmp, sizeof(double) * 4096))) return rc2;
+    if (g->mem_mode == kMemCount) return PR_OK;  // sizes only: no stream, events or pinned state
     if (hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void **)&g->host_st, sizeof(SweepState)) != hipSuccess)
       return pr_fail(PR_EDEVICE, "pr_graph_create: stream/event/pinned allocation failed");
-    if ((rc2 = fpr_dev_alloc(g, (void **)&g->red_tmp, sizeof(double) * 4096))) return rc2;
     return PR_OK;
   }();
   if (rc != PR_OK) {
     destroy(g);
     return rc;
   }
+  // later (lazy) workspace allocations of a bound graph are the library's own
+  if (mem_mode == kMemArena) g->mem_mode = kMemOwn;
   *out = g;
   return PR_OK;
 }
+
+extern "C" int pr_graph_create(const pr_csr *csr, const pr_plan_opts *opts, pr_graph **out) {
+  pr_clear_error();
+  return create_impl(csr, opts, kMemOwn, nullptr, 0, out);
+}
+
+extern "C" int pr_graph_device_bytes(const pr_csr *csr, const pr_plan_opts *opts, size_t *bytes) {
+  pr_clear_error();
+  if (!bytes) return pr_fail(PR_EINVAL, "pr_graph_device_bytes: bytes is NULL");
+  pr_graph *g = nullptr;
+  int rc = create_impl(csr, opts, kMemCount, nullptr, 0, &g);
+  if (rc != PR_OK) return rc;
+  *bytes = g->arena_used;
+  g->owned.clear();
+  destroy(g);
+  return PR_OK;
+}
+
+extern "C" int pr_graph_bind(const pr_csr *csr, const pr_plan_opts *opts, void *dev_mem, size_t bytes,
+                             pr_graph **out) {
+  pr_clear_error();
+  if (!dev_mem || ((uintptr_t)dev_mem & 255) != 0)
+    return pr_fail(PR_EINVAL, "pr_graph_bind: dev_mem must be a 256-byte aligned device pointer");
+  hipPointerAttribute_t attr;
+  const hipError_t pe = hipPointerGetAttributes(&attr, dev_mem);
+  (void)hipGetLastError();  // a pointer HIP does not know leaves an error behind: clear it
+  if (pe != hipSuccess || attr.type != hipMemoryTypeDevice)
+    return pr_fail(PR_EINVAL, "pr_graph_bind: dev_mem is not device memory");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || attr.device != cur)
+    return pr_fail(PR_EINVAL, "pr_graph_bind: dev_mem lives on device %d, device %d is current", attr.device, cur);
+  return create_impl(csr, opts, kMemArena, dev_mem, bytes, out);
+}
+
+extern "C" void pr_graph_free(pr_graph *g) { destroy(g); }
 
 extern "C" int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *s) {
   pr_clear_error();
@@ -619,5 +757,7 @@ extern "C" int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *s) {
   s->grid = g->grid;
   s->gs_blocks = g->fwd.n_blocks;
   s->chunk = g->fwd.chunk;
+  s->graph_captures = g->graph_captures;
+  s->signature = g->signature;
   return PR_OK;
 }

@@ -36,6 +36,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -104,8 +105,7 @@ struct SweepArgs {
   double *wave_part;
   SweepState *st;
   const double *inv_w;
-  const double *p;
-  T *x;
+  const IoPtrs *io;  // the caller's x and p, read when the kernel starts
   T *c0;
   T *c1;
   const T *cl;
@@ -113,6 +113,7 @@ struct SweepArgs {
   double *trace;
   double d;
   double inv_n;
+  int64_t nv;  // vertices
   int n_items;
   int n_msplit;
   int chunk;
@@ -167,8 +168,8 @@ __device__ __forceinline__ Ctx<T> make_ctx(const SweepArgs<T> &a, const SweepSta
   C.idx = a.idx;
   C.w = a.w;
   C.inv_w = a.inv_w;
-  C.p = a.p;
-  C.x = a.x;
+  C.p = a.io->p;
+  C.x = static_cast<T *>(a.io->x);
   C.cl = a.cl;
   C.cl_rows = a.cl_rows;
   C.cin = (it & 1) ? a.c1 : a.c0;
@@ -637,6 +638,139 @@ void k_sweep(SweepArgs<T> a) {
   }
 }
 
+// The in-place form (Algorithm 2 / Eq. 9 swept in place, Section 4.3's
+// asynchronous blocks).  The contributions live in one array c in vertex
+// order, read and written during the sweep.  Wavefront w takes the blocks
+// w, w + W, ... of kIpVpb<T> consecutive vertices; for each block it copies
+// the block's contributions into its own LDS slice, then updates the block in
+// kIpVpb / 64 steps: in step k lane l updates vertex l * (kIpVpb / 64) + k of
+// the block, so each lane walks its own run of consecutive vertices in order.
+// A source inside the block is read from LDS, where it already holds this
+// sweep's value once its lane has passed it (the earlier vertices of every
+// run); a source outside the block is read from c as it stands, this sweep's
+// value if its block is done, the previous one if not (the asynchrony that
+// Section 4.3 allows; other XCDs see writes no sooner than the launch ends).
+// Within a step the rows use the values from before the step: lanes take the
+// rows of up to kIpShort in-edges one edge at a time, then the wavefront sums
+// the longer rows of the step one by one, its 64 lanes striding the list.
+// The update is Eq. 1 with the lagged dangling mass and, with kFlagScaled,
+// the mass-scaled teleport of the fused form; the new contribution goes to
+// LDS and to c.  Reductions as in k_sweep (one partial per workgroup).
+constexpr int kIpLds = 8192;  // LDS bytes per wavefront for its block
+constexpr int kIpShort = 32;  // longest row a single lane sums
+template <typename T>
+constexpr int kIpVpb = kIpLds / (int)sizeof(T);  // vertices per block: 1024 FP64, 2048 FP32
+
+template <typename T, bool WEIGHTED>
+__device__ __forceinline__ T ip_gather(const SweepArgs<T> &a, const T *blk, const T *c, int64_t b0, int nb,
+                                       uint32_t e) {
+  const int32_t s = sld(a.idx + e);
+  const uint32_t ls = (uint32_t)((int64_t)s - b0);
+  T v = ls < (uint32_t)nb ? blk[ls] : c[s];
+  if constexpr (WEIGHTED) v = wmul(v, sld(a.w + e));
+  return v;
+}
+
+template <typename T, bool WEIGHTED>
+__global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(FPR_WAVES_PER_EU)))
+void k_inplace(SweepArgs<T> a) {
+  constexpr int VPB = kIpVpb<T>;
+  constexpr int PER = VPB / 64;
+  __shared__ __align__(16) T blk_all[kSweepWaves][VPB];
+  __shared__ double s_part[3][kSweepWaves];
+  const SweepState *st = a.st;
+  if (st->done) return;
+  const Ctx<T> C = make_ctx<T, true>(a, st);
+  T *c = C.cout;  // == C.cin: one array, in place
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T *blk = blk_all[wave];
+  const int64_t W = (int64_t)gridDim.x * kSweepWaves;
+  const int64_t nblocks = (a.nv + VPB - 1) / VPB;
+  Red red;
+  for (int64_t b = (int64_t)blockIdx.x * kSweepWaves + wave; b < nblocks; b += W) {
+    const int64_t b0 = b * VPB;
+    const int nb = (int)min((int64_t)VPB, a.nv - b0);
+    for (int i = lane; i < nb; i += 64) blk[i] = c[b0 + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int k = 0; k < PER; ++k) {
+      const int i = lane * PER + k;
+      const bool act = i < nb;
+      uint32_t e0 = 0, e1 = 0;
+      if (act) {
+        e0 = sld(a.rptr + (b0 + i));
+        e1 = sld(a.rptr + (b0 + i + 1));
+      }
+      const bool lng = e1 - e0 > (uint32_t)kIpShort;
+      LaneSum<T> acc;
+      if (act && !lng) {
+        uint32_t e = e0;
+        for (; e + 4 <= e1; e += 4) {
+          T v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = ip_gather<T, WEIGHTED>(a, blk, c, b0, nb, e + j);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc.add(v[j]);
+        }
+        for (; e < e1; ++e) acc.add(ip_gather<T, WEIGHTED>(a, blk, c, b0, nb, e));
+      }
+      double sum = acc.value();
+      // the step's long rows, one at a time, by the whole wavefront
+      uint64_t lm = __ballot(act && lng);
+      while (lm) {
+        const int r = __builtin_ctzll(lm);
+        lm &= lm - 1;
+        const uint32_t f0 = __builtin_amdgcn_readlane(e0, r), f1 = __builtin_amdgcn_readlane(e1, r);
+        LaneSum<T> part;
+        for (uint32_t e = f0 + lane; e < f1; e += 64) part.add(ip_gather<T, WEIGHTED>(a, blk, c, b0, nb, e));
+        part.group_reduce(64);
+        if (lane == r) sum = part.value();
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (act) {
+        const int64_t u = b0 + i;
+        const double xo = (double)C.x[u];
+        const double iw = sld(C.inv_w + u);
+        const double pu = (C.flags & kFlagUniformP) ? C.inv_n : sld(C.p + u);
+        const double xn = C.tele * pu + C.d * (sum + C.dterm);
+        const T xs = (T)xn;
+        C.x[u] = xs;
+        const double xd = (double)xs;
+        if (iw != 0.0) {
+          const T cv = (T)(xd * iw);
+          blk[i] = cv;
+          c[u] = cv;
+        } else {
+          red.dang += xd;
+        }
+        red.chg += fabs(xd - xo);
+        red.tot += xd;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  const double chg = wave_sum(red.chg);
+  const double dang = wave_sum(red.dang);
+  const double tot = wave_sum(red.tot);
+  if (lane == 0) {
+    s_part[0][wave] = chg;
+    s_part[1][wave] = dang;
+    s_part[2][wave] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int r = threadIdx.x;
+    double v = s_part[r][0];
+    for (int k = 1; k < kSweepWaves; ++k) v += s_part[r][k];
+    a.wave_part[(size_t)r * a.part_stride + a.part_base + blockIdx.x] = v;
+  }
+}
+
 // Phase 1 of the edge-centric form (Algorithm 1): every out-edge v -> u gets
 // v's contribution x_v / W_v (times the edge weight) in its contributionList
 // position, the position of that edge in the sweep's edge layout.  The value
@@ -648,7 +782,7 @@ struct ScatterArgs {
   const int32_t *pos;  // [m] its list position
   const double *w;     // [m] its weight (weighted graphs)
   const double *inv_w;
-  const T *x;
+  const IoPtrs *io;  // x: the ranks of the previous sweep
   T *cl;
   int64_t m;
   const SweepState *st;
@@ -658,9 +792,10 @@ constexpr int kScatterGrid = 2048;
 template <typename T, bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_scatter(ScatterArgs<T> a) {
   if (a.st->done) return;
+  const T *x = static_cast<const T *>(a.io->x);
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < a.m; e += (int64_t)gridDim.x * kBlock) {
     const int32_t v = sld(a.src + e);
-    const double xd = (double)a.x[v];
+    const double xd = (double)x[v];
     T c = (T)(xd * a.inv_w[v]);
     if constexpr (WEIGHTED) c = wmul(c, sld(a.w + e));
     a.cl[sld(a.pos + e)] = c;
@@ -788,8 +923,9 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs<T> a) {
     a.x[u] = xs;
     const double xd = (double)xs;
     const double iw = a.inv_w[u];
-    if (a.raw) a.c[a.gpos[u]] = xs;
-    else if (iw != 0.0) a.c[a.gpos[u]] = (T)(xd * iw);
+    const size_t slot = a.gpos ? (size_t)a.gpos[u] : (size_t)u;  // null: vertex order
+    if (a.raw) a.c[slot] = xs;
+    else if (iw != 0.0) a.c[slot] = (T)(xd * iw);
     if (iw == 0.0) dang += xd;
     tot += xd;
   }
@@ -910,11 +1046,13 @@ int ensure_trace(pr_graph *g, int max_iter) {
   return PR_OK;
 }
 
+// Initial ranks and contributions (in the plan's gather layout, or in vertex
+// order for the in-place form).
 template <typename T>
 int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T *x, double tol,
-                int max_iter, T *c0 = nullptr, int raw = 0) {
+                int max_iter, T *c0 = nullptr, int raw = 0, bool vertex_order = false) {
   InitArgs<T> a;
-  a.gpos = P.gpos;
+  a.gpos = vertex_order ? nullptr : P.gpos;
   a.inv_w = g->inv_w;
   a.p = p;
   a.x_in = x_in;
@@ -933,9 +1071,28 @@ int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T 
   return PR_OK;
 }
 
+__global__ void k_set_io(IoPtrs *io, void *x, const double *p) {
+  io->x = x;
+  io->p = p;
+}
+
+// Points the plan's IoPtrs block at x and p (queued on the work stream, so it
+// takes effect for the launches queued after it).  Skipped when the block
+// already holds them.
+int set_io(pr_graph *g, DevPlan &P, void *x, const double *p) {
+  if (P.io_valid && P.io_last.x == x && P.io_last.p == p) return PR_OK;
+  hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, g->work, P.io, x, p);
+  PR_HIP(hipGetLastError());
+  P.io_last = IoPtrs{x, p};
+  P.io_valid = true;
+  return PR_OK;
+}
+
+// The launch arguments of the sweeps of plan P; x and p go through P's IoPtrs
+// block (set_io), only whether p is given is part of the arguments.
 template <typename T>
-SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d, int flags,
-                       double *trace, T *c0 = nullptr, T *c1 = nullptr) {
+SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, double d, int flags,
+                       double *trace, T *c0 = nullptr, T *c1 = nullptr, int form = PR_JACOBI) {
   SweepArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.rows = P.rows;
@@ -955,8 +1112,7 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   a.wave_part = P.wave_part;
   a.st = P.st;
   a.inv_w = g->inv_w;
-  a.p = p;
-  a.x = x;
+  a.io = P.io;
   a.c0 = c0 ? c0 : contrib<T>(g, 0);
   a.c1 = c1 ? c1 : contrib<T>(g, 1);
   a.cl = cl_buf<T>(g);
@@ -980,6 +1136,16 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, T *x, double d,
   a.n_part = P.n_waves / kSweepWaves;
   a.fresh_lo = 0;
   a.fresh_hi = 0;
+  a.nv = g->n;
+  if (form == PR_INPLACE) {
+    // vertex-order in-lists and one contribution array, updated in place
+    a.rptr = P.ip_ptr;
+    a.idx = P.ip_src;
+    a.w = P.ip_w;
+    a.c1 = a.c0;
+    a.n_msplit = 0;
+    a.hot = 0;
+  }
   return a;
 }
 
@@ -1011,6 +1177,51 @@ void launch_one(const DevPlan &P, const SweepArgs<T> &a0, hipStream_t s, hipEven
   hipLaunchKernelGGL((k_finalize<T, FUSED>), dim3(1), dim3(kFinBlock), 0, s, a);
 }
 
+// Phase 1 of the list forms over scatter entries [lo, hi) (Algorithm 1's
+// scatter, or Algorithm 2's fused scatter of one launch's vertices).
+template <typename T>
+void scatter_range(pr_graph *g, const SweepArgs<T> &a, bool weighted, int64_t lo, int64_t hi, hipStream_t s) {
+  if (hi <= lo) return;
+  const DevPlan &P = g->fwd;
+  ScatterArgs<T> sa;
+  sa.src = P.cl_src + lo;
+  sa.pos = P.cl_pos + lo;
+  sa.w = P.cl_w ? P.cl_w + lo : nullptr;
+  sa.inv_w = g->inv_w;
+  sa.io = a.io;
+  sa.cl = const_cast<T *>(a.cl);
+  sa.m = hi - lo;
+  sa.st = a.st;
+  const int grid = (int)std::min<int64_t>(kScatterGrid, (hi - lo + kBlock - 1) / kBlock);
+  if (weighted) hipLaunchKernelGGL((k_scatter<T, true>), dim3(grid), dim3(kBlock), 0, s, sa);
+  else hipLaunchKernelGGL((k_scatter<T, false>), dim3(grid), dim3(kBlock), 0, s, sa);
+}
+
+// The loop-fused list form (Algorithm 2 with the paper's contributionList):
+// per Gauss-Seidel block, the launch that sums its rows' list slices and
+// updates them, then the scatter of those vertices' new contributions into
+// the list; the split hubs, updated by the finalize kernel, scatter after it.
+// A block reads, through the list, this sweep's contributions of the blocks
+// before it and the previous sweep's of the others: the values the block
+// Gauss-Seidel pull gathers, summed in the same order.
+template <typename T>
+void launch_fused_list(pr_graph *g, const SweepArgs<T> &a0, bool weighted, hipStream_t s, hipEvent_t mark) {
+  const DevPlan &P = g->fwd;
+  const int B = P.n_blocks, G = a0.n_waves / kSweepWaves;
+  SweepArgs<T> a = a0;
+  for (int b = 0; b < B; ++b) {
+    a.blk_lo = b;
+    a.blk_hi = b + 1;
+    a.part_base = b * G;
+    hipLaunchKernelGGL((k_sweep<T, false, kModeList>), dim3(G), dim3(kSweepBlock), 0, s, a);
+    scatter_range<T>(g, a, weighted, P.cl_group[b], P.cl_group[b + 1], s);
+  }
+  if (mark) (void)hipEventRecord(mark, s);
+  a.n_part = B * G;
+  hipLaunchKernelGGL((k_finalize<T, false>), dim3(1), dim3(kFinBlock), 0, s, a);
+  scatter_range<T>(g, a, weighted, P.cl_group[B], P.cl_group[B + 1], s);
+}
+
 template <typename T>
 void launch_marked(pr_graph *g, const SweepArgs<T> &a, int form, bool weighted, hipStream_t s,
                    hipEvent_t mark) {
@@ -1023,13 +1234,21 @@ void launch_marked(pr_graph *g, const SweepArgs<T> &a, int form, bool weighted, 
     sa.pos = P.cl_pos;
     sa.w = P.cl_w;
     sa.inv_w = g->inv_w;
-    sa.x = a.x;
+    sa.io = a.io;
     sa.cl = const_cast<T *>(a.cl);
     sa.m = P.m;
     sa.st = a.st;
     if (weighted) hipLaunchKernelGGL((k_scatter<T, true>), dim3(kScatterGrid), dim3(kBlock), 0, s, sa);
     else hipLaunchKernelGGL((k_scatter<T, false>), dim3(kScatterGrid), dim3(kBlock), 0, s, sa);
     launch_one<T, false, kModeList>(P, a, s, mark);
+  } else if (form == PR_FUSED_EDGE_LIST) {
+    launch_fused_list<T>(g, a, weighted, s, mark);
+  } else if (form == PR_INPLACE) {
+    const dim3 grid(a.n_waves / kSweepWaves), block(kSweepBlock);
+    if (weighted) hipLaunchKernelGGL((k_inplace<T, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_inplace<T, false>), grid, block, 0, s, a);
+    if (mark) (void)hipEventRecord(mark, s);
+    hipLaunchKernelGGL((k_finalize<T, true>), dim3(1), dim3(kFinBlock), 0, s, a);
   } else if (form == PR_FUSED) {
     if (weighted) launch_one<T, true, kModeWeighted>(P, a, s, mark);
     else launch_one<T, true, kModePlain>(P, a, s, mark);
@@ -1045,14 +1264,9 @@ void launch_sweeps(pr_graph *g, const SweepArgs<T> &a, int form, bool weighted, 
   for (int k = 0; k < count; ++k) launch_marked<T>(g, a, form, weighted, s, nullptr);
 }
 
-// Cached hipGraph executables of `count` sweeps for one exact argument set.
-struct GraphEntry {
-  const void *key_graph;
-  std::vector<unsigned char> key;
-  hipGraphExec_t exec;
-};
-static std::vector<GraphEntry> g_graph_cache;
-
+// The queued sweeps run from a hipGraph cached per graph, keyed by the bytes
+// of their launch arguments (which hold no caller pointer: x and p go through
+// the plan's IoPtrs block), the form and the sweep count.
 template <typename T>
 int run_sweeps(pr_graph *g, const SweepArgs<T> &a, int form, bool use_graph, int count) {
   if (!use_graph) {
@@ -1064,15 +1278,15 @@ int run_sweeps(pr_graph *g, const SweepArgs<T> &a, int form, bool use_graph, int
   memcpy(key.data(), &a, sizeof(a));
   int extra[3] = {form, count, (int)sizeof(T)};
   memcpy(key.data() + sizeof(a), extra, sizeof(extra));
-  for (auto &e : g_graph_cache) {
-    if (e.key_graph == g && e.key == key) {
+  for (auto &e : g->graph_cache) {
+    if (e.key == key) {
       PR_HIP(hipGraphLaunch(e.exec, g->work));
       return PR_OK;
     }
   }
-  if (g_graph_cache.size() >= 32) {
-    for (auto &e : g_graph_cache) (void)hipGraphExecDestroy(e.exec);
-    g_graph_cache.clear();
+  if (g->graph_cache.size() >= 32) {
+    for (auto &e : g->graph_cache) (void)hipGraphExecDestroy(e.exec);
+    g->graph_cache.clear();
   }
   hipGraph_t graph;
   PR_HIP(hipStreamBeginCapture(g->work, hipStreamCaptureModeThreadLocal));
@@ -1085,7 +1299,8 @@ int run_sweeps(pr_graph *g, const SweepArgs<T> &a, int form, bool use_graph, int
   hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) return pr_fail(PR_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
-  g_graph_cache.push_back(GraphEntry{g, key, exec});
+  g->graph_cache.push_back(GraphEntry{key, exec});
+  g->graph_captures++;
   PR_HIP(hipGraphLaunch(exec, g->work));
   return PR_OK;
 }
@@ -1096,18 +1311,51 @@ int poll_state(pr_graph *g, DevPlan &P) {
   return PR_OK;
 }
 
+bool is_list_form(int form) { return form == PR_EDGE_LIST || form == PR_FUSED_EDGE_LIST; }
+
+// The loop-fused list form keeps its list up to date sweep by sweep: it is
+// filled once from the start vector (Algorithm 2 primes it before its loop).
+template <typename T>
+void prime_list(pr_graph *g, const SweepArgs<T> &a, int form) {
+  if (form == PR_FUSED_EDGE_LIST) scatter_range<T>(g, a, g->weighted, 0, g->fwd.m, g->work);
+}
+
+// The device buffers of a solve: the contribution arrays of each precision
+// (previous and current sweep) and the FP32 copy of the ranks.  Null members
+// mean the graph's own buffers, allocated on first use.
+struct SolveBufs {
+  double *c64[2] = {nullptr, nullptr};
+  float *c32[2] = {nullptr, nullptr};
+  float *x32 = nullptr;
+};
+
+template <typename T>
+void bufs_of(const SolveBufs &b, T *&c0, T *&c1) {
+  if constexpr (sizeof(T) == 8) {
+    c0 = b.c64[0];
+    c1 = b.c64[1];
+  } else {
+    c0 = b.c32[0];
+    c1 = b.c32[1];
+  }
+}
+
 // One stage: init from (p | x_in) then sweeps until the state says done.
 // stall: stop polling once the residual fails to halve between polls (FP32 floor).
 template <typename T>
 int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o, const double *p,
                 const double *x_in, T *x, int flags, int form, double *trace, bool stall,
-                int *iters, double *resid) {
+                int *iters, double *resid, const SolveBufs &bufs) {
   int rc;
-  if ((rc = ensure_contrib<T>(g))) return rc;
-  if (form == PR_EDGE_LIST && (rc = ensure_cl<T>(g))) return rc;
+  T *c0 = nullptr, *c1 = nullptr;
+  bufs_of<T>(bufs, c0, c1);
+  if (!c0 && (rc = ensure_contrib<T>(g))) return rc;
+  if (is_list_form(form) && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
-  if ((rc = launch_init<T>(g, P, p, x_in, x, tol, max_iter))) return rc;
-  SweepArgs<T> a = make_args<T>(g, P, p, x, d, flags, trace);
+  if ((rc = launch_init<T>(g, P, p, x_in, x, tol, max_iter, c0, 0, form == PR_INPLACE))) return rc;
+  if ((rc = set_io(g, P, x, p))) return rc;
+  SweepArgs<T> a = make_args<T>(g, P, p, d, flags, trace, c0, c1, form);
+  prime_list<T>(g, a, form);
   const int G = std::max(1, o.sweeps_per_poll);
   double prev = INFINITY;
   int done_sweeps = 0;
@@ -1133,18 +1381,22 @@ int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &
 int validate_common(pr_graph *g, double d, const pr_opts &o) {
   if (!g) return pr_fail(PR_EINVAL, "graph is NULL");
   if (!(d > 0.0 && d < 1.0)) return pr_fail(PR_EINVAL, "d=%g is not in (0, 1)", d);
-  if (o.mode != PR_JACOBI && o.mode != PR_FUSED && o.mode != PR_EDGE_LIST)
+  if (o.mode != PR_JACOBI && o.mode != PR_FUSED && o.mode != PR_EDGE_LIST && o.mode != PR_INPLACE &&
+      o.mode != PR_FUSED_EDGE_LIST)
     return pr_fail(PR_EINVAL, "bad mode %d", o.mode);
-  if (o.mode == PR_EDGE_LIST && !g->fwd.cl_pos)
-    return pr_fail(PR_EINVAL, "the edge-list form needs a graph planned with with_cl = 1");
+  if (o.mode == PR_INPLACE && !g->fwd.ip_ptr)
+    return pr_fail(PR_EINVAL, "the in-place form needs a graph planned with with_inplace = 1");
+  if ((o.mode == PR_EDGE_LIST || o.mode == PR_FUSED_EDGE_LIST) && !g->fwd.cl_pos)
+    return pr_fail(PR_EINVAL, "the edge-list forms need a graph planned with with_cl = 1");
   if (o.precision != PR_FP64 && o.precision != PR_FP32)
     return pr_fail(PR_EINVAL, "bad precision %d", o.precision);
   if (o.dangling != PR_DANGLING_UNIFORM && o.dangling != PR_DANGLING_LEAK)
     return pr_fail(PR_EINVAL, "bad dangling mode %d", o.dangling);
   if (o.norm != PR_NORM_L1 && o.norm != PR_NORM_LINF) return pr_fail(PR_EINVAL, "bad norm %d", o.norm);
-  if (o.mode == PR_FUSED && o.fused_scaled && (o.dangling != PR_DANGLING_UNIFORM || o.norm != PR_NORM_L1))
+  const bool gs = o.mode == PR_FUSED || o.mode == PR_INPLACE || o.mode == PR_FUSED_EDGE_LIST;
+  if (gs && o.fused_scaled && (o.dangling != PR_DANGLING_UNIFORM || o.norm != PR_NORM_L1))
     return pr_fail(PR_EINVAL, "the mass-scaled fused form needs uniform dangling and the L1 norm");
-  if (o.mode == PR_FUSED && o.norm == PR_NORM_LINF)
+  if (gs && o.norm == PR_NORM_LINF)
     return pr_fail(PR_EINVAL, "the max-norm residual is supported by the Jacobi form only");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != g->device)
@@ -1156,8 +1408,9 @@ int flags_of(const pr_opts &o) {
   int f = 0;
   if (o.dangling == PR_DANGLING_LEAK) f |= kFlagLeak;
   if (o.norm == PR_NORM_LINF) f |= kFlagLinf;
-  if (o.mode == PR_FUSED && o.fused_scaled) f |= kFlagScaled;
-  if (o.mode == PR_EDGE_LIST) f |= kFlagList;
+  if ((o.mode == PR_FUSED || o.mode == PR_INPLACE || o.mode == PR_FUSED_EDGE_LIST) && o.fused_scaled)
+    f |= kFlagScaled;
+  if (o.mode == PR_EDGE_LIST || o.mode == PR_FUSED_EDGE_LIST) f |= kFlagList;
   return f;
 }
 
@@ -1179,14 +1432,8 @@ struct StreamJoin {
 // ------------------------------------------------------------------ ABI --
 
 void fpr_sweep_release(pr_graph *g) {
-  for (size_t i = 0; i < g_graph_cache.size();) {
-    if (g_graph_cache[i].key_graph == g) {
-      (void)hipGraphExecDestroy(g_graph_cache[i].exec);
-      g_graph_cache.erase(g_graph_cache.begin() + i);
-    } else {
-      ++i;
-    }
-  }
+  for (auto &e : g->graph_cache) (void)hipGraphExecDestroy(e.exec);
+  g->graph_cache.clear();
 }
 
 int fpr_grid_for(pr_graph *g) {
@@ -1214,18 +1461,24 @@ extern "C" void pr_opts_default(pr_opts *o) {
   o->trace = nullptr;
 }
 
-extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts *opts,
-                        const double *p, double *x, int *iters, double *resid, void *stream) {
-  pr_clear_error();
-  pr_opts o;
-  pr_opts_default(&o);
-  if (opts) o = *opts;
+namespace {
+
+int validate_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o, const double *x,
+                   const int *iters, const double *resid) {
   int rc = validate_common(g, d, o);
   if (rc) return rc;
   if (!(tol > 0.0)) return pr_fail(PR_EINVAL, "tol=%g must be > 0", tol);
   if (max_iter < 1) return pr_fail(PR_EINVAL, "max_iter=%d must be >= 1", max_iter);
   if (!x) return pr_fail(PR_EINVAL, "x is NULL");
   if (!iters || !resid) return pr_fail(PR_EINVAL, "iters/resid are NULL");
+  return PR_OK;
+}
+
+// The body of pr_solve; `bufs` names the device buffers to work in (members
+// left null are the graph's own).
+int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o, const double *p, double *x,
+               int *iters, double *resid, void *stream, const SolveBufs &bufs) {
+  int rc;
   StreamJoin join(g, stream);
   double *trace = nullptr;
   if (o.trace) {
@@ -1240,27 +1493,31 @@ extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const p
   double target = tol;
   if (o.precision == PR_FP64) {
     if ((rc = solve_stage<double>(g, d, tol, max_iter, o, p, o.warm_start ? x : nullptr, x, flags,
-                                  form, trace, false, &it, &r)))
+                                  form, trace, false, &it, &r, bufs)))
       return rc;
     if (scaled) {
       hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const double *)x,
                          x, g->n, (const SweepState *)g->fwd.st, 1);
     }
   } else {
-    if (!g->x32 && (rc = fpr_dev_alloc(g, (void **)&g->x32, sizeof(float) * (size_t)g->n))) return rc;
+    float *x32 = bufs.x32;
+    if (!x32) {
+      if (!g->x32 && (rc = fpr_dev_alloc(g, (void **)&g->x32, sizeof(float) * (size_t)g->n))) return rc;
+      x32 = g->x32;
+    }
     const double tol32 = o.fp32_tol > 0.0 ? o.fp32_tol : std::max(tol, 1e-7);
     const double rtol = o.refine_tol < 0.0 ? tol : o.refine_tol;
-    if ((rc = solve_stage<float>(g, d, tol32, max_iter, o, p, o.warm_start ? x : nullptr, g->x32,
-                                 flags, form, trace, rtol > 0.0, &it, &r)))
+    if ((rc = solve_stage<float>(g, d, tol32, max_iter, o, p, o.warm_start ? x : nullptr, x32,
+                                 flags, form, trace, rtol > 0.0, &it, &r, bufs)))
       return rc;
     target = rtol > 0.0 ? rtol : tol32;
     hipLaunchKernelGGL(k_to64<float>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
-                       (const float *)g->x32, x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0);
+                       (const float *)x32, x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0);
     if (rtol > 0.0 && it < max_iter) {
       int it2 = 0;
       double r2 = INFINITY;
       if ((rc = solve_stage<double>(g, d, rtol, max_iter - it, o, p, x, x, flags, form,
-                                    trace ? trace + it : nullptr, false, &it2, &r2)))
+                                    trace ? trace + it : nullptr, false, &it2, &r2, bufs)))
         return rc;
       if (scaled)
         hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
@@ -1279,6 +1536,96 @@ extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const p
   return (r < target) ? PR_OK : PR_NOT_CONVERGED;
 }
 
+}  // namespace
+
+extern "C" int pr_solve(pr_graph *g, double d, double tol, int max_iter, const pr_opts *opts,
+                        const double *p, double *x, int *iters, double *resid, void *stream) {
+  pr_clear_error();
+  pr_opts o;
+  pr_opts_default(&o);
+  if (opts) o = *opts;
+  int rc = validate_solve(g, d, tol, max_iter, o, x, iters, resid);
+  if (rc) return rc;
+  return solve_impl(g, d, tol, max_iter, o, p, x, iters, resid, stream, SolveBufs());
+}
+
+// ------------------------------------------------------- caller workspace --
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The workspace a solve with options o takes: two contribution arrays of each
+// precision it sweeps in (FP64 also for the refinement of an FP32 solve) and
+// the FP32 copy of the ranks, each rounded up to 256 bytes.  With `base`, the
+// buffers are carved from it in that order.
+size_t ws_layout(const pr_graph *g, const pr_opts &o, double tol, unsigned char *base, SolveBufs *b) {
+  const size_t n = (size_t)g->n;
+  const double rtol = o.refine_tol < 0.0 ? tol : o.refine_tol;
+  const bool fp64 = o.precision == PR_FP64 || rtol > 0.0;
+  const bool fp32 = o.precision == PR_FP32;
+  const size_t b64 = align256(sizeof(double) * n), b32 = align256(sizeof(float) * n);
+  size_t off = 0;
+  if (fp64) {
+    if (base) {
+      b->c64[0] = reinterpret_cast<double *>(base + off);
+      b->c64[1] = reinterpret_cast<double *>(base + off + b64);
+    }
+    off += 2 * b64;
+  }
+  if (fp32) {
+    if (base) {
+      b->c32[0] = reinterpret_cast<float *>(base + off);
+      b->c32[1] = reinterpret_cast<float *>(base + off + b32);
+      b->x32 = reinterpret_cast<float *>(base + off + 2 * b32);
+    }
+    off += 3 * b32;
+  }
+  return off;
+}
+
+// What a solve in a caller's (or the static) workspace cannot take: the
+// forms and options whose buffers it would have to allocate or clear.
+int ws_refuse(const char *who, const pr_opts &o) {
+  if (is_list_form(o.mode))
+    return pr_fail(PR_EINVAL, "%s: the edge-list forms need their contributionList (m values)", who);
+  if (o.trace) return pr_fail(PR_EINVAL, "%s: a residual trace needs a device buffer", who);
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" int pr_workspace_bytes(const pr_graph *g, double tol, const pr_opts *opts, size_t *bytes) {
+  pr_clear_error();
+  if (!g || !bytes) return pr_fail(PR_EINVAL, "pr_workspace_bytes: NULL argument");
+  pr_opts o;
+  pr_opts_default(&o);
+  if (opts) o = *opts;
+  int rc = ws_refuse("pr_workspace_bytes", o);
+  if (rc) return rc;
+  *bytes = ws_layout(g, o, tol, nullptr, nullptr);
+  return PR_OK;
+}
+
+extern "C" int pr_solve_ws(pr_graph *g, double d, double tol, int max_iter, const pr_opts *opts, const double *p,
+                           double *x, void *ws, size_t ws_bytes, int *iters, double *resid, void *stream) {
+  pr_clear_error();
+  pr_opts o;
+  pr_opts_default(&o);
+  if (opts) o = *opts;
+  int rc = validate_solve(g, d, tol, max_iter, o, x, iters, resid);
+  if (rc) return rc;
+  if ((rc = ws_refuse("pr_solve_ws", o))) return rc;
+  if (!ws || ((uintptr_t)ws & 255) != 0)
+    return pr_fail(PR_EINVAL, "pr_solve_ws: ws must be a 256-byte aligned device pointer");
+  const size_t need = ws_layout(g, o, tol, nullptr, nullptr);
+  if (ws_bytes < need)
+    return pr_fail(PR_EINVAL, "pr_solve_ws: the workspace holds %zu bytes, the solve needs %zu", ws_bytes, need);
+  SolveBufs b;
+  ws_layout(g, o, tol, static_cast<unsigned char *>(ws), &b);
+  return solve_impl(g, d, tol, max_iter, o, p, x, iters, resid, stream, b);
+}
+
 namespace {
 
 // `sweeps` sweeps of precision T from the FP64 vector x (read, cast, written back).
@@ -1294,11 +1641,14 @@ int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, doubl
     xs = g->x32;
   }
   if ((rc = ensure_contrib<T>(g))) return rc;
-  if (o.mode == PR_EDGE_LIST && (rc = ensure_cl<T>(g))) return rc;
+  if (is_list_form(o.mode) && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
-  if ((rc = launch_init<T>(g, P, p, x, xs, -1.0, std::max(1, sweeps)))) return rc;
+  const bool vo = o.mode == PR_INPLACE;
+  if ((rc = launch_init<T>(g, P, p, x, xs, -1.0, std::max(1, sweeps), nullptr, 0, vo))) return rc;
   const int flags = flags_of(o);
-  SweepArgs<T> a = make_args<T>(g, P, p, xs, d, flags, nullptr);
+  if ((rc = set_io(g, P, xs, p))) return rc;
+  SweepArgs<T> a = make_args<T>(g, P, p, d, flags, nullptr, nullptr, nullptr, o.mode);
+  prime_list<T>(g, a, o.mode);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (elapsed_ms) {
     PR_HIP(hipEventCreate(&e0));
@@ -1354,10 +1704,12 @@ int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps,
     xs = g->x32;
   }
   if ((rc = ensure_contrib<T>(g))) return rc;
-  if (o.mode == PR_EDGE_LIST && (rc = ensure_cl<T>(g))) return rc;
+  if (is_list_form(o.mode) && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
-  if ((rc = launch_init<T>(g, P, nullptr, x, xs, -1.0, sweeps))) return rc;
-  SweepArgs<T> a = make_args<T>(g, P, nullptr, xs, d, flags_of(o), nullptr);
+  if ((rc = launch_init<T>(g, P, nullptr, x, xs, -1.0, sweeps, nullptr, 0, o.mode == PR_INPLACE))) return rc;
+  if ((rc = set_io(g, P, xs, nullptr))) return rc;
+  SweepArgs<T> a = make_args<T>(g, P, nullptr, d, flags_of(o), nullptr, nullptr, nullptr, o.mode);
+  prime_list<T>(g, a, o.mode);
   std::vector<hipEvent_t> ev(3 * (size_t)sweeps, nullptr);
   for (auto &e : ev) PR_HIP(hipEventCreate(&e));
   for (int k = 0; k < sweeps; ++k) {
@@ -1414,7 +1766,8 @@ extern "C" int pr_certificate(pr_graph *g, double d, const double *p, const doub
   if ((rc = ensure_contrib<double>(g))) return rc;
   DevPlan &P = g->fwd;
   if ((rc = launch_init<double>(g, P, p, x, g->xtmp, -1.0, 1))) return rc;
-  SweepArgs<double> a = make_args<double>(g, P, p, g->xtmp, d, 0, nullptr);
+  if ((rc = set_io(g, P, g->xtmp, p))) return rc;
+  SweepArgs<double> a = make_args<double>(g, P, p, d, 0, nullptr);
   launch_sweeps(g, a, false, g->weighted, 1, g->work);
   PR_HIP(hipGetLastError());
   if ((rc = poll_state(g, P))) return rc;
@@ -1441,7 +1794,8 @@ extern "C" int pr_adjoint(pr_graph *g, double d, const double *x, const double *
   // lam^0 = g; gathered value = lam (no 1/W scaling), all vertices
   if ((rc = launch_init<double>(g, P, dLdx, dLdx, lam, tol, max_iter, g->ca64[0], 1))) return rc;
   const int flags = kFlagAdjoint | kFlagLinf;
-  SweepArgs<double> a = make_args<double>(g, P, dLdx, lam, d, flags, nullptr, g->ca64[0], g->ca64[1]);
+  if ((rc = set_io(g, P, lam, dLdx))) return rc;
+  SweepArgs<double> a = make_args<double>(g, P, dLdx, d, flags, nullptr, g->ca64[0], g->ca64[1]);
   const int G = 8;
   int done_sweeps = 0;
   for (;;) {

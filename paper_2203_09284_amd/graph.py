@@ -14,7 +14,8 @@ import torch
 
 from . import _lib as L
 
-MODES = {"jacobi": L.PR_JACOBI, "fused": L.PR_FUSED, "edge_list": L.PR_EDGE_LIST}
+MODES = {"jacobi": L.PR_JACOBI, "fused": L.PR_FUSED, "edge_list": L.PR_EDGE_LIST, "inplace": L.PR_INPLACE,
+         "fused_edge_list": L.PR_FUSED_EDGE_LIST}
 PRECISIONS = {"fp64": L.PR_FP64, "fp32": L.PR_FP32}
 DANGLING = {"uniform": L.PR_DANGLING_UNIFORM, "leak": L.PR_DANGLING_LEAK}
 NORMS = {"l1": L.PR_NORM_L1, "linf": L.PR_NORM_LINF}
@@ -53,10 +54,10 @@ class CanonicalCSR:
     edge_map: np.ndarray
 
 
-def build_csr(n: int, src, dst, weights=None, keep: bool = True):
+def build_csr(n: int, src, dst, weights=None, keep: bool = True, library=None):
     """Run pr_build_csr on host arrays.  Returns (PrCsr owned by the library,
     CanonicalCSR numpy copy or None)."""
-    lib = L.lib()
+    lib = library or L.lib()
     src = np.ascontiguousarray(src, np.int32)
     dst = np.ascontiguousarray(dst, np.int32)
     if src.shape != dst.shape:
@@ -67,7 +68,7 @@ def build_csr(n: int, src, dst, weights=None, keep: bool = True):
     csr = L.PrCsr()
     rc = lib.pr_build_csr(n, len(src), src.ctypes.data_as(L.vp), dst.ctypes.data_as(L.vp),
                           None if w is None else w.ctypes.data_as(L.vp), ctypes.byref(csr))
-    L.check(rc)
+    L.check(rc, library=lib)
     copy = None
     if keep:
         n_, m_ = csr.n, csr.m
@@ -92,9 +93,14 @@ class Graph:
     """A graph resident on the current GPU, with its execution plan."""
 
     def __init__(self, n: int, src, dst, weights=None, with_adjoint: bool = False,
-                 plan: dict | None = None, keep_csr: bool = False):
-        lib = L.lib()
-        csr, copy = build_csr(n, src, dst, weights, keep=True)
+                 plan: dict | None = None, keep_csr: bool = False, library: str = "",
+                 device_memory: str = "library"):
+        """library: "" for the product build, "naive" for the test variant whose
+        FP32 sums are uncompensated.  device_memory: "library" (pr_graph_create
+        allocates the graph's device arrays) or "torch" (pr_graph_bind places
+        them in one torch uint8 tensor this object holds)."""
+        lib = self._lib = L.lib(library)
+        csr, copy = build_csr(n, src, dst, weights, keep=True, library=lib)
         self.csr = copy if keep_csr else None
         self.edge_map = torch.from_numpy(copy.edge_map) if weights is not None else None
         po = L.PrPlanOpts()
@@ -103,9 +109,22 @@ class Graph:
             setattr(po, k, int(v))
         po.with_adjoint = 1 if with_adjoint else 0
         handle = ctypes.c_void_p()
+        self.graph_memory = None
         try:
-            rc = lib.pr_graph_create(ctypes.byref(csr), ctypes.byref(po), ctypes.byref(handle))
-            L.check(rc)
+            if device_memory == "torch":
+                nbytes = ctypes.c_size_t(0)
+                L.check(lib.pr_graph_device_bytes(ctypes.byref(csr), ctypes.byref(po), ctypes.byref(nbytes)),
+                        library=lib)
+                self.graph_memory = torch.empty(max(1, nbytes.value), dtype=torch.uint8,
+                                                device=torch.device("cuda", torch.cuda.current_device()))
+                rc = lib.pr_graph_bind(ctypes.byref(csr), ctypes.byref(po),
+                                       ctypes.c_void_p(self.graph_memory.data_ptr()), nbytes.value,
+                                       ctypes.byref(handle))
+            elif device_memory == "library":
+                rc = lib.pr_graph_create(ctypes.byref(csr), ctypes.byref(po), ctypes.byref(handle))
+            else:
+                raise ValueError("device_memory must be 'library' or 'torch'")
+            L.check(rc, library=lib)
         finally:
             lib.pr_csr_free(ctypes.byref(csr))
         self._h = handle
@@ -117,8 +136,9 @@ class Graph:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            L.lib().pr_graph_destroy(self._h)
+            self._lib.pr_graph_free(self._h)
             self._h = ctypes.c_void_p()
+        self.graph_memory = None
 
     def __del__(self):
         try:
@@ -128,14 +148,14 @@ class Graph:
 
     def stats(self) -> dict:
         s = L.PrGraphStats()
-        L.check(L.lib().pr_graph_stats_get(self._h, ctypes.byref(s)))
+        L.check(self._lib.pr_graph_stats_get(self._h, ctypes.byref(s)), library=self._lib)
         return {k: getattr(s, k) for k, _ in L.PrGraphStats._fields_}
 
     # ------------------------------------------------------------- solve --
     def _opts(self, mode, precision, dangling, norm, warm, fused_scaled, sweeps_per_poll,
               use_hip_graph, refine_tol, fp32_tol, trace_buf):
         o = L.PrOpts()
-        L.lib().pr_opts_default(ctypes.byref(o))
+        self._lib.pr_opts_default(ctypes.byref(o))
         o.mode = MODES[mode]
         o.precision = PRECISIONS[precision]
         o.dangling = DANGLING[dangling]
@@ -158,8 +178,11 @@ class Graph:
               warm_start: bool = False, dangling: str = "uniform", norm: str = "l1",
               fused_scaled: bool = True, sweeps_per_poll: int | None = None,
               use_hip_graph: bool = True, refine_tol: float | None = None,
-              fp32_tol: float | None = None, trace: bool = False, stream=None):
-        """pr_solve.  Returns (x, sweeps, residual, converged[, trace])."""
+              fp32_tol: float | None = None, trace: bool = False, stream=None,
+              workspace=None):
+        """pr_solve; pr_solve_ws with a workspace (a torch
+        uint8 CUDA tensor of at least workspace_bytes(...) bytes, or "torch" for
+        a fresh one).  Returns (x, sweeps, residual, converged[, trace])."""
         if x is None:
             x = torch.empty(self.n, dtype=torch.float64, device=self.device)
         tr = np.zeros(max_iter) if trace else None
@@ -167,15 +190,33 @@ class Graph:
                        use_hip_graph, refine_tol, fp32_tol, tr)
         it = ctypes.c_int(0)
         res = ctypes.c_double(0.0)
-        rc = L.lib().pr_solve(self._h, d, tol, max_iter, ctypes.byref(o),
-                              _dev_ptr(p, torch.float64, self.n, "p"),
-                              _dev_ptr(x, torch.float64, self.n, "x"), ctypes.byref(it),
-                              ctypes.byref(res), _stream_ptr(stream))
-        L.check(rc)
+        if workspace is not None:
+            if isinstance(workspace, str):
+                workspace = torch.empty(max(1, self.workspace_bytes(tol, o)), dtype=torch.uint8, device=self.device)
+            if not workspace.is_cuda or workspace.dtype != torch.uint8:
+                raise ValueError("workspace must be a uint8 CUDA tensor")
+            rc = self._lib.pr_solve_ws(self._h, d, tol, max_iter, ctypes.byref(o),
+                                       _dev_ptr(p, torch.float64, self.n, "p"), _dev_ptr(x, torch.float64, self.n, "x"),
+                                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.byref(it),
+                                       ctypes.byref(res), _stream_ptr(stream))
+        else:
+            rc = self._lib.pr_solve(self._h, d, tol, max_iter, ctypes.byref(o),
+                                    _dev_ptr(p, torch.float64, self.n, "p"), _dev_ptr(x, torch.float64, self.n, "x"),
+                                    ctypes.byref(it), ctypes.byref(res), _stream_ptr(stream))
+        L.check(rc, library=self._lib)
         out = (x, it.value, res.value, rc == L.PR_OK)
         if trace:
             return out + (tr[:it.value].copy(),)
         return out
+
+    def workspace_bytes(self, tol: float = 1e-8, opts=None, mode: str = "jacobi", precision: str = "fp64",
+                        refine_tol: float | None = None) -> int:
+        """pr_workspace_bytes: device bytes pr_solve_ws needs for these options."""
+        if opts is None:
+            opts = self._opts(mode, precision, "uniform", "l1", False, True, None, True, refine_tol, None, None)
+        nb = ctypes.c_size_t(0)
+        L.check(self._lib.pr_workspace_bytes(self._h, tol, ctypes.byref(opts), ctypes.byref(nb)), library=self._lib)
+        return nb.value
 
     def iterate(self, x: torch.Tensor, sweeps: int, d: float = 0.85, mode: str = "jacobi",
                 p: torch.Tensor | None = None, dangling: str = "uniform", norm: str = "l1",
@@ -187,11 +228,11 @@ class Graph:
                        None, None)
         res = ctypes.c_double(0.0)
         ms = ctypes.c_double(0.0)
-        rc = L.lib().pr_iterate(self._h, d, ctypes.byref(o), _dev_ptr(p, torch.float64, self.n, "p"),
+        rc = self._lib.pr_iterate(self._h, d, ctypes.byref(o), _dev_ptr(p, torch.float64, self.n, "p"),
                                 _dev_ptr(x, torch.float64, self.n, "x"), int(sweeps),
                                 ctypes.byref(res), ctypes.byref(ms) if timed else None,
                                 _stream_ptr(stream))
-        L.check(rc)
+        L.check(rc, library=self._lib)
         return (res.value, ms.value) if timed else res.value
 
     def profile_sweeps(self, sweeps: int, d: float = 0.85, mode: str = "jacobi", precision: str = "fp64",
@@ -203,44 +244,56 @@ class Graph:
         x = torch.full((self.n,), 1.0 / self.n, dtype=torch.float64, device=self.device)
         a = ctypes.c_double(0.0)
         b = ctypes.c_double(0.0)
-        rc = L.lib().pr_profile_sweeps(self._h, d, ctypes.byref(o), _dev_ptr(x, torch.float64, self.n, "x"),
+        rc = self._lib.pr_profile_sweeps(self._h, d, ctypes.byref(o), _dev_ptr(x, torch.float64, self.n, "x"),
                                        int(sweeps), ctypes.byref(a), ctypes.byref(b), _stream_ptr(stream))
-        L.check(rc)
+        L.check(rc, library=self._lib)
         return a.value, b.value
 
     def certificate(self, x: torch.Tensor, d: float = 0.85, p: torch.Tensor | None = None,
                     stream=None) -> float:
         """||F(x) - x||_1, computed on the GPU; ||x - x*||_1 <= this / (1 - d)."""
         out = ctypes.c_double(0.0)
-        rc = L.lib().pr_certificate(self._h, d, _dev_ptr(p, torch.float64, self.n, "p"),
+        rc = self._lib.pr_certificate(self._h, d, _dev_ptr(p, torch.float64, self.n, "p"),
                                     _dev_ptr(x, torch.float64, self.n, "x"), ctypes.byref(out),
                                     _stream_ptr(stream))
-        L.check(rc)
+        L.check(rc, library=self._lib)
         return out.value
 
     # ---------------------------------------------------------- batched --
     def solve_batched(self, seeds: torch.Tensor, d: float = 0.85, tol: float = 1e-6,
-                      max_iter: int = 1000, tile: int = 0, X: torch.Tensor | None = None,
-                      stream=None):
-        """pr_solve_batched.  Returns (X [n, k] float32, iters[k], residuals[k])."""
+                      max_iter: int = 1000, tile: int = 0, shape: dict | None = None,
+                      X: torch.Tensor | None = None, stream=None):
+        """pr_solve_batched.  shape: {"tile", "items_per_grab", "wg_per_cu"}; or
+        tile > 0 alone (default grab and workgroups); neither: autotuned.
+        Returns (X [n, k] float32, iters[k], residuals[k])."""
         k = int(seeds.numel())
         if X is None:
             X = torch.empty((self.n, k), dtype=torch.float32, device=self.device)
+        sh = None
+        if shape is not None or tile:
+            sh = L.PrBatchShape()
+            self._lib.pr_batch_shape_default(ctypes.byref(sh))
+            if tile:
+                sh.tile = int(tile)
+            for key, v in (shape or {}).items():
+                setattr(sh, key, int(v))
         its = (ctypes.c_int * k)()
         res = (ctypes.c_double * k)()
-        rc = L.lib().pr_solve_batched(self._h, d, tol, max_iter, k,
-                                      _dev_ptr(seeds, torch.int32, k, "seeds"), int(tile),
-                                      _dev_ptr(X, torch.float32, self.n * k, "X"), its, res,
-                                      _stream_ptr(stream))
-        L.check(rc)
+        rc = self._lib.pr_solve_batched(self._h, d, tol, max_iter, k,
+                                        _dev_ptr(seeds, torch.int32, k, "seeds"),
+                                        ctypes.byref(sh) if sh is not None else None,
+                                        _dev_ptr(X, torch.float32, self.n * k, "X"), its, res,
+                                        _stream_ptr(stream))
+        L.check(rc, library=self._lib)
         return X, np.array(its[:], np.int64), np.array(res[:], np.float64)
 
-    def autotune_batched(self, k: int, cache_path: str | None = None, stream=None) -> int:
-        tile = ctypes.c_int(0)
-        rc = L.lib().pr_autotune_batched(self._h, int(k), None if cache_path is None else cache_path.encode(),
-                                         ctypes.byref(tile), _stream_ptr(stream))
-        L.check(rc)
-        return tile.value
+    def autotune_batched(self, k: int, cache_path: str | None = None, stream=None) -> dict:
+        """pr_autotune_batched: the fastest launch shape for k columns, as a dict."""
+        sh = L.PrBatchShape()
+        rc = self._lib.pr_autotune_batched(self._h, int(k), None if cache_path is None else cache_path.encode(),
+                                           ctypes.byref(sh), _stream_ptr(stream))
+        L.check(rc, library=self._lib)
+        return {"tile": sh.tile, "items_per_grab": sh.items_per_grab, "wg_per_cu": sh.wg_per_cu}
 
     # ---------------------------------------------------------- adjoint --
     def adjoint(self, x: torch.Tensor, dLdx: torch.Tensor, d: float = 0.85, tol: float = 1e-14,
@@ -251,11 +304,11 @@ class Graph:
         gw = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device) if want_w else None
         it = ctypes.c_int(0)
         res = ctypes.c_double(0.0)
-        rc = L.lib().pr_adjoint(self._h, d, _dev_ptr(x, torch.float64, self.n, "x"),
+        rc = self._lib.pr_adjoint(self._h, d, _dev_ptr(x, torch.float64, self.n, "x"),
                                 _dev_ptr(dLdx, torch.float64, self.n, "dLdx"), tol, max_iter,
                                 _dev_ptr(lam, torch.float64, None, "lam"),
                                 _dev_ptr(gp, torch.float64, None, "dLdp"),
                                 _dev_ptr(gw, torch.float64, None, "dLdw"), ctypes.byref(it),
                                 ctypes.byref(res), _stream_ptr(stream))
-        L.check(rc)
+        L.check(rc, library=self._lib)
         return lam, gp, (gw[:self.m] if gw is not None else None), it.value, res.value

@@ -95,13 +95,18 @@ def test_batched_tile_widths_agree_with_hubs_and_long_rows():
     st = g.stats()
     assert st["n_heavy"] > 0 and st["n_medium"] > 0, st
     outs = []
-    for tile in (4, 8, 16, 64):
-        say("batched hubs tile=%d" % tile)
-        X, its, res = g.solve_batched(sd, d=D, tol=1e-6, tile=tile)
+    shapes = [dict(tile=t) for t in (4, 8, 16, 64)]
+    shapes += [dict(tile=64, items_per_grab=4, wg_per_cu=1), dict(tile=16, items_per_grab=2, wg_per_cu=2),
+               dict(tile=32, items_per_grab=16, wg_per_cu=1), dict(tile=8, items_per_grab=3, wg_per_cu=1)]
+    for sh in shapes:
+        say("batched hubs %s" % sh)
+        X, its, res = g.solve_batched(sd, d=D, tol=1e-6, shape=sh)
         outs.append((X.cpu().numpy(), its, res))
     g.close()
+    # every launch shape: the same bits, sweep counts and residuals
     for X, its, res in outs[1:]:
         assert np.array_equal(X, outs[0][0]) and np.array_equal(its, outs[0][1])
+        assert np.array_equal(res, outs[0][2])
     og = oracle.csr(n, s, t)
     for j in (0, 23):
         assert l1(outs[-1][0][:, j].astype(np.float64), _ppr_ref(og, n, seeds[j])) <= 1e-5, j
@@ -161,14 +166,22 @@ def test_batched_autotune_cache(tmp_path):
     g = fpr.Graph(n, s, t)
     path = str(tmp_path / "tune.jsonl")
     say("autotune")
-    tile = g.autotune_batched(32, path)
-    assert tile in (4, 8, 16, 32)
+    shape = g.autotune_batched(32, path)
+    assert shape["tile"] in (8, 16, 32) and shape["items_per_grab"] in (1, 2, 4) and shape["wg_per_cu"] in (1, 2)
     text = open(path).read()
-    assert '"tile": %d' % tile in text
+    assert '"tile": %d, "items_per_grab": %d, "wg_per_cu": %d' % (shape["tile"], shape["items_per_grab"],
+                                                                   shape["wg_per_cu"]) in text
+    assert "sig=%016x" % g.stats()["signature"] in text
     g.close()
     g2 = fpr.Graph(n, s, t)
-    assert g2.autotune_batched(32, path) == tile  # read back from the cache file
+    assert g2.autotune_batched(32, path) == shape  # read back from the cache file
     g2.close()
+    # a graph of the same size but other edges is tuned afresh (its own key)
+    s3, t3 = gg.rmat(11, 8, seed=16)
+    g3 = fpr.Graph(n, s3, t3)
+    g3.autotune_batched(32, path)
+    assert len(open(path).read().strip().splitlines()) == 2
+    g3.close()
 
 
 def test_batched_rejects_weighted_graphs():
@@ -194,6 +207,31 @@ def test_batched_rejects_bad_seeds():
         g.solve_batched(torch.tensor([1, -1], dtype=torch.int32, device="cuda"), tile=4)
     with pytest.raises(FusedPRError):
         g.solve_batched(torch.tensor([1, 2], dtype=torch.int32, device="cuda"), tile=6)
+    for bad in (dict(items_per_grab=0), dict(items_per_grab=17), dict(wg_per_cu=3), dict(tile=68)):
+        with pytest.raises(FusedPRError):
+            g.solve_batched(torch.tensor([1, 2], dtype=torch.int32, device="cuda"), shape=bad)
+    g.close()
+
+
+def test_batched_sweeps_reuse_their_captured_graphs():
+    """The batched sweeps run as cached hipGraphs: new output matrices and
+    new seeds do not capture again."""
+    fpr = _fpr()
+    n = 1 << 12
+    s, t = gg.rmat(12, 16, seed=17)
+    og = oracle.csr(n, s, t)
+    g = fpr.Graph(n, s, t)
+    sh = dict(tile=16)
+    g.solve_batched(torch.tensor(gg.sample_distinct(n, 16, 17, 4), dtype=torch.int32, device="cuda"), d=D,
+                    tol=1e-6, shape=sh)
+    base = g.stats()["graph_captures"]
+    for rep_ in range(6):
+        seeds = gg.sample_distinct(n, 16, 30 + rep_, 4)
+        X, its, res = g.solve_batched(torch.tensor(seeds, dtype=torch.int32, device="cuda"), d=D, tol=1e-6, shape=sh)
+        Xh = X.cpu().numpy().astype(np.float64)
+        for j in (0, 15):
+            assert l1(Xh[:, j], _ppr_ref(og, n, seeds[j])) <= 1e-5, (rep_, j)
+    assert g.stats()["graph_captures"] == base
     g.close()
 
 

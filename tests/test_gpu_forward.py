@@ -284,6 +284,37 @@ def test_edge_list_form_equals_jacobi_bits(case, plan):
     g.close()
 
 
+@pytest.mark.parametrize("plan", range(len(PLANS)))
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_fused_edge_list_form_equals_fused_bits(case, plan):
+    """Algorithm 2 with the edge-ordered contributionList (per Gauss-Seidel
+    block: contiguous row sums and the update, then the block's fused scatter
+    through offsetList) reads this sweep's contributions of the earlier blocks
+    and the previous sweep's of the others, as the block Gauss-Seidel pull
+    does, and adds them in the same order: bit-identical iterates, in both
+    precisions, mass-scaled and plain, through pr_solve and pr_iterate."""
+    name, n, src, dst, w, p = CASES[case]
+    say("case %s plan %d fused edge list" % (name, plan))
+    fpr = _fpr()
+    _, xr = _ref(n, src, dst, w, p)
+    g = fpr.Graph(n, src, dst, w, plan=dict(PLANS[plan] or {}, with_cl=1))
+    for prec in ("fp64", "fp32"):
+        for scaled in (True, False):
+            kw = dict(d=D, tol=1e-12, max_iter=3000, precision=prec, p=_p_dev(p), fused_scaled=scaled)
+            xa, ia, ra, oka = g.solve(mode="fused", **kw)
+            xb, ib, rb, okb = g.solve(mode="fused_edge_list", **kw)
+            assert oka and okb and ia == ib and ra == rb, (prec, scaled, ia, ib, ra, rb)
+            assert torch.equal(xa, xb), (prec, scaled)
+            assert l1(xb.cpu().numpy(), xr) <= 1e-9
+    for prec in ("fp64", "fp32"):
+        x0 = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+        x1 = x0.clone()
+        g.iterate(x0, 5, d=D, mode="fused", precision=prec, p=_p_dev(p))
+        g.iterate(x1, 5, d=D, mode="fused_edge_list", precision=prec, p=_p_dev(p))
+        assert torch.equal(x0, x1), prec
+    g.close()
+
+
 def test_edge_list_form_needs_its_plan():
     fpr = _fpr()
     from paper_2203_09284_amd._lib import FusedPRError
@@ -291,6 +322,8 @@ def test_edge_list_form_needs_its_plan():
     g = fpr.Graph(10, s, t)
     with pytest.raises(FusedPRError):
         g.solve(mode="edge_list")
+    with pytest.raises(FusedPRError):
+        g.solve(mode="fused_edge_list")
     g.close()
 
 

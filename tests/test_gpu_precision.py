@@ -1,0 +1,91 @@
+"""The FP32 storage path (ranks and contributions in FP32, compensated sums,
+FP64 reductions) against the FP64 oracle: what the compensation buys, and the
+FP32 bar (L1 <= 1e-5) without any FP64 refinement at the R-MAT-20 size.
+
+The compensated build is compared with a build of the same sources whose FP32
+sums are plain (FPR_NAIVE_SUM=1, libfusedpr_naive.so)."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+
+
+def _fpr():
+    import paper_2203_09284_amd as fpr
+    return fpr
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def l1(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).sum())
+
+
+def tiny_terms_graph(T=16000, eps=1.27e-3):
+    """Vertex 1 has one large in-contribution (from vertex 0, about 0.46) and T
+    tiny ones (from vertices 2..T+1, each about 0.4 of an FP32 ulp of 0.46:
+    every tiny source also points to vertex 0 with weight 1, and to vertex 1
+    with weight eps).  Vertex 1 points back to vertex 0.  A lane that adds the
+    large term first and then its share of the tiny ones loses every tiny one
+    to rounding unless the sum is compensated."""
+    tiny = np.arange(2, T + 2, dtype=np.int32)
+    src = np.concatenate([[0, 1], tiny, tiny]).astype(np.int32)
+    dst = np.concatenate([[1, 0], np.ones(T, np.int32), np.zeros(T, np.int32)]).astype(np.int32)
+    w = np.concatenate([[1.0, 1.0], np.full(T, eps), np.ones(T)])
+    return T + 2, src, dst, w
+
+
+def test_compensated_fp32_sum_beats_plain_sum():
+    fpr = _fpr()
+    n, src, dst, w = tiny_terms_graph()
+    og = oracle.csr(n, src, dst, w)
+    xs, _, _ = oracle.jacobi(og, D, tol=1e-15, max_iter=5000)
+    # the row of vertex 1 (16,001 in-edges) on one wavefront: lane 0 adds the
+    # large term, then every 64th tiny one
+    plan = dict(chunk=16384)
+    errs = {}
+    for lib in ("", "naive"):
+        g = fpr.Graph(n, src, dst, w, plan=plan, library=lib)
+        # one FP32 sweep from the fixed point: F(x*) = x*, so what moves is
+        # FP32 arithmetic (input and output rounding, and the sums)
+        x = torch.tensor(xs, device="cuda")
+        g.iterate(x, 1, d=D, mode="jacobi", precision="fp32")
+        xh = x.cpu().numpy()
+        x2, it, res, ok = g.solve(d=D, tol=1e-7, max_iter=2000, mode="jacobi", precision="fp32", refine_tol=0)
+        errs[lib] = (abs(xh[1] - xs[1]), l1(xh, xs), l1(x2.cpu().numpy(), xs))
+        say("%-6s one sweep: |err| at the row %.3e, L1 %.3e; FP32 solve L1 %.3e (%d sweeps)" %
+            (lib or "comp", errs[lib][0], errs[lib][1], errs[lib][2], it))
+        g.close()
+    ulp = float(np.spacing(np.float32(xs[1])))
+    comp, naive = errs[""], errs["naive"]
+    # compensated: within a few FP32 ulps of the row value; plain: the lost
+    # tiny terms (about 250 * 1.19e-8 * d) show
+    assert comp[0] <= 4 * ulp
+    assert naive[0] >= 1e-6 and naive[0] >= 20 * comp[0]
+    assert comp[1] <= naive[1] and comp[2] <= naive[2]
+    assert comp[2] <= 1e-5
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", ["jacobi", "fused"])
+def test_fp32_without_refinement_at_rmat20(mode):
+    """R-MAT scale 20 (the benchmark's graph, default plan): the FP32 stage
+    alone, no FP64 refinement sweeps, meets the FP32 bar against the oracle."""
+    fpr = _fpr()
+    w = gg.rmat20()
+    n = w["n"]
+    og = oracle.csr(n, w["src"], w["dst"])
+    xr, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=1000, threads=16)
+    g = fpr.Graph(n, w["src"], w["dst"])
+    x, it, res, ok = g.solve(d=D, tol=1e-7, max_iter=1000, mode=mode, precision="fp32", refine_tol=0)
+    err = l1(x.cpu().numpy(), xr)
+    say("rmat20 %s FP32 only: %d sweeps, residual %.2e, L1 vs oracle %.3e" % (mode, it, res, err))
+    assert err <= 1e-5
+    g.close()

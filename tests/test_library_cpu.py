@@ -148,10 +148,12 @@ def test_product_and_oracle_share_no_code():
 
 def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     from paper_2203_09284_amd import _lib as L
-    monkeypatch.setattr(L, "_LIB", None)
-    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(L, "_LIBS", {})
+    monkeypatch.setattr(L, "VARIANTS", {"": str(tmp_path / "missing.so"), "naive": str(tmp_path / "gone.so")})
     with pytest.raises(ImportError, match="not built"):
         L.lib()
+    with pytest.raises(ImportError, match="not built"):
+        L.lib("naive")
 
 
 def test_every_compute_entry_point_cites_the_paper():
@@ -162,3 +164,48 @@ def test_every_compute_entry_point_cites_the_paper():
     for name in ("pr_build_csr", "pr_graph_create", "pr_solve", "pr_iterate", "pr_profile_sweeps",
                  "pr_certificate", "pr_solve_batched", "pr_autotune_batched", "pr_adjoint"):
         assert cited.get(name), name
+
+
+def _csr_view(c):
+    """A pr_csr whose arrays are the given numpy arrays (kept alive by the caller)."""
+    from paper_2203_09284_amd import _lib as L
+    p = lambda a, t: a.ctypes.data_as(t) if a is not None else None
+    return L.PrCsr(n=c["n"], m=c["m"], in_ptr=p(c["in_ptr"], L.c_i64p), in_src=p(c["in_src"], L.c_i32p),
+                   in_w=None, out_ptr=p(c["out_ptr"], L.c_i64p), out_dst=p(c["out_dst"], L.c_i32p), out_w=None,
+                   out_to_in=p(c["out_to_in"], L.c_i64p), out_deg=p(c["out_deg"], L.c_i32p),
+                   in_deg=p(c["in_deg"], L.c_i32p), m_input=0, edge_map=None)
+
+
+def test_graph_create_refuses_a_malformed_csr():
+    # the structural checks run before any device work, so they hold without a GPU
+    from paper_2203_09284_amd.graph import build_csr
+    L, lib = _lib()
+    src, dst = gg.random_graph(50, 300, 7)
+    csr, c = build_csr(50, src, dst)
+    lib.pr_csr_free(ctypes.byref(csr))
+    good = dict(n=c.n, m=c.m, in_ptr=c.in_ptr.copy(), in_src=c.in_src.copy(), out_ptr=c.out_ptr.copy(),
+                out_dst=c.out_dst.copy(), out_to_in=c.out_to_in.copy(), out_deg=c.out_deg.copy(),
+                in_deg=c.in_deg.copy())
+    bad_cases = []
+    b = dict(good, in_ptr=good["in_ptr"].copy())
+    b["in_ptr"][5], b["in_ptr"][6] = b["in_ptr"][6] + 1, b["in_ptr"][5]
+    bad_cases.append((b, "decreasing offsets"))
+    b = dict(good, in_src=good["in_src"].copy())
+    b["in_src"][3] = 50
+    bad_cases.append((b, "outside"))
+    b = dict(good, out_deg=good["out_deg"].copy())
+    b["out_deg"][0] += 1
+    bad_cases.append((b, "out_deg"))
+    b = dict(good, out_ptr=good["out_ptr"].copy())
+    b["out_ptr"][-1] -= 1
+    bad_cases.append((b, "span"))
+    b = dict(good, out_dst=None)
+    bad_cases.append((b, "not a pr_build_csr result"))
+    for arrays, msg in bad_cases:
+        view = _csr_view(arrays)
+        po = L.PrPlanOpts()
+        lib.pr_plan_opts_default(ctypes.byref(po))
+        h = ctypes.c_void_p()
+        rc = lib.pr_graph_create(ctypes.byref(view), ctypes.byref(po), ctypes.byref(h))
+        assert rc == L.PR_EINVAL and not h.value, msg
+        assert msg.encode() in lib.pr_last_error(), (msg, lib.pr_last_error())
