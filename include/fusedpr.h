@@ -276,6 +276,26 @@ int pr_workspace_bytes(const pr_graph *g, double tol, const pr_opts *o, size_t *
 int pr_solve_ws(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, const double *p, double *x,
                 void *ws, size_t ws_bytes, int *iters, double *resid, void *stream);
 
+/* pr_solve for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, checks, results and return values as pr_solve on a graph
+ * that already exists; the caller passes x (and p) as before.  Where pr_solve
+ * allocates the contribution arrays (and the FP32 copy of the ranks) on first
+ * use, this entry point takes them from a fixed array in the library's device
+ * image: pr_noalloc_scratch_bytes() bytes (32 MiB) on each device, held until
+ * the process ends.  A solve needs 16 n bytes in FP64 and 12 n in FP32, plus
+ * 16 n for the FP64 refinement (each rounded up to 256 bytes), so up to about
+ * 2 million vertices in FP64; a larger graph gives PR_EINVAL.  It queues its
+ * sweeps as plain launches (no hipGraph is instantiated), and refuses
+ * PR_EDGE_LIST and a residual trace, which need buffers of their own
+ * (PR_EINVAL).  Every call on one device works in the same array: calls that
+ * overlap on one device (any graphs, any threads or streams) race and give
+ * wrong ranks.  Nothing in the array needs to start at zero: each call writes
+ * every value before reading it. */
+int pr_solve_noalloc(pr_graph *g, double d, double tol, int max_iter, const pr_opts *o, const double *p,
+                     double *x, int *iters, double *resid, void *stream);
+size_t pr_noalloc_scratch_bytes(void);
+
 /* Exactly `sweeps` sweeps from the x passed in (no convergence test), in the
  * form o->mode and the precision o->precision select: the body of
  * Algorithm 1's loop (Eq. 2, Jacobi) or of Algorithm 2's (Eq. 9, fused),

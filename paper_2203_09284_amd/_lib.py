@@ -76,6 +76,9 @@ SIGNATURES = {
     "pr_opts_default": (None, [ctypes.POINTER(PrOpts)]),
     "pr_solve": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(PrOpts),
                                 vp, vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
+    "pr_solve_noalloc": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.POINTER(PrOpts), vp, vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),
+    "pr_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "pr_iterate": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts), vp, vp, ctypes.c_int, c_f64p,
                                   c_f64p, vp]),
     "pr_certificate": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, c_f64p, vp]),

@@ -1626,6 +1626,66 @@ extern "C" int pr_solve_ws(pr_graph *g, double d, double tol, int max_iter, cons
   return solve_impl(g, d, tol, max_iter, o, p, x, iters, resid, stream, b);
 }
 
+// ----------------------------------------------------- no-allocation solve --
+//
+// pr_solve_noalloc works in a fixed device array instead of buffers it would
+// otherwise allocate on first use: one array per device, in the library's
+// image, whose address each device gets once (hipGetSymbolAddress, with that
+// device current) and keeps.  Host code uses only that address: the array's
+// name is a host-side stand-in.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kScratchDevices] = {};
+
+// The address of `scratch` on device `dev` (the current device), looked up on
+// the first call for that device.
+int scratch_on(int dev, unsigned char **out) {
+  if (dev < 0 || dev >= kScratchDevices)
+    return pr_fail(PR_EINVAL, "pr_solve_noalloc: device %d outside the %d the scratch table holds", dev,
+                   kScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return pr_fail(PR_EDEVICE, "pr_solve_noalloc: hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                     hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" size_t pr_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" int pr_solve_noalloc(pr_graph *g, double d, double tol, int max_iter, const pr_opts *opts,
+                                const double *p, double *x, int *iters, double *resid, void *stream) {
+  pr_clear_error();
+  pr_opts o;
+  pr_opts_default(&o);
+  if (opts) o = *opts;
+  int rc = validate_solve(g, d, tol, max_iter, o, x, iters, resid);
+  if (rc) return rc;
+  if ((rc = ws_refuse("pr_solve_noalloc", o))) return rc;
+  o.use_hip_graph = 0;  // instantiating a hipGraph may allocate
+  const size_t need = ws_layout(g, o, tol, nullptr, nullptr);
+  if (need > kScratchBytes)
+    return pr_fail(PR_EINVAL, "pr_solve_noalloc: n = %lld needs %zu bytes of scratch, more than the %zu it holds",
+                   (long long)g->n, need, kScratchBytes);
+  unsigned char *base = nullptr;
+  if ((rc = scratch_on(g->device, &base))) return rc;
+  SolveBufs b;
+  ws_layout(g, o, tol, base, &b);
+  return solve_impl(g, d, tol, max_iter, o, p, x, iters, resid, stream, b);
+}
+
 namespace {
 
 // `sweeps` sweeps of precision T from the FP64 vector x (read, cast, written back).

@@ -178,9 +178,10 @@ class Graph:
               warm_start: bool = False, dangling: str = "uniform", norm: str = "l1",
               fused_scaled: bool = True, sweeps_per_poll: int | None = None,
               use_hip_graph: bool = True, refine_tol: float | None = None,
-              fp32_tol: float | None = None, trace: bool = False, stream=None,
+              fp32_tol: float | None = None, trace: bool = False, stream=None, no_alloc: bool = False,
               workspace=None):
-        """pr_solve; pr_solve_ws with a workspace (a torch
+        """pr_solve; pr_solve_noalloc with no_alloc (the library allocates no
+        device memory in the call); pr_solve_ws with a workspace (a torch
         uint8 CUDA tensor of at least workspace_bytes(...) bytes, or "torch" for
         a fresh one).  Returns (x, sweeps, residual, converged[, trace])."""
         if x is None:
@@ -200,9 +201,10 @@ class Graph:
                                        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.byref(it),
                                        ctypes.byref(res), _stream_ptr(stream))
         else:
-            rc = self._lib.pr_solve(self._h, d, tol, max_iter, ctypes.byref(o),
-                                    _dev_ptr(p, torch.float64, self.n, "p"), _dev_ptr(x, torch.float64, self.n, "x"),
-                                    ctypes.byref(it), ctypes.byref(res), _stream_ptr(stream))
+            entry = self._lib.pr_solve_noalloc if no_alloc else self._lib.pr_solve
+            rc = entry(self._h, d, tol, max_iter, ctypes.byref(o), _dev_ptr(p, torch.float64, self.n, "p"),
+                       _dev_ptr(x, torch.float64, self.n, "x"), ctypes.byref(it), ctypes.byref(res),
+                       _stream_ptr(stream))
         L.check(rc, library=self._lib)
         out = (x, it.value, res.value, rc == L.PR_OK)
         if trace:
