@@ -488,7 +488,8 @@ def profile_driver(args):
         g.close()
         return
     mode, prec = args.profile.split("-")[:2]
-    g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1 if mode == "edge_list" else 0))
+    g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1 if "edge_list" in mode else 0,
+                                                        with_inplace=1 if mode == "inplace" else 0))
     x = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
     g.iterate(x, args.profile_sweeps, d=D, mode=mode, precision=prec, use_hip_graph=False)
     torch.cuda.synchronize()
