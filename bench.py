@@ -473,7 +473,8 @@ def profile_driver(args):
         import graphgen as gg
         g = fpr.Graph(w["n"], w["src"], w["dst"])
         seeds = torch.tensor(gg.ppr_seeds(g.n), dtype=torch.int32, device="cuda")
-        X, its, _ = g.solve_batched(seeds, d=D, tol=1e-6, tile=64)
+        shape = g.autotune_batched(64)  # the launch shape the benchmark's solve uses
+        X, its, _ = g.solve_batched(seeds, d=D, tol=1e-6, shape=shape)
         torch.cuda.synchronize()
         a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -482,7 +483,8 @@ def profile_driver(args):
         torch.cuda.synchronize()
         # sweeps that did work (launches after every column froze exit at once)
         print(json.dumps({"profile": "batched", "workload": args.workload, "n": g.n, "m": g.m,
-                          "sweeps": int(its.max()), "copy_bytes": COPY_BYTES, "columns": 64,
+                          "sweeps": int(its.max()) * (64 // shape["tile"]), "shape": shape,
+                          "copy_bytes": COPY_BYTES, "columns": 64,
                           "b_alg": b_alg(g.n, g.m, 4 * 64),
                           "source_sha": kernel_source_sha(BATCHED_SOURCES)}), flush=True)
         g.close()
@@ -572,7 +574,8 @@ def pmc_summary(args):
     import csv
     key, fetch_csv, write_csv, driver_log = args.pmc_summary
     drv = json.loads([ln for ln in open(driver_log) if ln.startswith('{"profile"')][-1])
-    kname = "k_vsweep(" if drv["profile"] == "batched" else "k_sweep<"
+    kname = ("k_vsweep(" if drv["profile"] == "batched" else
+             "k_inplace<" if drv["profile"].startswith("inplace") else "k_sweep<")
 
     def read(path, counter):
         sweep, copy = [], []
@@ -614,6 +617,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline workload and R-MAT-20 forms only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None, metavar="LEGS",
+                    help="comma-separated legs to run alone (rmat20,er10k,adjoint,road8m), without the "
+                         "headline: a quick measurement, not the benchmark line")
     ap.add_argument("--profile", default=None, help="{jacobi,fused,edge_list}-{fp64,fp32} | batched")
     ap.add_argument("--profile-sweeps", type=int, default=20)
     ap.add_argument("--workload", default="rmat24")
@@ -646,6 +652,14 @@ def main():
         raise SystemExit("bench.py needs a GPU: the HIP library has no CPU path")
     torch.cuda.set_device(0)
     cores = min(os.cpu_count() or 1, 16)
+
+    if args.only:
+        table = {"rmat20": lambda: leg_rmat20(torch, fpr, oracle, args.steps, args.warmup, cores, args),
+                 "er10k": lambda: leg_er10k(torch, fpr, oracle, args.steps, args.warmup),
+                 "adjoint": lambda: leg_adjoint(torch, fpr, oracle, args.steps, args.warmup, cores),
+                 "road8m": lambda: leg_road(torch, fpr, oracle, max(3, args.steps // 4), 1, cores)}
+        print(json.dumps({name: table[name]() for name in args.only.split(",")}), flush=True)
+        return
 
     h = headline_rmat24(torch, fpr, oracle, args.steps, args.warmup, cores, not args.no_cpu_baseline)
     n, m, forms, kern = h["n"], h["m"], h["forms"], h["kern"]

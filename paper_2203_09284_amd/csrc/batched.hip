@@ -20,7 +20,8 @@
 //
 // Arithmetic.  Ranks and contributions are FP32; sums use Neumaier
 // compensation per lane and TwoSum when quarters combine (in quarter order).
-// Per-column residuals and dangling mass are FP64, reduced in a fixed order.
+// Per-column residuals and dangling mass are summed in 64-bit fixed point
+// (2^-60 units), exact and order-free, then read as FP64.
 // A column whose L1 residual drops below tol is frozen: its values stop
 // changing and its sweep count is recorded.  A launch's sweeps stop once all
 // its columns are frozen.
@@ -43,7 +44,6 @@ namespace {
 
 constexpr int kVBlock = 512;          // threads per workgroup of the sweep
 constexpr int kVWaves = kVBlock / 64;
-constexpr int kVGroup = 16;           // lanes per group: one 256-byte row of 64 columns
 constexpr int kVMaxT = 64;            // columns per launch at most
 constexpr int kVFin = 256;            // threads per workgroup of the finalize kernel (one per column)
 
@@ -73,7 +73,8 @@ struct VArgs {
   float4 *c0;            // [n][Q] gather-layout order
   float4 *c1;
   double *hpart;         // [n_chunks][T]
-  double *item_part;     // [n_items][2][T]: change and dangling mass per item and column
+  unsigned long long *wg_part;  // [2][T][n_wg]: change and dangling mass per column and workgroup
+                                // (fixed point, kFix units)
   VState *st;
   double d;
   double inv_n;
@@ -112,27 +113,50 @@ struct Sum4 {
   }
 };
 
+// Per-column change and dangling mass.  Within a work item they are summed
+// in FP64 in a fixed order (each group over its rows, then the four groups in
+// order), so an item's sums do not depend on which wavefront ran it; each
+// item's sum is then rounded once to 64-bit fixed point (kFix = 2^60 units per
+// 1.0) and the items are added as integers, whose sums do not depend on their
+// order.  So the totals, and the dangling mass every column's next sweep adds,
+// are the same bits whatever the launch shape.  Both totals stay below 4
+// (sums of |x' - x| and of x over a column whose values sum to 1), far inside
+// the 64-bit range.
+constexpr double kFix = 1152921504606846976.0;  // 2^60
+__device__ __forceinline__ unsigned long long to_fix(double v) {
+  return (unsigned long long)__double2ll_rn(v * kFix);
+}
+
 struct VRed {
   double chg[4] = {0.0, 0.0, 0.0, 0.0};
   double dang[4] = {0.0, 0.0, 0.0, 0.0};
 };
 
-// Lane view of a launch: the lane's group, its columns and their state.
+
+// Lane view of a launch.  A row of Q float4 (T = 4Q columns) is read by a
+// group of LPR >= Q lanes (lane j holds columns 4j..4j+3); four groups form a
+// quad-slot, which runs one work item at a time (its four runs, or the four
+// quarters of a long row); a wavefront holds 16 / LPR quad-slots.
 struct VCtx {
   const float4 *cin;
   float4 *cout;
-  int g, j;
+  int g, j;   // group within the quad-slot, lane within the group
+  int base;   // first lane of the quad-slot
+  int qs;     // quad-slot within the wavefront
   bool act;
   bool frozen[4];
   int seed[4];
   double dterm[4];
 };
 
+template <int LPR>
 __device__ __forceinline__ VCtx make_vctx(const VArgs &a) {
   VCtx C;
   const int lane = threadIdx.x & 63;
-  C.g = lane / kVGroup;
-  C.j = lane % kVGroup;
+  C.j = lane % LPR;
+  C.g = (lane / LPR) & 3;
+  C.qs = lane / (4 * LPR);
+  C.base = C.qs * 4 * LPR;
   C.act = C.j < a.Q;
   C.cin = a.par ? a.c1 : a.c0;
   C.cout = a.par ? a.c0 : a.c1;
@@ -146,44 +170,74 @@ __device__ __forceinline__ VCtx make_vctx(const VArgs &a) {
   return C;
 }
 
-// Lane b of the caller's 16-lane row (DPP row_newbcast:b).
-template <int B>
-__device__ __forceinline__ int row_bcast(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x150 + B, 0xf, 0xf, true);
+// Lane `src` of the caller's group of LPR lanes (DPP: row broadcasts for
+// groups of 16 and 8 lanes, quad permutes for 4 and 2; a group of one lane is
+// the lane itself).
+template <int LPR, int SRC>
+__device__ __forceinline__ int group_bcast(int v) {
+  if constexpr (LPR == 16) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x150 + SRC, 0xf, 0xf, true);
+  } else if constexpr (LPR == 8) {
+    const int lo = __builtin_amdgcn_update_dpp(0, v, 0x150 + SRC, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, v, 0x150 + 8 + SRC, 0xf, 0xf, true);
+    return (threadIdx.x & 8) ? hi : lo;
+  } else if constexpr (LPR == 4) {
+    return __builtin_amdgcn_update_dpp(0, v, SRC | (SRC << 2) | (SRC << 4) | (SRC << 6), 0xf, 0xf, true);
+  } else if constexpr (LPR == 2) {
+    return __builtin_amdgcn_update_dpp(0, v, SRC | (SRC << 2) | ((2 + SRC) << 4) | ((2 + SRC) << 6), 0xf, 0xf,
+                                       true);
+  } else {
+    return v;
+  }
 }
 
-// Adds the rows of cnt <= 16 in-edges, in list order, whose gather slots lane
-// b of the group holds in `sl` (one load of 16 slots per group instead of one
-// per edge); 8 row reads in flight per lane.
-__device__ __forceinline__ void chunk16(const VArgs &a, const VCtx &C, int sl, int cnt, Sum4 &acc) {
-  float4 v[kBatch];
+// A group's 16 gather slots: lane j holds slots j, j + LPR, ... (16 / LPR of
+// them); slot b is at lane b % LPR, register b / LPR.
+template <int LPR>
+struct Slots16 {
+  int v[16 / LPR];
+  template <int B>
+  __device__ __forceinline__ int get() const {
+    return group_bcast<LPR, B % LPR>(v[B / LPR]);
+  }
+};
+
+template <int LPR>
+__device__ __forceinline__ void load_slots(const VArgs &a, const VCtx &C, uint32_t e, uint32_t e1, Slots16<LPR> &sl) {
+#pragma unroll
+  for (int r = 0; r < 16 / LPR; ++r) {
+    const uint32_t at = e + C.j + r * LPR;
+    sl.v[r] = at < e1 ? a.idx[at] : 0;
+  }
+}
+
+template <int LPR, int B0>
+__device__ __forceinline__ void read8(const VArgs &a, const VCtx &C, const Slots16<LPR> &sl, int cnt, float4 *v) {
   int s[kBatch];
-  s[0] = row_bcast<0>(sl);
-  s[1] = row_bcast<1>(sl);
-  s[2] = row_bcast<2>(sl);
-  s[3] = row_bcast<3>(sl);
-  s[4] = row_bcast<4>(sl);
-  s[5] = row_bcast<5>(sl);
-  s[6] = row_bcast<6>(sl);
-  s[7] = row_bcast<7>(sl);
+  s[0] = sl.template get<B0 + 0>();
+  s[1] = sl.template get<B0 + 1>();
+  s[2] = sl.template get<B0 + 2>();
+  s[3] = sl.template get<B0 + 3>();
+  s[4] = sl.template get<B0 + 4>();
+  s[5] = sl.template get<B0 + 5>();
+  s[6] = sl.template get<B0 + 6>();
+  s[7] = sl.template get<B0 + 7>();
 #pragma unroll
   for (int b = 0; b < kBatch; ++b)
-    v[b] = (b < cnt && C.act) ? C.cin[(size_t)s[b] * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    v[b] = (B0 + b < cnt && C.act) ? C.cin[(size_t)s[b] * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Adds the rows of cnt <= 16 in-edges, in list order, whose gather slots the
+// group holds in `sl`; 8 row reads in flight per lane.
+template <int LPR>
+__device__ __forceinline__ void chunk16(const VArgs &a, const VCtx &C, const Slots16<LPR> &sl, int cnt, Sum4 &acc) {
+  float4 v[kBatch];
+  read8<LPR, 0>(a, C, sl, cnt, v);
 #pragma unroll
   for (int b = 0; b < kBatch; ++b)
     if (b < cnt) acc.add(v[b]);
   if (cnt > kBatch) {
-    s[0] = row_bcast<8>(sl);
-    s[1] = row_bcast<9>(sl);
-    s[2] = row_bcast<10>(sl);
-    s[3] = row_bcast<11>(sl);
-    s[4] = row_bcast<12>(sl);
-    s[5] = row_bcast<13>(sl);
-    s[6] = row_bcast<14>(sl);
-    s[7] = row_bcast<15>(sl);
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b)
-      v[b] = (kBatch + b < cnt && C.act) ? C.cin[(size_t)s[b] * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    read8<LPR, kBatch>(a, C, sl, cnt, v);
 #pragma unroll
     for (int b = 0; b < kBatch; ++b)
       if (kBatch + b < cnt) acc.add(v[b]);
@@ -191,10 +245,12 @@ __device__ __forceinline__ void chunk16(const VArgs &a, const VCtx &C, int sl, i
 }
 
 // Sum over the in-edges [e0, e1) in list order.
+template <int LPR>
 __device__ __forceinline__ void range_sum(const VArgs &a, const VCtx &C, uint32_t e0, uint32_t e1, Sum4 &acc) {
   for (uint32_t e = e0; e < e1; e += 16) {
-    const int sl = e + C.j < e1 ? a.idx[e + C.j] : 0;
-    chunk16(a, C, sl, (int)min(16u, e1 - e), acc);
+    Slots16<LPR> sl;
+    load_slots<LPR>(a, C, e, e1, sl);
+    chunk16<LPR>(a, C, sl, (int)min(16u, e1 - e), acc);
   }
 }
 
@@ -233,10 +289,12 @@ __device__ __forceinline__ void vupdate(const VArgs &a, const VCtx &C, uint32_t 
 // vertex and slot, and the current row's update operands, load while the
 // current row's rows are read; the next row's first 16 gather slots load
 // while the current row is updated.
+template <int LPR>
 __device__ __forceinline__ void run_rows(const VArgs &a, const VCtx &C, int r0, int r1, VRed &red) {
   uint32_t e0 = a.rptr[r0], e1 = a.rptr[r0 + 1];
   uint32_t u = a.rows[r0], slot = a.rowpos[r0];
-  int sl = e0 + C.j < e1 ? a.idx[e0 + C.j] : 0;
+  Slots16<LPR> sl;
+  load_slots<LPR>(a, C, e0, e1, sl);
   for (int r = r0; r < r1; ++r) {
     const bool more = r + 1 < r1;
     const uint32_t ne1 = more ? a.rptr[r + 2] : e1;
@@ -246,10 +304,10 @@ __device__ __forceinline__ void run_rows(const VArgs &a, const VCtx &C, int r0, 
     const float4 xo = C.act ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
     Sum4 acc;
     for (uint32_t e = e0; e < e1; e += 16) {
-      if (e != e0) sl = e + C.j < e1 ? a.idx[e + C.j] : 0;
-      chunk16(a, C, sl, (int)min(16u, e1 - e), acc);
+      if (e != e0) load_slots<LPR>(a, C, e, e1, sl);
+      chunk16<LPR>(a, C, sl, (int)min(16u, e1 - e), acc);
     }
-    sl = (more && e1 + C.j < ne1) ? a.idx[e1 + C.j] : 0;
+    load_slots<LPR>(a, C, e1, more ? ne1 : e1, sl);
     double s[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) s[q] = acc.v[q].value();
@@ -261,66 +319,71 @@ __device__ __forceinline__ void run_rows(const VArgs &a, const VCtx &C, int r0, 
   }
 }
 
-// The four groups sum one quarter each of [e0, e1); group 0 ends with the
-// whole sum (quarters combined in order).
+// The four groups of a quad-slot sum one quarter each of [e0, e1); group 0
+// ends with the whole sum (quarters combined in order).
+template <int LPR>
 __device__ __forceinline__ Sum4 quarter_sum(const VArgs &a, const VCtx &C, uint32_t e0, uint32_t e1) {
   const uint32_t L = e1 - e0;
   const uint32_t q0 = e0 + (uint32_t)(((uint64_t)L * C.g) / 4);
   const uint32_t q1 = e0 + (uint32_t)(((uint64_t)L * (C.g + 1)) / 4);
   Sum4 acc;
-  range_sum(a, C, q0, q1, acc);
+  range_sum<LPR>(a, C, q0, q1, acc);
   Sum4 tot = acc;
 #pragma unroll
   for (int k = 1; k < 4; ++k) {
-    const Sum4 o = acc.from_lane(C.j + kVGroup * k);
+    const Sum4 o = acc.from_lane(C.base + C.j + LPR * k);
     tot.combine_with(o);
   }
   return tot;
 }
 
-// The change and dangling mass of one item, per column: the four groups in
-// order, written by group 0 to the item's partial slots.  Every item gets a
-// record (zeros for hub chunks), so the per-column totals are sums over items
-// in item order, whichever wavefront ran which item.
-__device__ __forceinline__ void flush_item(const VArgs &a, const VCtx &C, int item, VRed &red) {
-  double ch[4], dg[4];
+// Ends a work item: its per-column sums (the quad-slot's four groups in
+// order), rounded to fixed point, into the workgroup's totals in LDS
+// (integer atomics: the order of the adds does not matter).
+template <int LPR>
+__device__ __forceinline__ void fold_item(const VCtx &C, VRed &red, unsigned long long (*tot)[kVMaxT]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    ch[q] = red.chg[q];
-    dg[q] = red.dang[q];
+    double ch = red.chg[q], dg = red.dang[q];
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
-      ch[q] += __shfl(red.chg[q], C.j + kVGroup * k, 64);
-      dg[q] += __shfl(red.dang[q], C.j + kVGroup * k, 64);
+      ch += __shfl(red.chg[q], C.base + C.j + LPR * k, 64);
+      dg += __shfl(red.dang[q], C.base + C.j + LPR * k, 64);
     }
+    if (C.g == 0 && C.act) {
+      atomicAdd(&tot[0][4 * C.j + q], to_fix(ch));
+      atomicAdd(&tot[1][4 * C.j + q], to_fix(dg));
+    }
+    red.chg[q] = 0.0;
+    red.dang[q] = 0.0;
   }
-  if (C.g == 0 && C.act) {
-    double *rec = a.item_part + (size_t)item * 2 * a.T + 4 * C.j;
-    *reinterpret_cast<double4 *>(rec) = make_double4(ch[0], ch[1], ch[2], ch[3]);
-    *reinterpret_cast<double4 *>(rec + a.T) = make_double4(dg[0], dg[1], dg[2], dg[3]);
-  }
-  red = VRed();
 }
 
+template <int LPR>
 __global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_vsweep(VArgs a0) {
+  constexpr int NQS = 16 / LPR;  // quad-slots per wavefront
+  __shared__ unsigned long long s_tot[2][kVMaxT];
   VArgs a = a0;
   a.x = static_cast<float4 *>(a0.io->x);
-  const VCtx C = make_vctx(a);
+  const VCtx C = make_vctx<LPR>(a);
   // every group holds the same columns: the vote is uniform over the workgroup
   const bool all_frozen = C.frozen[0] && C.frozen[1] && C.frozen[2] && C.frozen[3];
   if (__ballot(!all_frozen) == 0ull) return;
+  if (threadIdx.x < 2 * kVMaxT) s_tot[threadIdx.x / kVMaxT][threadIdx.x % kVMaxT] = 0;
+  __syncthreads();
   const int wave = threadIdx.x >> 6;
-  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kVWaves + wave));
-  const int n_waves = a.n_wg * kVWaves;
+  // each quad-slot takes items as a wavefront of its own would
+  const int vw = (int)(blockIdx.x * kVWaves + wave) * NQS + C.qs;
+  const int nvw = a.n_wg * kVWaves * NQS;
   VRed red;
-  for (int first = gw * a.ipg; first < a.n_items; first += n_waves * a.ipg) {
+  for (int first = vw * a.ipg; first < a.n_items; first += nvw * a.ipg) {
     const int last = min(first + a.ipg, a.n_items);
     for (int item = first; item < last; ++item) {
       const int4 wi = a.items[item];
       if (wi.x == kVQuad) {
         if (C.g < wi.z) {
           const int2 rr = a.vrun[wi.y + C.g];
-          run_rows(a, C, rr.x, rr.y, red);
+          run_rows<LPR>(a, C, rr.x, rr.y, red);
         }
       } else if (wi.x == kVLong) {
         const int r = wi.y;
@@ -328,7 +391,7 @@ __global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) vo
         const uint32_t slot = a.rowpos[r];
         const double iw = a.inv_w[u];
         const float4 xo = (C.g == 0 && C.act) ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const Sum4 tot = quarter_sum(a, C, a.rptr[r], a.rptr[r + 1]);
+        const Sum4 tot = quarter_sum<LPR>(a, C, a.rptr[r], a.rptr[r + 1]);
         if (C.g == 0 && C.act) {
           double s[4];
 #pragma unroll
@@ -339,22 +402,31 @@ __global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) vo
         const uint32_t rb = a.rptr[wi.y], re = a.rptr[wi.y + 1];
         const uint32_t c0 = rb + (uint32_t)wi.z * (uint32_t)a.chunk;
         const uint32_t c1 = min(re, c0 + (uint32_t)a.chunk);
-        const Sum4 tot = quarter_sum(a, C, c0, c1);
+        const Sum4 tot = quarter_sum<LPR>(a, C, c0, c1);
         if (C.g == 0 && C.act) {
           double *hp = a.hpart + (size_t)(wi.w + wi.z) * a.T + 4 * C.j;
 #pragma unroll
           for (int q = 0; q < 4; ++q) hp[q] = tot.v[q].value();
         }
       }
-      flush_item(a, C, item, red);
+      fold_item<LPR>(C, red, s_tot);
     }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * a.T) {
+    const int kind = threadIdx.x / a.T, col = threadIdx.x % a.T;
+    a.wg_part[((size_t)kind * a.T + col) * a.n_wg + blockIdx.x] = s_tot[kind][col];
   }
 }
 
-// One workgroup per column: completes the split hubs, sums the workgroup
-// partials in a fixed order, and updates the column's state.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a0) {
-  __shared__ double s_red[2][kVFin / 64];
+  __shared__ unsigned long long s_red[2][kVFin / 64];
   VArgs a = a0;
   a.x = static_cast<float4 *>(a0.io->x);
   const int col = blockIdx.x;
@@ -364,10 +436,10 @@ __global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a0) {
   const double dterm = st->D[col] * a.inv_n;
   float *xf = reinterpret_cast<float *>(a.x);
   float *cf = reinterpret_cast<float *>(a.par ? a.c0 : a.c1);
-  double chg = 0.0, dang = 0.0;
-  for (int i = threadIdx.x; i < a.n_items; i += kVFin) {
-    chg += a.item_part[(size_t)i * 2 * a.T + col];
-    dang += a.item_part[((size_t)i * 2 + 1) * a.T + col];
+  unsigned long long chg = 0, dang = 0;
+  for (int i = threadIdx.x; i < a.n_wg; i += kVFin) {
+    chg += a.wg_part[(size_t)col * a.n_wg + i];
+    dang += a.wg_part[((size_t)a.T + col) * a.n_wg + i];
   }
   for (int h = threadIdx.x; h < a.n_split; h += kVFin) {
     const int4 hs = a.hsplit[h];
@@ -386,26 +458,27 @@ __global__ __launch_bounds__(kVFin) void k_vfinal(VArgs a0) {
     const float old = xf[(size_t)u * a.T + col];
     const double tele = ((int)u == seed) ? (1.0 - a.d) : 0.0;
     const float xn = (float)(tele + a.d * (s + dterm));
-    chg += fabs((double)xn - (double)old);
+    chg += to_fix(fabs((double)xn - (double)old));
     xf[(size_t)u * a.T + col] = xn;
     const double iw = a.inv_w[u];
     if (iw != 0.0) cf[(size_t)slot * a.T + col] = (float)((double)xn * iw);
-    else dang += (double)xn;
+    else dang += to_fix((double)xn);
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  chg = wave_sum(chg);
-  dang = wave_sum(dang);
+  chg = wave_sum_u64(chg);
+  dang = wave_sum_u64(dang);
   if (lane == 0) {
     s_red[0][wave] = chg;
     s_red[1][wave] = dang;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double ch = s_red[0][0], dg = s_red[1][0];
+    unsigned long long chs = s_red[0][0], dgs = s_red[1][0];
     for (int w = 1; w < kVFin / 64; ++w) {
-      ch += s_red[0][w];
-      dg += s_red[1][w];
+      chs += s_red[0][w];
+      dgs += s_red[1][w];
     }
+    const double ch = (double)chs / kFix, dg = (double)dgs / kFix;
     const int it = st->iters[col] + 1;
     st->iters[col] = it;
     st->resid[col] = ch;
@@ -475,7 +548,8 @@ __global__ void k_vcheck(const int32_t *seeds, int k, int64_t n, int *bad) {
 struct VWork {
   int64_t cols_cap = 0;  // columns the row arrays hold
   float4 *x = nullptr, *c0 = nullptr, *c1 = nullptr;
-  double *hpart = nullptr, *item_part = nullptr;
+  double *hpart = nullptr;
+  unsigned long long *wg_part = nullptr;
   VState *st = nullptr;
   VState *host_st = nullptr;
   IoPtrs *io = nullptr;  // where the sweep kernels find x
@@ -503,7 +577,9 @@ int ensure_vwork(pr_graph *g, VWork &w, int T) {
     if ((rc = fpr_dev_alloc(g, (void **)&w.c1, sizeof(float4) * rows))) return rc;
     if ((rc = fpr_dev_alloc(g, (void **)&w.hpart, sizeof(double) * (size_t)T * (size_t)std::max(1, P.n_chunks))))
       return rc;
-    if ((rc = fpr_dev_alloc(g, (void **)&w.item_part, sizeof(double) * 2 * (size_t)T * (size_t)std::max(1, P.n_bitems))))
+    // partials for the largest grid a shape can ask for (two workgroups per CU)
+    if ((rc = fpr_dev_alloc(g, (void **)&w.wg_part,
+                            sizeof(unsigned long long) * 2 * (size_t)T * (size_t)(2 * std::max(1, g->n_cu)))))
       return rc;
     w.cols_cap = T;
   }
@@ -560,7 +636,7 @@ VArgs make_vargs(pr_graph *g, VWork &w, double d, int T, int col0, const pr_batc
   a.c0 = w.c0;
   a.c1 = w.c1;
   a.hpart = w.hpart;
-  a.item_part = w.item_part;
+  a.wg_part = w.wg_part;
   a.st = w.st;
   a.d = d;
   a.inv_n = 1.0 / (double)g->n;
@@ -576,10 +652,21 @@ VArgs make_vargs(pr_graph *g, VWork &w, double d, int T, int col0, const pr_batc
   return a;
 }
 
+// The sweep kernel for a launch's row width: lanes per row = Q rounded up to
+// a power of two, so a row of T columns is read by T / 4 lanes.
+void launch_vsweep(const VArgs &a, hipStream_t s) {
+  const dim3 grid(a.n_wg), block(kVBlock);
+  if (a.Q <= 1) hipLaunchKernelGGL(k_vsweep<1>, grid, block, 0, s, a);
+  else if (a.Q <= 2) hipLaunchKernelGGL(k_vsweep<2>, grid, block, 0, s, a);
+  else if (a.Q <= 4) hipLaunchKernelGGL(k_vsweep<4>, grid, block, 0, s, a);
+  else if (a.Q <= 8) hipLaunchKernelGGL(k_vsweep<8>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_vsweep<16>, grid, block, 0, s, a);
+}
+
 void launch_vsweeps(pr_graph *g, VArgs a, int par0, int cnt) {
   for (int s = 0; s < cnt; ++s) {
     a.par = (par0 + s) & 1;
-    hipLaunchKernelGGL(k_vsweep, dim3(a.n_wg), dim3(kVBlock), 0, g->work, a);
+    launch_vsweep(a, g->work);
     hipLaunchKernelGGL(k_vfinal, dim3(a.T), dim3(kVFin), 0, g->work, a);
   }
 }

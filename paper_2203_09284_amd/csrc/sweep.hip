@@ -650,9 +650,11 @@ void k_sweep(SweepArgs<T> a) {
 // run); a source outside the block is read from c as it stands, this sweep's
 // value if its block is done, the previous one if not (the asynchrony that
 // Section 4.3 allows; other XCDs see writes no sooner than the launch ends).
-// Within a step the rows use the values from before the step: lanes take the
-// rows of up to kIpShort in-edges one edge at a time, then the wavefront sums
-// the longer rows of the step one by one, its 64 lanes striding the list.
+// Within a step the rows use the values from before the step: lanes sum the
+// rows of up to kIpShort in-edges themselves (kBatch loads in flight), then
+// the wavefront sums the longer rows of the step one by one, its 64 lanes
+// striding the list.  The next vertex's list end and the update operands load
+// while the step's values are gathered.
 // The update is Eq. 1 with the lagged dangling mass and, with kFlagScaled,
 // the mass-scaled teleport of the fused form; the new contribution goes to
 // LDS and to c.  Reductions as in k_sweep (one partial per workgroup).
@@ -661,13 +663,19 @@ constexpr int kIpShort = 32;  // longest row a single lane sums
 template <typename T>
 constexpr int kIpVpb = kIpLds / (int)sizeof(T);  // vertices per block: 1024 FP64, 2048 FP32
 
+// Edge e's value for the in-place form (ok: e is an edge of the row; a lane
+// past the row's end reads nothing from memory): from the block's LDS copy
+// when the source s lies in the block, else from the shared array (the global
+// load runs only on the lanes that need it, so a batch stays branch-free).
 template <typename T, bool WEIGHTED>
-__device__ __forceinline__ T ip_gather(const SweepArgs<T> &a, const T *blk, const T *c, int64_t b0, int nb,
-                                       uint32_t e) {
-  const int32_t s = sld(a.idx + e);
+__device__ __forceinline__ T ip_value(const SweepArgs<T> &a, const T *blk, const T *c, int64_t b0, int nb,
+                                      int32_t s, uint32_t e, bool ok) {
   const uint32_t ls = (uint32_t)((int64_t)s - b0);
-  T v = ls < (uint32_t)nb ? blk[ls] : c[s];
-  if constexpr (WEIGHTED) v = wmul(v, sld(a.w + e));
+  const bool in = ls < (uint32_t)nb;
+  const T vh = blk[in ? ls : 0];
+  T v = vh;
+  if (ok && !in) v = ((gptr<T>)c)[s];
+  if constexpr (WEIGHTED) v = ok ? wmul(v, sld(a.w + e)) : (T)0;
   return v;
 }
 
@@ -690,40 +698,76 @@ void k_inplace(SweepArgs<T> a) {
   for (int64_t b = (int64_t)blockIdx.x * kSweepWaves + wave; b < nblocks; b += W) {
     const int64_t b0 = b * VPB;
     const int nb = (int)min((int64_t)VPB, a.nv - b0);
-    for (int i = lane; i < nb; i += 64) blk[i] = c[b0 + i];
+    {
+      // the block's contributions into LDS: every load issued before the
+      // first LDS write (one memory round trip per block)
+      T v[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) v[k] = lane + 64 * k < nb ? c[b0 + lane + 64 * k] : (T)0;
+#pragma unroll
+      for (int k = 0; k < PER; ++k)
+        if (lane + 64 * k < nb) blk[lane + 64 * k] = v[k];
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // this lane's run: local vertices lo .. lo + PER - 1; the list bounds of
+    // the next vertex load one step ahead
+    const int lo = lane * PER;
+    uint32_t e0 = lo < nb ? sld(a.rptr + (b0 + lo)) : 0u;
+    uint32_t e1 = lo < nb ? sld(a.rptr + (b0 + lo + 1)) : 0u;
     for (int k = 0; k < PER; ++k) {
-      const int i = lane * PER + k;
+      const int i = lo + k;
       const bool act = i < nb;
-      uint32_t e0 = 0, e1 = 0;
+      const int64_t u = b0 + i;
+      // update operands and the next step's list end, independent of the sums
+      double xo = 0.0, iw = 0.0, pu = C.inv_n;
       if (act) {
-        e0 = sld(a.rptr + (b0 + i));
-        e1 = sld(a.rptr + (b0 + i + 1));
+        xo = (double)C.x[u];
+        iw = sld(C.inv_w + u);
+        if (!(C.flags & kFlagUniformP)) pu = sld(C.p + u);
       }
-      const bool lng = e1 - e0 > (uint32_t)kIpShort;
+      const uint32_t e2 = (i + 1 < nb && k + 1 < PER) ? sld(a.rptr + (u + 2)) : e1;
+      const uint32_t L = act ? e1 - e0 : 0u;
+      const bool lng = L > (uint32_t)kIpShort;
       LaneSum<T> acc;
-      if (act && !lng) {
-        uint32_t e = e0;
-        for (; e + 4 <= e1; e += 4) {
-          T v[4];
+      if (!lng) {
+        // rows of up to kIpShort edges: kBatch neighbour ids, then kBatch
+        // values, in flight per lane
+        for (uint32_t j0 = 0; j0 < L; j0 += kBatch) {
+          int32_t sv[kBatch];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) v[j] = ip_gather<T, WEIGHTED>(a, blk, c, b0, nb, e + j);
+          for (int j = 0; j < kBatch; ++j) sv[j] = j0 + j < L ? sld(a.idx + (e0 + j0 + j)) : (int32_t)b0;
+          T v[kBatch];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc.add(v[j]);
+          for (int j = 0; j < kBatch; ++j)
+            v[j] = ip_value<T, WEIGHTED>(a, blk, c, b0, nb, sv[j], e0 + j0 + j, j0 + j < L);
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j)
+            if (j0 + j < L) acc.add(v[j]);
         }
-        for (; e < e1; ++e) acc.add(ip_gather<T, WEIGHTED>(a, blk, c, b0, nb, e));
       }
       double sum = acc.value();
-      // the step's long rows, one at a time, by the whole wavefront
-      uint64_t lm = __ballot(act && lng);
+      // the step's long rows, one at a time, by the whole wavefront (a lane's
+      // edges are f0 + lane, + 64, ...; kBatch loads in flight)
+      uint64_t lm = __ballot(lng);
       while (lm) {
         const int r = __builtin_ctzll(lm);
         lm &= lm - 1;
         const uint32_t f0 = __builtin_amdgcn_readlane(e0, r), f1 = __builtin_amdgcn_readlane(e1, r);
         LaneSum<T> part;
-        for (uint32_t e = f0 + lane; e < f1; e += 64) part.add(ip_gather<T, WEIGHTED>(a, blk, c, b0, nb, e));
+        for (uint32_t e = f0 + lane; e < f1; e += 64 * kBatch) {
+          int32_t sv[kBatch];
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j) sv[j] = e + 64 * j < f1 ? sld(a.idx + (e + 64 * j)) : (int32_t)b0;
+          T v[kBatch];
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j)
+            v[j] = ip_value<T, WEIGHTED>(a, blk, c, b0, nb, sv[j], e + 64 * j, e + 64 * j < f1);
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j)
+            if (e + 64 * j < f1) part.add(v[j]);
+        }
         part.group_reduce(64);
         if (lane == r) sum = part.value();
       }
@@ -731,10 +775,6 @@ void k_inplace(SweepArgs<T> a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (act) {
-        const int64_t u = b0 + i;
-        const double xo = (double)C.x[u];
-        const double iw = sld(C.inv_w + u);
-        const double pu = (C.flags & kFlagUniformP) ? C.inv_n : sld(C.p + u);
         const double xn = C.tele * pu + C.d * (sum + C.dterm);
         const T xs = (T)xn;
         C.x[u] = xs;
@@ -752,6 +792,8 @@ void k_inplace(SweepArgs<T> a) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      e0 = e1;
+      e1 = e2;
     }
   }
   const double chg = wave_sum(red.chg);
@@ -1356,12 +1398,23 @@ int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &
   if ((rc = set_io(g, P, x, p))) return rc;
   SweepArgs<T> a = make_args<T>(g, P, p, d, flags, trace, c0, c1, form);
   prime_list<T>(g, a, form);
+  // Sweeps are queued in batches between host polls: G, then G/2, then as
+  // many as the residual's decay over the last batch predicts are still
+  // needed (at most G), so that few sweeps queue past convergence.  A batch
+  // runs as hipGraphs of power-of-two sweep counts, so at most four graphs
+  // per form are captured.  The FP32 stage keeps batches of G: it stops when
+  // the residual fails to halve between polls (its floor).
   const int G = std::max(1, o.sweeps_per_poll);
   double prev = INFINITY;
   int done_sweeps = 0;
+  int cnt = std::min(G, max_iter);
   for (;;) {
-    const int cnt = std::min(G, max_iter - done_sweeps);
-    if ((rc = run_sweeps<T>(g, a, form, o.use_hip_graph != 0, cnt))) return rc;
+    for (int left = cnt; left > 0;) {
+      int piece = 1;
+      while (piece * 2 <= left) piece *= 2;
+      if ((rc = run_sweeps<T>(g, a, form, o.use_hip_graph != 0, piece))) return rc;
+      left -= piece;
+    }
     if ((rc = poll_state(g, P))) return rc;
     const int before = done_sweeps;
     done_sweeps = g->host_st->iter;
@@ -1371,7 +1424,16 @@ int solve_stage(pr_graph *g, double d, double tol, int max_iter, const pr_opts &
     const double r = g->host_st->resid;
     if (!(r == r)) return pr_fail(PR_EDEVICE, "residual is NaN after sweep %d", done_sweeps);
     if (stall && r >= 0.5 * prev) break;
+    int next = G;
+    if (!stall && prev == INFINITY) {
+      next = std::max(1, G / 2);
+    } else if (!stall && r > 0.0 && r < prev && tol > 0.0) {
+      const double rate = std::pow(r / prev, 1.0 / cnt);
+      const double need = std::log(tol / r) / std::log(rate);
+      if (need == need) next = (int)std::min<double>(G, std::max(1.0, std::ceil(need + 0.25)));
+    }
     prev = r;
+    cnt = std::min(next, max_iter - done_sweeps);
   }
   *iters = g->host_st->iter;
   *resid = g->host_st->resid;

@@ -95,7 +95,9 @@ def test_new_output_and_teleport_vectors_reuse_the_captured_graph():
         p_ref = _ref(n, s, t, p_h)
         assert ok and l1(x.cpu().numpy(), p_ref) <= 1e-9, k
     after_p = g.stats()["graph_captures"]
-    assert after_p <= base + 1  # at most one more: "p given" is a different launch configuration
+    # "p given" is another launch configuration: its own graphs, at most one
+    # per power-of-two batch size (8, 4, 2, 1), whatever the number of vectors
+    assert after_p <= base + 4
     g.close()
 
 
