@@ -577,7 +577,7 @@ def pmc_summary(args):
     import csv
     key, fetch_csv, write_csv, driver_log = args.pmc_summary
     drv = json.loads([ln for ln in open(driver_log) if ln.startswith('{"profile"')][-1])
-    kname = ("k_vsweep(" if drv["profile"] == "batched" else
+    kname = ("k_vsweep<" if drv["profile"] == "batched" else
              "k_inplace<" if drv["profile"].startswith("inplace") else "k_sweep<")
 
     def read(path, counter):
