@@ -658,10 +658,13 @@ void k_sweep(SweepArgs<T> a) {
 // The update is Eq. 1 with the lagged dangling mass and, with kFlagScaled,
 // the mass-scaled teleport of the fused form; the new contribution goes to
 // LDS and to c.  Reductions as in k_sweep (one partial per workgroup).
-constexpr int kIpLds = 8192;  // LDS bytes per wavefront for its block
-constexpr int kIpShort = 32;  // longest row a single lane sums
+#ifndef FPR_IP_RUN
+#define FPR_IP_RUN 2
+#endif
+constexpr int kIpRun = FPR_IP_RUN;  // consecutive vertices a lane updates in order
+constexpr int kIpShort = 32;        // longest row a single lane sums
 template <typename T>
-constexpr int kIpVpb = kIpLds / (int)sizeof(T);  // vertices per block: 1024 FP64, 2048 FP32
+constexpr int kIpVpb = 64 * kIpRun;  // vertices per block
 
 // Edge e's value for the in-place form (ok: e is an edge of the row; a lane
 // past the row's end reads nothing from memory): from the block's LDS copy
