@@ -302,6 +302,12 @@ def leg_road(torch, fpr, oracle, steps, warmup, threads):
                forms={k: rounded(v) for k, v in forms.items()},
                kernel_us={k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
                alg_gbs_jacobi_fp64=sig(b_alg(n, m, 8) / (kern["jacobi-fp64"][0] * 1e-6) / 1e9))
+    # the fastest form on this graph: the in-place sweep, against the same
+    # algorithmic bytes (it reads the same per-vertex and per-edge arrays)
+    b64 = b_alg(n, m, 8)
+    ki = kern["inplace-fp64"][0]
+    out["roofline_inplace_fp64"] = roofline(b64 / (ki * 1e-6) / 1e9, traffic_record("inplace_fp64_road8m"),
+                                            "k_inplace<double>", b64, ki, 1)
     out["speedup_vs_jacobi_fp64"] = {k: sig(forms["jacobi-fp64"]["ms"] / f["ms"]) for k, f in forms.items()
                                      if k != "jacobi-fp64"}
     log("road8m: jacobi %.3f ms (%d), fused %.3f ms (%d), inplace %.3f ms (%d), sweep %.1f us" %
