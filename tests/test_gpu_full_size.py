@@ -141,7 +141,8 @@ def test_rmat18_weighted_adjoint():
 @pytest.mark.timeout(1200)
 def test_rmat24_bfs_forms_oracle_certificate():
     """Scale 24 (BFS order) in the benchmark's launch configuration: fused FP32
-    with FP64 refinement, fused FP64 and Jacobi FP64, each solved to 1e-12.  The
+    with FP64 refinement, fused FP64, Jacobi FP64 and the in-place form (FP64),
+    each solved to 1e-12.  The
     oracle's CSR build takes minutes at this size, so the oracle checks every
     result through one application of Eq. 1 straight from the raw edge list:
     ||x - x*||_1 <= ||F(x) - x||_1 / (1 - d) must be at most 1e-9 for the whole
@@ -153,7 +154,7 @@ def test_rmat24_bfs_forms_oracle_certificate():
     w = gg.rmat24_bfs()
     n, src, dst = w["n"], w["src"], w["dst"]
     say("rmat24 graph")
-    g = fpr.Graph(n, src, dst)
+    g = fpr.Graph(n, src, dst, plan=dict(with_inplace=1))
     st = g.stats()
     in_deg = np.bincount(dst, minlength=n)
     hubs = np.flatnonzero(in_deg > st["chunk"])
@@ -163,7 +164,7 @@ def test_rmat24_bfs_forms_oracle_certificate():
                                                                    len(hubs), len(rows)))
     assert len(hubs) > 0 and in_deg.max() > 8 * st["chunk"]  # both hub kinds are exercised
     results = {}
-    for mode, prec in (("fused", "fp32"), ("fused", "fp64"), ("jacobi", "fp64")):
+    for mode, prec in (("fused", "fp32"), ("fused", "fp64"), ("jacobi", "fp64"), ("inplace", "fp64")):
         say("rmat24 solve %s %s" % (mode, prec))
         x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=1000, mode=mode, precision=prec)
         assert ok, (mode, prec)
@@ -176,6 +177,7 @@ def test_rmat24_bfs_forms_oracle_certificate():
     # every pair of results is within the sum of their bounds of each other
     a, b = results[("fused", "fp64")], results[("jacobi", "fp64")]
     assert l1(a, b) <= 2e-9 and l1(results[("fused", "fp32")], b) <= 2e-9
+    assert l1(results[("inplace", "fp64")], b) <= 2e-9
     g.close()
 
 
@@ -187,13 +189,14 @@ def test_road8m_forms():
     og = oracle.csr(n, w["src"], w["dst"])
     xr, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=2000, threads=THREADS)
     say("road8m")
-    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1))
-    for mode in ("jacobi", "fused", "edge_list"):
+    g = fpr.Graph(n, w["src"], w["dst"], plan=dict(with_cl=1, with_inplace=1))
+    for mode in ("jacobi", "fused", "edge_list", "fused_edge_list", "inplace"):
         x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=2000, mode=mode)
-        say("  %s sweeps=%d" % (mode, it))
+        say("  %s sweeps=%d L1 vs oracle %.2e" % (mode, it, l1(x.cpu().numpy(), xr)))
         assert ok and l1(x.cpu().numpy(), xr) <= 1e-9, mode
-    x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=2000, mode="fused", precision="fp32")
-    assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
+    for mode in ("fused", "inplace"):
+        x, it, res, ok = g.solve(d=D, tol=1e-12, max_iter=2000, mode=mode, precision="fp32")
+        assert ok and l1(x.cpu().numpy(), xr) <= 1e-9, mode
     g.close()
 
 
