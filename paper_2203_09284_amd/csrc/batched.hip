@@ -42,6 +42,21 @@ using namespace fpr::dev;
 
 namespace {
 
+// Rows streamed once per sweep (the ranks, read and written; the new
+// contribution rows, written) go through non-temporal loads and stores, so
+// they do not push the gathered contribution rows of popular sources out of
+// L2.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 nt_load(const float4 *p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void nt_store(float4 *p, const float4 &v) {
+  const nt_f4 t = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(t, reinterpret_cast<nt_f4 *>(p));
+}
+
+
 constexpr int kVBlock = 512;          // threads per workgroup of the sweep
 constexpr int kVWaves = kVBlock / 64;
 constexpr int kVMaxT = 64;            // columns per launch at most
@@ -274,11 +289,11 @@ __device__ __forceinline__ void vupdate(const VArgs &a, const VCtx &C, uint32_t 
       red.chg[q] += fabs((double)xn[q] - (double)old);
     }
   }
-  a.x[(size_t)u * a.Q + C.j] = make_float4(xn[0], xn[1], xn[2], xn[3]);
+  nt_store(&a.x[(size_t)u * a.Q + C.j], make_float4(xn[0], xn[1], xn[2], xn[3]));
   if (iw != 0.0) {
-    C.cout[(size_t)slot * a.Q + C.j] =
-        make_float4((float)((double)xn[0] * iw), (float)((double)xn[1] * iw), (float)((double)xn[2] * iw),
-                    (float)((double)xn[3] * iw));
+    nt_store(&C.cout[(size_t)slot * a.Q + C.j],
+             make_float4((float)((double)xn[0] * iw), (float)((double)xn[1] * iw),
+                         (float)((double)xn[2] * iw), (float)((double)xn[3] * iw)));
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q) red.dang[q] += (double)xn[q];
@@ -301,7 +316,7 @@ __device__ __forceinline__ void run_rows(const VArgs &a, const VCtx &C, int r0, 
     const uint32_t nu = more ? a.rows[r + 1] : 0u;
     const uint32_t nslot = more ? a.rowpos[r + 1] : 0u;
     const double iw = a.inv_w[u];
-    const float4 xo = C.act ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 xo = C.act ? nt_load(&a.x[(size_t)u * a.Q + C.j]) : make_float4(0.f, 0.f, 0.f, 0.f);
     Sum4 acc;
     for (uint32_t e = e0; e < e1; e += 16) {
       if (e != e0) load_slots<LPR>(a, C, e, e1, sl);
@@ -390,7 +405,7 @@ __global__ __launch_bounds__(kVBlock) __attribute__((amdgpu_waves_per_eu(4))) vo
         const uint32_t u = a.rows[r];
         const uint32_t slot = a.rowpos[r];
         const double iw = a.inv_w[u];
-        const float4 xo = (C.g == 0 && C.act) ? a.x[(size_t)u * a.Q + C.j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 xo = (C.g == 0 && C.act) ? nt_load(&a.x[(size_t)u * a.Q + C.j]) : make_float4(0.f, 0.f, 0.f, 0.f);
         const Sum4 tot = quarter_sum<LPR>(a, C, a.rptr[r], a.rptr[r + 1]);
         if (C.g == 0 && C.act) {
           double s[4];
