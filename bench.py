@@ -660,6 +660,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU: the HIP library has no CPU path")
     torch.cuda.set_device(0)
+    # host threads for the oracle legs: one GPU's process gets a share of 16
+    # host CPUs, whatever the host shows (`nproc` is reported beside it)
     cores = min(os.cpu_count() or 1, 16)
 
     if args.only:
