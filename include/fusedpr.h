@@ -127,13 +127,15 @@ typedef struct pr_plan_opts {
   int steps;             /* one-wavefront rows per work item (default 1) */
   int hot_slots;         /* gather slots staged in LDS per sweep workgroup (-1 = as many as fit,
                             0 = none) */
-  int gather_layout;     /* order of the gathered array: 1 (default) sorted by gather count, the
-                            hottest vertices first; 0 vertex-id order; 2 the most gathered
-                            vertices (as many as the LDS copy holds in FP32) first, the rest in
-                            vertex-id order, which keeps the locality of an ordered input */
+  int gather_layout;     /* order of the gathered array: 1 sorted by gather count, the hottest
+                            vertices first; 0 vertex-id order; 2 the most gathered vertices (as
+                            many as the LDS copy holds in FP32) first, the rest in vertex-id
+                            order, which keeps the locality of an ordered input; -1 (default)
+                            2 when the input is local (see local_share), else 1 */
   int with_adjoint;      /* also plan the out-edge (transposed) pull for pr_adjoint */
-  int gs_blocks;         /* Gauss-Seidel blocks of the fused form (0 = default by edges per
-                            sweep wavefront: 1 under 64, 2 under 6144, 3 under 49152, else 8;
+  int gs_blocks;         /* Gauss-Seidel blocks of the fused form (0 = default: 1 when the
+                            input is local (see local_share), else by edges per sweep
+                            wavefront: 1 under 64, 2 under 6144, 3 under 49152, else 8;
                             else 1..64): the
                             vertices, in decreasing out-degree, are cut into this many blocks
                             of equal in-edge count (hubs join the last block) and swept one
@@ -169,6 +171,16 @@ typedef struct pr_graph_stats {
                                          output or teleport vector) */
   uint64_t signature;                 /* 64-bit hash of the stored graph (sizes, offsets,
                                          neighbours, weights): the key of tuned settings */
+  double local_share;                 /* share of the in-edges whose source id is within
+                                         1024 of the destination's.  At 1/4 or more, and at
+                                         least four times the share of a random labeling
+                                         (about 2048 / n), the input counts as local (a grid,
+                                         a mesh, a road network in its natural order):
+                                         out-degree blocks would then
+                                         interleave in id order and read every source line
+                                         once per block, so the default plan keeps one block
+                                         and the id order of the gathered array */
+  int gather_layout;                  /* the gathered array's order, as resolved */
 } pr_graph_stats;
 
 int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *out);

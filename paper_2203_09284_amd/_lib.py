@@ -40,7 +40,8 @@ class PrGraphStats(ctypes.Structure):
                 ("e_light", ctypes.c_int64), ("e_medium", ctypes.c_int64), ("e_heavy", ctypes.c_int64),
                 ("n_items", ctypes.c_int64), ("n_dangling", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("grid", ctypes.c_int), ("gs_blocks", ctypes.c_int),
-                ("chunk", ctypes.c_int), ("graph_captures", ctypes.c_int64), ("signature", ctypes.c_uint64)]
+                ("chunk", ctypes.c_int), ("graph_captures", ctypes.c_int64), ("signature", ctypes.c_uint64),
+                ("local_share", ctypes.c_double), ("gather_layout", ctypes.c_int)]
 
 
 class PrBatchShape(ctypes.Structure):

@@ -39,6 +39,7 @@ constexpr int kBatch = 8;                     // loads in flight per lane and ba
 constexpr int kPrefetch = 4;                  // row rounds whose list bounds are loaded up front
 constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather slots, per workgroup
 constexpr int kHotLayout = kHotBytes / 4;     // slots kept in gather-count order by gather_layout 2
+constexpr int64_t kLocalSpan = 1024;          // id distance under which an in-edge counts as local
 constexpr int kTileEdges = 512;               // edges of a tile: 8 consecutive per lane
 constexpr int kTileRows = 128;                // rows of a tile at most (row sums staged in LDS)
 constexpr int kVRunCost = 64;                 // batched: batch rounds per run of short rows
@@ -156,6 +157,7 @@ struct GraphEntry {
 struct pr_graph {
   int device = 0;
   int n_cu = 0;
+  double local_share = 0.0;  // in-edges whose source id is within kLocalSpan of the destination
   int64_t n = 0, m = 0;
   bool weighted = false;
   pr_plan_opts popts{};

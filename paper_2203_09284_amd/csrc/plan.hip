@@ -46,7 +46,7 @@ extern "C" void pr_plan_opts_default(pr_plan_opts *o) {
   o->tile_rows = kTileRows;
   o->steps = 1;
   o->hot_slots = -1;
-  o->gather_layout = 1;
+  o->gather_layout = -1;
   o->with_adjoint = 0;
   o->gs_blocks = 0;
   o->with_cl = 0;
@@ -541,7 +541,7 @@ static int create_impl(const pr_csr *csr, const pr_plan_opts *opts, int mem_mode
   if (opts) o = *opts;
   if ((o.chunk != 0 && (o.chunk < 64 || o.chunk > (1 << 20))) || o.tile_max_row < 0 || o.tile_max_row > kTileEdges ||
       o.tile_rows < 1 || o.tile_rows > kTileRows || o.steps < 1 || o.steps > 64 || o.gs_blocks < 0 ||
-      o.gs_blocks > 64 || o.gather_layout < 0 || o.gather_layout > 2)
+      o.gs_blocks > 64 || o.gather_layout < -1 || o.gather_layout > 2)
     return pr_fail(PR_EINVAL,
                    "pr_graph_create: need chunk = 0 or 64 <= chunk <= 2^20, 0 <= tile_max_row <= 512, "
                    "1 <= tile_rows <= 128, 1 <= steps <= 64, 0 <= gs_blocks <= 64, gather_layout 0..2");
@@ -593,6 +593,24 @@ static int create_impl(const pr_csr *csr, const pr_plan_opts *opts, int mem_mode
     o.chunk = (int)c;
   }
   o.tile_max_row = std::min(o.tile_max_row, o.chunk);
+  {
+    // share of in-edges whose source id lies within kLocalSpan of the
+    // destination's: the input's own order already groups the sources of
+    // neighbouring rows
+    int64_t near = 0;
+    for (int64_t u = 0; u < csr->n; ++u)
+      for (int64_t e = csr->in_ptr[u]; e < csr->in_ptr[u + 1]; ++e) {
+        const int64_t dv = (int64_t)csr->in_src[e] - u;
+        near += (dv < kLocalSpan && dv > -kLocalSpan) ? 1 : 0;
+      }
+    g->local_share = csr->m > 0 ? (double)near / (double)csr->m : 0.0;
+  }
+  // local: a quarter of the in-edges or more, and at least four times the
+  // share a random labeling gives (about 2 kLocalSpan / n)
+  const double random_share = std::min(1.0, (double)(2 * kLocalSpan - 1) / (double)csr->n);
+  const bool local = g->local_share >= 0.25 && g->local_share >= 4.0 * random_share;
+  if (o.gather_layout < 0) o.gather_layout = local ? 2 : 1;
+  if (o.gs_blocks == 0 && local) o.gs_blocks = 1;
   if (o.gs_blocks == 0) {
     // Each block costs a launch (ramp and tail, about 10 us) and saves
     // sweeps; the longer a sweep, the more blocks pay off.  By edges per
@@ -759,5 +777,7 @@ extern "C" int pr_graph_stats_get(const pr_graph *g, pr_graph_stats *s) {
   s->chunk = g->fwd.chunk;
   s->graph_captures = g->graph_captures;
   s->signature = g->signature;
+  s->local_share = g->local_share;
+  s->gather_layout = g->popts.gather_layout;
   return PR_OK;
 }

@@ -327,6 +327,39 @@ def test_edge_list_form_needs_its_plan():
     g.close()
 
 
+def test_local_input_keeps_one_block_and_id_order():
+    """The default plan measures the share of in-edges whose source id is
+    within 1024 of the destination's.  A street grid in row-major order is
+    local (about half its in-edges join horizontal neighbours): the default plan
+    keeps one Gauss-Seidel block and the hot-first, then id-order gathered
+    array, and solves with the same bits as that plan asked for explicitly.  A
+    permuted R-MAT graph is not local and keeps the plan by edges per sweep
+    wavefront and gather-count order."""
+    fpr = _fpr()
+    side = 300
+    s, t = gg.road_grid(side, seed=81)
+    n = side * side
+    _, xr = _ref(n, s, t, None, None)
+    g = fpr.Graph(n, s, t)
+    st = g.stats()
+    say("road grid: local share %.3f, blocks %d, layout %d" % (st["local_share"], st["gs_blocks"], st["gather_layout"]))
+    assert st["local_share"] >= 0.25 and st["gs_blocks"] == 1 and st["gather_layout"] == 2
+    e = fpr.Graph(n, s, t, plan=dict(gs_blocks=1, gather_layout=2))
+    for mode in ("jacobi", "fused"):
+        a = g.solve(d=D, tol=1e-12, mode=mode)
+        b = e.solve(d=D, tol=1e-12, mode=mode)
+        assert a[1] == b[1] and torch.equal(a[0], b[0]), mode
+        assert l1(a[0].cpu().numpy(), xr) <= 1e-9
+    g.close()
+    e.close()
+    s, t = gg.rmat(14, 16, seed=2)
+    g = fpr.Graph(1 << 14, s, t)
+    st = g.stats()
+    say("rmat14: local share %.3f, blocks %d, layout %d" % (st["local_share"], st["gs_blocks"], st["gather_layout"]))
+    assert st["local_share"] < 0.25 and st["gather_layout"] == 1
+    g.close()
+
+
 def test_gauss_seidel_blocks_cut_sweeps():
     """Block Gauss-Seidel over out-degree-ordered blocks needs fewer sweeps than
     Jacobi (Stein-Rosenberg for the regular splitting; soft check), and every
