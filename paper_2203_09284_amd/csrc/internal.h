@@ -40,6 +40,16 @@ constexpr int kPrefetch = 4;                  // row rounds whose list bounds ar
 constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather slots, per workgroup
 constexpr int kHotLayout = kHotBytes / 4;     // slots kept in gather-count order by gather_layout 2
 constexpr int64_t kLocalSpan = 1024;          // id distance under which an in-edge counts as local
+#ifndef FPR_IP_RUN
+#define FPR_IP_RUN 2
+#endif
+// In-place form: a wavefront's block of 64 * kIpRun vertices is updated in
+// kIpRun steps, lane l taking its run of consecutive vertices l * kIpRun + k
+// (k = 0 .. kIpRun - 1).  The plan stores the block interleaved: vertex
+// l * kIpRun + k sits at position 64 k + l, so every step reads and writes
+// consecutive positions (the last, partial block keeps vertex order).
+constexpr int kIpRun = FPR_IP_RUN;
+constexpr int kIpVpb = 64 * kIpRun;
 constexpr int kTileEdges = 512;               // edges of a tile: 8 consecutive per lane
 constexpr int kTileRows = 128;                // rows of a tile at most (row sums staged in LDS)
 constexpr int kVRunCost = 64;                 // batched: batch rounds per run of short rows
@@ -131,10 +141,13 @@ struct DevPlan {
   double *cl_w = nullptr;         // [m] its weight (weighted graphs)
   int64_t cl_size = 0;            // list positions (tiles * 512 + m)
   uint32_t cl_rows = 0;           // first position of the idx region
-  // in-place form (plan option with_inplace): the in-edges in vertex order
-  uint32_t *ip_ptr = nullptr;     // [n+1] offsets
-  int32_t *ip_src = nullptr;      // [m] source vertex ids
+  // in-place form (plan option with_inplace): the in-edges by position
+  // (vertex order, interleaved inside each block: kIpRun)
+  uint32_t *ip_ptr = nullptr;     // [n+1] offsets, in position order
+  int32_t *ip_src = nullptr;      // [m] source positions
   double *ip_w = nullptr;         // [m] weights (weighted graphs)
+  uint32_t *ip_pos = nullptr;     // [n] position of each vertex
+  double *ip_iw = nullptr;        // [n] 1/W in position order
   std::vector<int64_t> cl_group;  // [n_blocks + 2] first scatter entry of each group: sources
                                   // updated by block b's launch, then by the finalize kernel
   std::vector<uint8_t> upd_launch;  // host, during planning: the launch that updates each vertex

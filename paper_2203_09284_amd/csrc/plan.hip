@@ -687,12 +687,38 @@ static int create_impl(const pr_csr *csr, const pr_plan_opts *opts, int mem_mode
       if (csr->in_w && (rc2 = upload(g, &g->fwd.cl_w, wv.data(), wv.size()))) return rc2;
     }
     if (o.with_inplace) {
-      // the in-place form reads the canonical in-lists as they are
+      // the canonical in-lists, rows and sources renumbered by position:
+      // inside a full block of kIpVpb vertices, vertex b0 + l * kIpRun + k
+      // sits at position b0 + 64 k + l; the last, partial block keeps
+      // vertex order
+      std::vector<uint32_t> pos(n), vert(n);
+      for (int64_t b0 = 0; b0 < n; b0 += kIpVpb) {
+        const int64_t nb = std::min<int64_t>(kIpVpb, n - b0);
+        for (int64_t i = 0; i < nb; ++i) {
+          const int64_t v = nb == kIpVpb ? b0 + (i % 64) * kIpRun + i / 64 : b0 + i;
+          pos[v] = (uint32_t)(b0 + i);
+          vert[b0 + i] = (uint32_t)v;
+        }
+      }
       std::vector<uint32_t> ip(n + 1);
-      for (int64_t v = 0; v <= n; ++v) ip[v] = (uint32_t)csr->in_ptr[v];
+      std::vector<int32_t> isrc((size_t)csr->m);
+      std::vector<double> iwt(csr->in_w ? (size_t)csr->m : 0), iiw(n);
+      ip[0] = 0;
+      for (int64_t q = 0; q < n; ++q) {
+        const int64_t v = vert[q];
+        uint32_t at = ip[q];
+        for (int64_t e = csr->in_ptr[v]; e < csr->in_ptr[v + 1]; ++e, ++at) {
+          isrc[at] = (int32_t)pos[csr->in_src[e]];
+          if (csr->in_w) iwt[at] = csr->in_w[e];
+        }
+        ip[q + 1] = at;
+        iiw[q] = inv_w[v];
+      }
       if ((rc2 = upload(g, &g->fwd.ip_ptr, ip.data(), ip.size()))) return rc2;
-      if ((rc2 = upload(g, &g->fwd.ip_src, csr->in_src, (size_t)csr->m))) return rc2;
-      if (csr->in_w && (rc2 = upload(g, &g->fwd.ip_w, csr->in_w, (size_t)csr->m))) return rc2;
+      if ((rc2 = upload(g, &g->fwd.ip_src, isrc.data(), isrc.size()))) return rc2;
+      if (csr->in_w && (rc2 = upload(g, &g->fwd.ip_w, iwt.data(), iwt.size()))) return rc2;
+      if ((rc2 = upload(g, &g->fwd.ip_pos, pos.data(), pos.size()))) return rc2;
+      if ((rc2 = upload(g, &g->fwd.ip_iw, iiw.data(), iiw.size()))) return rc2;
     }
     if (o.with_adjoint) {
       if ((rc2 = build_plan(g, g->adj, n, csr->out_ptr, csr->out_dst, csr->out_w, o, false))) return rc2;

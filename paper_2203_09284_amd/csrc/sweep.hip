@@ -639,12 +639,15 @@ void k_sweep(SweepArgs<T> a) {
 }
 
 // The in-place form (Algorithm 2 / Eq. 9 swept in place, Section 4.3's
-// asynchronous blocks).  The contributions live in one array c in vertex
-// order, read and written during the sweep.  Wavefront w takes the blocks
-// w, w + W, ... of kIpVpb<T> consecutive vertices; for each block it copies
-// the block's contributions into its own LDS slice, then updates the block in
-// kIpVpb / 64 steps: in step k lane l updates vertex l * (kIpVpb / 64) + k of
-// the block, so each lane walks its own run of consecutive vertices in order.
+// asynchronous blocks).  The contributions live in one array c, read and
+// written during the sweep.  Wavefront w takes the blocks w, w + W, ... of
+// kIpVpb consecutive vertices; for each block it copies the block's
+// contributions into its own LDS slice, then updates the block in kIpRun
+// steps: in step k lane l updates vertex l * kIpRun + k of the block, so each
+// lane walks its own run of consecutive vertices in order.  The plan stores
+// the block interleaved (that vertex at position 64 k + l, in c and in every
+// per-position array), so the 64 lanes of a step read and write consecutive
+// positions; only the caller's x (and p) are read and written by vertex.
 // A source inside the block is read from LDS, where it already holds this
 // sweep's value once its lane has passed it (the earlier vertices of every
 // run); a source outside the block is read from c as it stands, this sweep's
@@ -653,18 +656,11 @@ void k_sweep(SweepArgs<T> a) {
 // Within a step the rows use the values from before the step: lanes sum the
 // rows of up to kIpShort in-edges themselves (kBatch loads in flight), then
 // the wavefront sums the longer rows of the step one by one, its 64 lanes
-// striding the list.  The next vertex's list end and the update operands load
-// while the step's values are gathered.
+// striding the list.
 // The update is Eq. 1 with the lagged dangling mass and, with kFlagScaled,
 // the mass-scaled teleport of the fused form; the new contribution goes to
 // LDS and to c.  Reductions as in k_sweep (one partial per workgroup).
-#ifndef FPR_IP_RUN
-#define FPR_IP_RUN 2
-#endif
-constexpr int kIpRun = FPR_IP_RUN;  // consecutive vertices a lane updates in order
-constexpr int kIpShort = 32;        // longest row a single lane sums
-template <typename T>
-constexpr int kIpVpb = 64 * kIpRun;  // vertices per block
+constexpr int kIpShort = 32;  // longest row a single lane sums
 
 // Edge e's value for the in-place form (ok: e is an edge of the row; a lane
 // past the row's end reads nothing from memory): from the block's LDS copy
@@ -685,8 +681,8 @@ __device__ __forceinline__ T ip_value(const SweepArgs<T> &a, const T *blk, const
 template <typename T, bool WEIGHTED>
 __global__ __launch_bounds__(kSweepBlock) __attribute__((amdgpu_waves_per_eu(FPR_WAVES_PER_EU)))
 void k_inplace(SweepArgs<T> a) {
-  constexpr int VPB = kIpVpb<T>;
-  constexpr int PER = VPB / 64;
+  constexpr int VPB = kIpVpb;
+  constexpr int PER = kIpRun;
   __shared__ __align__(16) T blk_all[kSweepWaves][VPB];
   __shared__ double s_part[3][kSweepWaves];
   const SweepState *st = a.st;
@@ -714,23 +710,23 @@ void k_inplace(SweepArgs<T> a) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // this lane's run: local vertices lo .. lo + PER - 1; the list bounds of
-    // the next vertex load one step ahead
-    const int lo = lane * PER;
-    uint32_t e0 = lo < nb ? sld(a.rptr + (b0 + lo)) : 0u;
-    uint32_t e1 = lo < nb ? sld(a.rptr + (b0 + lo + 1)) : 0u;
+    // step k: lane l takes position b0 + 64 k + l, which holds vertex
+    // b0 + l * PER + k of a full block (the k-th of the lane's run), vertex
+    // b0 + 64 k + l of the last, partial block
+    const bool full = nb == VPB;
     for (int k = 0; k < PER; ++k) {
-      const int i = lo + k;
+      const int i = k * 64 + lane;
       const bool act = i < nb;
-      const int64_t u = b0 + i;
-      // update operands and the next step's list end, independent of the sums
+      const int64_t u = full ? b0 + lane * PER + k : b0 + i;
+      // update operands, independent of the sums
+      const uint32_t e0 = act ? sld(a.rptr + (b0 + i)) : 0u;
+      const uint32_t e1 = act ? sld(a.rptr + (b0 + i + 1)) : 0u;
       double xo = 0.0, iw = 0.0, pu = C.inv_n;
       if (act) {
         xo = (double)C.x[u];
-        iw = sld(C.inv_w + u);
+        iw = sld(C.inv_w + (b0 + i));
         if (!(C.flags & kFlagUniformP)) pu = sld(C.p + u);
       }
-      const uint32_t e2 = (i + 1 < nb && k + 1 < PER) ? sld(a.rptr + (u + 2)) : e1;
       const uint32_t L = act ? e1 - e0 : 0u;
       const bool lng = L > (uint32_t)kIpShort;
       LaneSum<T> acc;
@@ -785,7 +781,7 @@ void k_inplace(SweepArgs<T> a) {
         if (iw != 0.0) {
           const T cv = (T)(xd * iw);
           blk[i] = cv;
-          c[u] = cv;
+          c[b0 + i] = cv;
         } else {
           red.dang += xd;
         }
@@ -795,8 +791,6 @@ void k_inplace(SweepArgs<T> a) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      e0 = e1;
-      e1 = e2;
     }
   }
   const double chg = wave_sum(red.chg);
@@ -1097,7 +1091,7 @@ template <typename T>
 int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T *x, double tol,
                 int max_iter, T *c0 = nullptr, int raw = 0, bool vertex_order = false) {
   InitArgs<T> a;
-  a.gpos = vertex_order ? nullptr : P.gpos;
+  a.gpos = vertex_order ? P.ip_pos : P.gpos;
   a.inv_w = g->inv_w;
   a.p = p;
   a.x_in = x_in;
@@ -1187,6 +1181,7 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, double d, int f
     a.rptr = P.ip_ptr;
     a.idx = P.ip_src;
     a.w = P.ip_w;
+    a.inv_w = P.ip_iw;
     a.c1 = a.c0;
     a.n_msplit = 0;
     a.hot = 0;
