@@ -41,7 +41,7 @@ constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather 
 constexpr int kHotLayout = kHotBytes / 4;     // slots kept in gather-count order by gather_layout 2
 constexpr int64_t kLocalSpan = 1024;          // id distance under which an in-edge counts as local
 #ifndef FPR_IP_RUN
-#define FPR_IP_RUN 2
+#define FPR_IP_RUN 8
 #endif
 // In-place form: a wavefront's block of 64 * kIpRun vertices is updated in
 // kIpRun steps, lane l taking its run of consecutive vertices l * kIpRun + k

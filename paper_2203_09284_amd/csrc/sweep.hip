@@ -723,7 +723,7 @@ void k_inplace(SweepArgs<T> a) {
       const uint32_t e1 = act ? sld(a.rptr + (b0 + i + 1)) : 0u;
       double xo = 0.0, iw = 0.0, pu = C.inv_n;
       if (act) {
-        xo = (double)C.x[u];
+        xo = (double)C.x[b0 + i];
         iw = sld(C.inv_w + (b0 + i));
         if (!(C.flags & kFlagUniformP)) pu = sld(C.p + u);
       }
@@ -776,7 +776,7 @@ void k_inplace(SweepArgs<T> a) {
       if (act) {
         const double xn = C.tele * pu + C.d * (sum + C.dterm);
         const T xs = (T)xn;
-        C.x[u] = xs;
+        C.x[b0 + i] = xs;
         const double xd = (double)xs;
         if (iw != 0.0) {
           const T cv = (T)(xd * iw);
@@ -948,7 +948,8 @@ struct InitArgs {
   int64_t n;
   double inv_n;
   int uniform_p;
-  int raw;  // adjoint: gathered value = x for every vertex
+  int raw;         // adjoint: gathered value = x for every vertex
+  int x_at_slot;   // x stored by gpos too (the in-place form's interleaved layout)
 };
 
 template <typename T>
@@ -959,10 +960,10 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs<T> a) {
        u += (int64_t)gridDim.x * kBlock) {
     double xv = a.x_in ? a.x_in[u] : (a.uniform_p ? a.inv_n : a.p[u]);
     T xs = (T)xv;
-    a.x[u] = xs;
+    const size_t slot = a.gpos ? (size_t)a.gpos[u] : (size_t)u;  // null: vertex order
+    a.x[a.x_at_slot ? slot : (size_t)u] = xs;
     const double xd = (double)xs;
     const double iw = a.inv_w[u];
-    const size_t slot = a.gpos ? (size_t)a.gpos[u] : (size_t)u;  // null: vertex order
     if (a.raw) a.c[slot] = xs;
     else if (iw != 0.0) a.c[slot] = (T)(xd * iw);
     if (iw == 0.0) dang += xd;
@@ -1023,10 +1024,11 @@ __global__ __launch_bounds__(kFinBlock) void k_init_final(const double *part, in
 // x64[u] = x[u] * scale (FP32 or FP64 source; scale = 1/S for mass-scaled iterates)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_to64(const T *x, double *out, int64_t n,
-                                                 const SweepState *st, int scaled) {
+                                                 const SweepState *st, int scaled,
+                                                 const uint32_t *map = nullptr) {
   const double scale = scaled ? 1.0 / st->S : 1.0;
   for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kBlock)
-    out[u] = (double)x[u] * scale;
+    out[u] = (double)x[map ? (size_t)map[u] : (size_t)u] * scale;
 }
 
 constexpr int kInitGrid = 1024;
@@ -1092,6 +1094,7 @@ int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T 
                 int max_iter, T *c0 = nullptr, int raw = 0, bool vertex_order = false) {
   InitArgs<T> a;
   a.gpos = vertex_order ? P.ip_pos : P.gpos;
+  a.x_at_slot = vertex_order ? 1 : 0;
   a.inv_w = g->inv_w;
   a.p = p;
   a.x_in = x_in;
@@ -1370,6 +1373,25 @@ struct SolveBufs {
 };
 
 template <typename T>
+void bufs_of(const SolveBufs &b, T *&c0, T *&c1);
+
+// The in-place form updates one contribution array, and keeps its ranks in
+// the plan's interleaved order in the precision's second contribution buffer
+// (the caller's, or the library's once allocated).
+template <typename T>
+int inplace_x(pr_graph *g, const SolveBufs &b, T *&xs) {
+  T *c0 = nullptr, *c1 = nullptr;
+  bufs_of<T>(b, c0, c1);
+  if (!c0) {
+    int rc = ensure_contrib<T>(g);
+    if (rc) return rc;
+    c1 = contrib<T>(g, 1);
+  }
+  xs = c1;
+  return PR_OK;
+}
+
+template <typename T>
 void bufs_of(const SolveBufs &b, T *&c0, T *&c1) {
   if constexpr (sizeof(T) == 8) {
     c0 = b.c64[0];
@@ -1551,17 +1573,23 @@ int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o
   int it = 0;
   double r = INFINITY;
   double target = tol;
+  const bool ip = form == PR_INPLACE;
+  const uint32_t *map = ip ? g->fwd.ip_pos : nullptr;  // the in-place form's ranks are interleaved
   if (o.precision == PR_FP64) {
-    if ((rc = solve_stage<double>(g, d, tol, max_iter, o, p, o.warm_start ? x : nullptr, x, flags,
+    double *xs = x;
+    if (ip && (rc = inplace_x<double>(g, bufs, xs))) return rc;
+    if ((rc = solve_stage<double>(g, d, tol, max_iter, o, p, o.warm_start ? x : nullptr, xs, flags,
                                   form, trace, false, &it, &r, bufs)))
       return rc;
-    if (scaled) {
-      hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const double *)x,
-                         x, g->n, (const SweepState *)g->fwd.st, 1);
+    if (scaled || ip) {
+      hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const double *)xs,
+                         x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0, map);
     }
   } else {
     float *x32 = bufs.x32;
-    if (!x32) {
+    if (ip) {
+      if ((rc = inplace_x<float>(g, bufs, x32))) return rc;
+    } else if (!x32) {
       if (!g->x32 && (rc = fpr_dev_alloc(g, (void **)&g->x32, sizeof(float) * (size_t)g->n))) return rc;
       x32 = g->x32;
     }
@@ -1572,16 +1600,18 @@ int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o
       return rc;
     target = rtol > 0.0 ? rtol : tol32;
     hipLaunchKernelGGL(k_to64<float>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
-                       (const float *)x32, x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0);
+                       (const float *)x32, x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0, map);
     if (rtol > 0.0 && it < max_iter) {
       int it2 = 0;
       double r2 = INFINITY;
-      if ((rc = solve_stage<double>(g, d, rtol, max_iter - it, o, p, x, x, flags, form,
+      double *xs = x;
+      if (ip && (rc = inplace_x<double>(g, bufs, xs))) return rc;
+      if ((rc = solve_stage<double>(g, d, rtol, max_iter - it, o, p, x, xs, flags, form,
                                     trace ? trace + it : nullptr, false, &it2, &r2, bufs)))
         return rc;
-      if (scaled)
+      if (scaled || ip)
         hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
-                           (const double *)x, x, g->n, (const SweepState *)g->fwd.st, 1);
+                           (const double *)xs, x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0, map);
       it += it2;
       r = r2;
     }
@@ -1754,16 +1784,18 @@ int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, doubl
                  double *resid, double *elapsed_ms) {
   int rc;
   T *xs = nullptr;
-  if constexpr (sizeof(T) == 8) {
+  const bool vo = o.mode == PR_INPLACE;
+  if ((rc = ensure_contrib<T>(g))) return rc;
+  if (vo) {
+    xs = contrib<T>(g, 1);  // the in-place form's interleaved ranks
+  } else if constexpr (sizeof(T) == 8) {
     xs = x;
   } else {
     if (!g->x32 && (rc = fpr_dev_alloc(g, (void **)&g->x32, sizeof(float) * (size_t)g->n))) return rc;
     xs = g->x32;
   }
-  if ((rc = ensure_contrib<T>(g))) return rc;
   if (is_list_form(o.mode) && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
-  const bool vo = o.mode == PR_INPLACE;
   if ((rc = launch_init<T>(g, P, p, x, xs, -1.0, std::max(1, sweeps), nullptr, 0, vo))) return rc;
   const int flags = flags_of(o);
   if ((rc = set_io(g, P, xs, p))) return rc;
@@ -1777,9 +1809,9 @@ int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, doubl
   }
   if (sweeps > 0 && (rc = run_sweeps<T>(g, a, o.mode, o.use_hip_graph != 0, sweeps))) return rc;
   if (elapsed_ms) PR_HIP(hipEventRecord(e1, g->work));
-  if (sizeof(T) != 8 || (flags & kFlagScaled))
+  if (sizeof(T) != 8 || (flags & kFlagScaled) || vo)
     hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const T *)xs, x, g->n,
-                       (const SweepState *)P.st, (flags & kFlagScaled) ? 1 : 0);
+                       (const SweepState *)P.st, (flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr);
   PR_HIP(hipGetLastError());
   if ((rc = poll_state(g, P))) return rc;
   if (resid) *resid = sweeps > 0 ? g->host_st->resid : INFINITY;
@@ -1817,16 +1849,19 @@ int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps,
                  double *finalize_ms) {
   int rc;
   T *xs = nullptr;
-  if constexpr (sizeof(T) == 8) {
+  const bool vo = o.mode == PR_INPLACE;
+  if ((rc = ensure_contrib<T>(g))) return rc;
+  if (vo) {
+    xs = contrib<T>(g, 1);  // the in-place form's interleaved ranks
+  } else if constexpr (sizeof(T) == 8) {
     xs = x;
   } else {
     if (!g->x32 && (rc = fpr_dev_alloc(g, (void **)&g->x32, sizeof(float) * (size_t)g->n))) return rc;
     xs = g->x32;
   }
-  if ((rc = ensure_contrib<T>(g))) return rc;
   if (is_list_form(o.mode) && (rc = ensure_cl<T>(g))) return rc;
   DevPlan &P = g->fwd;
-  if ((rc = launch_init<T>(g, P, nullptr, x, xs, -1.0, sweeps, nullptr, 0, o.mode == PR_INPLACE))) return rc;
+  if ((rc = launch_init<T>(g, P, nullptr, x, xs, -1.0, sweeps, nullptr, 0, vo))) return rc;
   if ((rc = set_io(g, P, xs, nullptr))) return rc;
   SweepArgs<T> a = make_args<T>(g, P, nullptr, d, flags_of(o), nullptr, nullptr, nullptr, o.mode);
   prime_list<T>(g, a, o.mode);
@@ -1838,9 +1873,9 @@ int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps,
     PR_HIP(hipEventRecord(ev[3 * k + 2], g->work));
   }
   PR_HIP(hipGetLastError());
-  if (sizeof(T) != 8 || (a.flags & kFlagScaled))
+  if (sizeof(T) != 8 || (a.flags & kFlagScaled) || vo)
     hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const T *)xs, x, g->n,
-                       (const SweepState *)P.st, (a.flags & kFlagScaled) ? 1 : 0);
+                       (const SweepState *)P.st, (a.flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr);
   PR_HIP(hipStreamSynchronize(g->work));
   double ts = 0.0, tf = 0.0;
   for (int k = 0; k < sweeps; ++k) {
