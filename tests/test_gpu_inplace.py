@@ -134,3 +134,43 @@ def test_inplace_road_grid_needs_fewer_sweeps_than_jacobi():
     x, it, res, ok = g.solve(d=D, tol=1e-13, max_iter=3000, mode="inplace")
     assert ok and l1(x.cpu().numpy(), xr) <= 1e-9
     g.close()
+
+
+@pytest.mark.parametrize("kind", ["weighted", "personalized", "road"])
+def test_inplace_interleaved_blocks(kind):
+    """Graphs of several full blocks and a partial last one, so the plan's
+    interleaved layout (inside a full block, lane l's k-th vertex at
+    position 64 k + l) is exercised together with what is read by vertex: the
+    edge weights, the teleport vector and the caller's start vector.  FP64 and
+    FP32 + refinement reach the oracle's fixed point; a warm start from that
+    point converges at once; pr_iterate from 1/n, run long enough, lands on
+    it too."""
+    fpr = _fpr()
+    n, w, p = 3000, None, None
+    if kind == "road":
+        side = 61
+        src, dst = gg.road_grid(side, seed=91)
+        n = side * side
+    else:
+        src, dst = gg.random_graph(n, 6 * n, 91)
+    if kind == "weighted":
+        w = gg.weights(len(src), 92)
+    if kind == "personalized":
+        p = gg.uniforms(93, 9, n)
+        p = p / p.sum()
+    say("interleaved %s n=%d (full blocks: %d)" % (kind, n, n // 512))
+    assert n // 512 >= 5 and n % 512 != 0
+    _, xr = _ref(n, src, dst, w, p)
+    g = fpr.Graph(n, src, dst, w, plan=dict(with_inplace=1))
+    for prec in ("fp64", "fp32"):
+        x, it, res, ok = g.solve(d=D, tol=1e-13, max_iter=3000, mode="inplace", precision=prec, p=_p_dev(p))
+        say("  %s sweeps=%d L1=%.2e" % (prec, it, l1(x.cpu().numpy(), xr)))
+        assert ok and l1(x.cpu().numpy(), xr) <= 1e-9, prec
+    x0 = torch.tensor(xr, dtype=torch.float64, device="cuda")
+    x, it, res, ok = g.solve(d=D, tol=1e-11, max_iter=3000, mode="inplace", p=_p_dev(p), x=x0.clone(),
+                             warm_start=True)
+    assert ok and it <= 3 and l1(x.cpu().numpy(), xr) <= 1e-9, it
+    xi = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+    g.iterate(xi, 400, d=D, mode="inplace", p=_p_dev(p))
+    assert l1(xi.cpu().numpy(), xr) <= 1e-9
+    g.close()
