@@ -111,3 +111,14 @@ def test_graph_signature_tells_equal_sized_graphs_apart():
     assert sa == sc and sa != sb
     for g in (a, b, c):
         g.close()
+
+
+def test_pagerank_convenience_plans_every_form():
+    fpr = _fpr()
+    n = 1 << 12
+    s, t = gg.rmat(12, 8, seed=36)
+    ref = _ref(n, s, t)
+    for mode in ("jacobi", "fused", "inplace", "edge_list", "fused_edge_list"):
+        for prec in ("fp64", "fp32"):
+            x, it = fpr.pagerank(n, s, t, tol=1e-12, mode=mode, precision=prec)
+            assert l1(x.cpu().numpy(), ref) <= 1e-9, (mode, prec)
