@@ -57,6 +57,23 @@ def test_noalloc_matches_pr_solve_on_two_calls_in_a_row():
         g.close()
 
 
+@pytest.mark.timeout(300)
+def test_noalloc_inplace_form_reaches_the_fixed_point():
+    """The in-place form keeps its interleaved ranks in the scratch's second
+    contribution buffer; it is asynchronous, so the check is the oracle's fixed
+    point (not the bits of pr_solve), again on two calls in a row."""
+    fpr = _fpr()
+    for scale, seed in ((17, 44), (12, 45)):
+        n, s, t, xr = _case(scale, seed)
+        g = fpr.Graph(n, s, t, plan=dict(with_inplace=1))
+        for prec in ("fp64", "fp32"):
+            x, it, r, ok = g.solve(d=D, tol=1e-12, max_iter=1000, mode="inplace", precision=prec, no_alloc=True)
+            print("n=%d inplace %s: sweeps %d, L1 vs oracle %.2e" % (n, prec, it, l1(x.cpu().numpy(), xr)),
+                  flush=True)
+            assert ok and l1(x.cpu().numpy(), xr) <= 1e-9, (scale, prec)
+        g.close()
+
+
 def test_noalloc_refuses_what_it_cannot_hold():
     fpr = _fpr()
     from paper_2203_09284_amd._lib import FusedPRError
