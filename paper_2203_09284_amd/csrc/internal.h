@@ -41,7 +41,7 @@ constexpr int kHotBytes = FPR_HOT_KB * 1024;  // LDS holding the hottest gather 
 constexpr int kHotLayout = kHotBytes / 4;     // slots kept in gather-count order by gather_layout 2
 constexpr int64_t kLocalSpan = 1024;          // id distance under which an in-edge counts as local
 #ifndef FPR_IP_RUN
-#define FPR_IP_RUN 8
+#define FPR_IP_RUN 4
 #endif
 // In-place form: a wavefront's block of 64 * kIpRun vertices is updated in
 // kIpRun steps, lane l taking its run of consecutive vertices l * kIpRun + k
@@ -148,6 +148,7 @@ struct DevPlan {
   double *ip_w = nullptr;         // [m] weights (weighted graphs)
   uint32_t *ip_pos = nullptr;     // [n] position of each vertex
   double *ip_iw = nullptr;        // [n] 1/W in position order
+  int32_t *ip_range = nullptr;    // [W+1] first block of each sweep wavefront (equal cost)
   std::vector<int64_t> cl_group;  // [n_blocks + 2] first scatter entry of each group: sources
                                   // updated by block b's launch, then by the finalize kernel
   std::vector<uint8_t> upd_launch;  // host, during planning: the launch that updates each vertex

@@ -719,6 +719,26 @@ static int create_impl(const pr_csr *csr, const pr_plan_opts *opts, int mem_mode
       if (csr->in_w && (rc2 = upload(g, &g->fwd.ip_w, iwt.data(), iwt.size()))) return rc2;
       if ((rc2 = upload(g, &g->fwd.ip_pos, pos.data(), pos.size()))) return rc2;
       if ((rc2 = upload(g, &g->fwd.ip_iw, iiw.data(), iiw.size()))) return rc2;
+      // each sweep wavefront takes a contiguous range of blocks of about equal
+      // cost (in-edges, plus two per vertex for the update), in ascending order
+      {
+        const int64_t nblocks = (n + kIpVpb - 1) / kIpVpb;
+        const int64_t W = (int64_t)g->grid * kSweepWaves;
+        std::vector<double> cum(nblocks + 1, 0.0);
+        for (int64_t b = 0; b < nblocks; ++b) {
+          const int64_t lo = b * kIpVpb, hi = std::min<int64_t>(n, lo + kIpVpb);
+          cum[b + 1] = cum[b] + (double)(ip[hi] - ip[lo]) + 2.0 * (double)(hi - lo);
+        }
+        std::vector<int32_t> range(W + 1);
+        int64_t b = 0;
+        for (int64_t w2 = 0; w2 <= W; ++w2) {
+          const double target = cum[nblocks] * (double)w2 / (double)W;
+          while (b < nblocks && cum[b] < target) ++b;
+          range[w2] = (int32_t)b;
+        }
+        range[W] = (int32_t)nblocks;
+        if ((rc2 = upload(g, &g->fwd.ip_range, range.data(), range.size()))) return rc2;
+      }
     }
     if (o.with_adjoint) {
       if ((rc2 = build_plan(g, g->adj, n, csr->out_ptr, csr->out_dst, csr->out_w, o, false))) return rc2;

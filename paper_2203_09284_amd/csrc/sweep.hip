@@ -129,6 +129,7 @@ struct SweepArgs {
   int part_stride;  // SoA stride of the three partial rows
   int n_part;       // partial slots the finalize kernel sums
   int fresh_lo, fresh_hi;  // slots rewritten by earlier blocks of this sweep (fused form)
+  const int32_t *ip_range;  // in-place form: first block of each wavefront, [W+1]
 };
 
 template <typename T>
@@ -640,8 +641,10 @@ void k_sweep(SweepArgs<T> a) {
 
 // The in-place form (Algorithm 2 / Eq. 9 swept in place, Section 4.3's
 // asynchronous blocks).  The contributions live in one array c, read and
-// written during the sweep.  Wavefront w takes the blocks w, w + W, ... of
-// kIpVpb consecutive vertices; for each block it copies the block's
+// written during the sweep.  Wavefront w takes a contiguous range of the
+// blocks of kIpVpb consecutive vertices, in ascending order (a source a few
+// blocks below its row is then mostly updated already, by this wavefront or
+// the one before); for each block it copies the block's
 // contributions into its own LDS slice, then updates the block in kIpRun
 // steps: in step k lane l updates vertex l * kIpRun + k of the block, so each
 // lane walks its own run of consecutive vertices in order.  The plan stores
@@ -693,8 +696,14 @@ void k_inplace(SweepArgs<T> a) {
   T *blk = blk_all[wave];
   const int64_t W = (int64_t)gridDim.x * kSweepWaves;
   const int64_t nblocks = (a.nv + VPB - 1) / VPB;
+  // each wavefront takes its contiguous range of blocks (the plan cuts them
+  // at equal cost), in ascending order: the blocks just below a block's range
+  // belong to the wavefront before, and are mostly done by the time they are
+  // read
+  const int64_t gw = (int64_t)blockIdx.x * kSweepWaves + wave;
+  const int64_t bend = gw < W ? min(nblocks, (int64_t)a.ip_range[gw + 1]) : 0;
   Red red;
-  for (int64_t b = (int64_t)blockIdx.x * kSweepWaves + wave; b < nblocks; b += W) {
+  for (int64_t b = gw < W ? a.ip_range[gw] : 0; b < bend; ++b) {
     const int64_t b0 = b * VPB;
     const int nb = (int)min((int64_t)VPB, a.nv - b0);
     {
@@ -1185,6 +1194,7 @@ SweepArgs<T> make_args(pr_graph *g, DevPlan &P, const double *p, double d, int f
     a.idx = P.ip_src;
     a.w = P.ip_w;
     a.inv_w = P.ip_iw;
+    a.ip_range = P.ip_range;
     a.c1 = a.c0;
     a.n_msplit = 0;
     a.hot = 0;
