@@ -221,8 +221,9 @@ typedef struct pr_opts {
                             contiguous row sums; needs a graph planned with with_cl; same
                             values, same summation order, same results as PR_JACOBI), or
                             PR_INPLACE (Algorithm 2 / Eq. 9 swept in place: each wavefront
-                            stages a block of consecutive vertices' contributions in LDS
-                            and updates the block in order, each lane walking its own run
+                            sweeps a contiguous range of blocks of consecutive vertices in
+                            ascending order, stages a block's contributions in LDS and
+                            updates the block in order, each lane walking its own run
                             of consecutive vertices, so a source inside the block that is
                             already updated is read fresh; the blocks run asynchronously,
                             reading the other blocks' contributions from one shared array
