@@ -15,7 +15,8 @@ The same JSON line carries, on the same GPU:
               contributionList form of Algorithm 1 (scatter, then contiguous row
               sums), each with the oracle's certificate on its error;
   roofline    of the dominant kernel, the fused FP64 sweep at scale 24 (the
-              FP32 sweep's beside it);
+              FP32 sweep's beside it), with the device time of the sweep's
+              memory gathers alone beside it (gather_probe);
   cpu_baseline the FP64 CPU oracle timed on the host cores: one application of
               Eq. 1 over the same scale-24 edge list (one Jacobi sweep);
   rmat20      R-MAT scale 20 (permuted ids; its working set fits the Infinity
@@ -373,6 +374,16 @@ def headline_rmat24(torch, fpr, oracle, steps, warmup, cores, cpu_baseline):
             ("fused-fp64", "jacobi-fp64", "fused-fp32", "jacobi-fp32", "inplace-fp32")}
     for name, (ks, kf) in kern.items():
         log("rmat24 %-12s sweep kernel %.1f us + finalize %.1f us per sweep" % (name, ks, kf))
+    # the sweep's memory gathers alone (every in-edge's slot past the LDS copy,
+    # nothing else), the floor of a sweep whose reads land on random lines; and
+    # as many uniformly random slots, the device's rate for uncached lines
+    floor = {p: g.probe_gathers(p, "graph")[0] for p in ("fp64", "fp32")}
+    uni_us = g.probe_gathers("fp64", "uniform")[0]
+    gather_probe = dict(fp64_us=round(floor["fp64"], 1), fp32_us=round(floor["fp32"], 1),
+                        uniform_fp64_us=round(uni_us, 1), uniform_g_gathers_s=sig(m / (uni_us * 1e-6) / 1e9),
+                        uniform_line_fill_tbs=sig(m * 128 / (uni_us * 1e-6) / 1e12))
+    log("rmat24 gathers alone: FP64 %.1f us, FP32 %.1f us per sweep; %d uniform FP64 gathers %.1f us"
+        % (floor["fp64"], floor["fp32"], m, uni_us))
     cpu = None
     if cpu_baseline:
         # the oracle as it stands, on a bounded sample of this workload: one
@@ -398,7 +409,7 @@ def headline_rmat24(torch, fpr, oracle, steps, warmup, cores, cpu_baseline):
             (cpu["value"], cores, cpu["single_thread_gteps"]))
     g.close()
     return dict(n=n, m=m, setup_s=setup_s, gs_blocks=st["gs_blocks"], forms=forms, kern=kern, cpu=cpu,
-                tol_1e7=c5_out)
+                tol_1e7=c5_out, gather_probe=gather_probe)
 
 
 def leg_rmat20(torch, fpr, oracle, steps, warmup, cores, args):
@@ -722,6 +733,7 @@ def main():
         "roofline_fp32": roofline(b32 / (k32 * 1e-6) / 1e9, traffic_record("fused_fp32_rmat24"),
                                   "k_sweep<float, fused>", b32, k32, h["gs_blocks"], b32 + 4 * m),
         "cpu_baseline": h["cpu"],
+        "gather_probe": h["gather_probe"],
         "forms": {k: rounded(f) for k, f in forms.items()},
         "kernel_us": {k: {"sweep": round(v[0], 2), "finalize": round(v[1], 2)} for k, v in kern.items()},
         "speedup_vs_jacobi_fp64_time_to_tol": {
@@ -729,6 +741,11 @@ def main():
         "tol_1e-7": h["tol_1e7"],
         "setup_s": round(h["setup_s"], 2),
     }
+    # the sweep against its own gathers' floor on this device
+    out["roofline"]["gather_floor_us"] = h["gather_probe"]["fp64_us"]
+    out["roofline"]["vs_gather_floor"] = round(h["gather_probe"]["fp64_us"] / k64, 3)
+    out["roofline_fp32"]["gather_floor_us"] = h["gather_probe"]["fp32_us"]
+    out["roofline_fp32"]["vs_gather_floor"] = round(h["gather_probe"]["fp32_us"] / k32, 3)
     out.update(extra)
     print(json.dumps(out), flush=True)
 

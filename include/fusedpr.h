@@ -343,6 +343,26 @@ int pr_profile_sweeps(pr_graph *g, double d, const pr_opts *o, double *x, int sw
 int pr_certificate(pr_graph *g, double d, const double *p, const double *x, double *result,
                    void *stream);
 
+/* Device time of the sweep's memory gathers alone: a kernel on the sweep's
+ * grid that reads, from an n-element array of the precision's type (FP64 8
+ * bytes, FP32 4 bytes, allocated and freed by the call), the value at every
+ * in-edge's gather slot in the plan's bin order, skipping the slots the sweep
+ * keeps in its LDS copy, eight loads in flight per lane, and sums them
+ * (mode 0); or as many slots drawn uniformly from [0, n) by a counter-based
+ * SplitMix64 mix of the edge index (mode 1: random lines that no cache holds).
+ * Nothing else is read or written.  The gathers are the reads of Eq. 1's sum;
+ * on a graph without id locality their rate, not HBM's streaming rate, bounds
+ * the sweep, so this is the sweep's floor on the device it runs on.
+ *   precision      PR_FP64 or PR_FP32
+ *   reps           timed launches after one untimed launch, 1..1000
+ *   best_us        host: fastest launch in microseconds
+ *   mean_us        host, nullable: their mean
+ * Measurement support; PR_EINVAL on bad arguments or a graph on another
+ * device, PR_ENOMEM when the array does not fit, PR_EDEVICE on a HIP error.
+ * The call waits for its launches. */
+int pr_probe_gathers(pr_graph *g, int precision, int mode, int reps, double *best_us, double *mean_us,
+                     void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched personalized PageRank: k teleport vectors, each one-hot on
  * seeds[j] (Eq. 1 with a personalised teleport term), solved together as a

@@ -85,6 +85,7 @@ SIGNATURES = {
     "pr_certificate": (ctypes.c_int, [vp, ctypes.c_double, vp, vp, c_f64p, vp]),
     "pr_profile_sweeps": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(PrOpts), vp, ctypes.c_int, c_f64p,
                                          c_f64p, vp]),
+    "pr_probe_gathers": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, c_f64p, c_f64p, vp]),
     "pr_batch_shape_default": (None, [ctypes.POINTER(PrBatchShape)]),
     "pr_solve_batched": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
                                         ctypes.POINTER(PrBatchShape), vp, ctypes.POINTER(ctypes.c_int), c_f64p, vp]),

@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfusedpr.so")
 ARCH = "gfx950"
 
-SOURCES = ["error.cpp", "csr_build.cpp", "plan.hip", "sweep.hip", "batched.hip", "adjoint.hip"]
+SOURCES = ["error.cpp", "csr_build.cpp", "plan.hip", "sweep.hip", "batched.hip", "adjoint.hip", "probe.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -251,6 +251,20 @@ class Graph:
         L.check(rc, library=self._lib)
         return a.value, b.value
 
+    def probe_gathers(self, precision: str = "fp64", mode: str = "graph", reps: int = 5, stream=None):
+        """pr_probe_gathers: device microseconds of the sweep's memory gathers
+        alone (mode "graph": this plan's in-edge slots past the LDS copy;
+        "uniform": as many uniformly random slots), (best, mean)."""
+        modes = {"graph": 0, "uniform": 1}
+        if precision not in PRECISIONS or mode not in modes:
+            raise ValueError("precision must be one of %s and mode one of %s" % (sorted(PRECISIONS), sorted(modes)))
+        best = ctypes.c_double(0.0)
+        mean = ctypes.c_double(0.0)
+        rc = self._lib.pr_probe_gathers(self._h, PRECISIONS[precision], modes[mode], int(reps), ctypes.byref(best),
+                                        ctypes.byref(mean), _stream_ptr(stream))
+        L.check(rc, library=self._lib)
+        return best.value, mean.value
+
     def certificate(self, x: torch.Tensor, d: float = 0.85, p: torch.Tensor | None = None,
                     stream=None) -> float:
         """||F(x) - x||_1, computed on the GPU; ||x - x*||_1 <= this / (1 - d)."""

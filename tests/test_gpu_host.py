@@ -122,3 +122,32 @@ def test_pagerank_convenience_plans_every_form():
         for prec in ("fp64", "fp32"):
             x, it = fpr.pagerank(n, s, t, tol=1e-12, mode=mode, precision=prec)
             assert l1(x.cpu().numpy(), ref) <= 1e-9, (mode, prec)
+
+
+def test_gather_probe_times_and_validates():
+    """pr_probe_gathers (measurement support): positive, ordered times for both
+    precisions and both slot streams, and PR_EINVAL for bad arguments."""
+    import ctypes
+    from paper_2203_09284_amd import _lib as L
+    fpr = _fpr()
+    n = 1 << 14
+    s, t = gg.rmat(14, 16, seed=33)
+    g = fpr.Graph(n, s, t)
+    try:
+        for prec in ("fp64", "fp32"):
+            for mode in ("graph", "uniform"):
+                best, mean = g.probe_gathers(prec, mode, reps=3)
+                assert 0.0 < best <= mean * (1 + 1e-9) < 1e6, (prec, mode, best, mean)
+        with pytest.raises(ValueError):
+            g.probe_gathers("fp16")
+        lib = L.lib()
+        out = ctypes.c_double(0.0)
+        for prec, mode, reps in ((7, 0, 3), (L.PR_FP64, 2, 3), (L.PR_FP64, 0, 0), (L.PR_FP32, 1, 1001)):
+            rc = lib.pr_probe_gathers(g._h, prec, mode, reps, ctypes.byref(out), None, None)
+            assert rc == L.PR_EINVAL, (prec, mode, reps, rc)
+        assert lib.pr_probe_gathers(g._h, L.PR_FP64, 0, 1, None, None, None) == L.PR_EINVAL
+        # the graph still solves to the oracle's fixed point afterwards
+        x, _, _, ok = g.solve(d=D, tol=1e-12, max_iter=1000, mode="fused")
+        assert ok and l1(x.cpu().numpy(), _ref(n, s, t)) <= 1e-9
+    finally:
+        g.close()
