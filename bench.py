@@ -32,7 +32,8 @@ The same JSON line carries, on the same GPU:
     python bench.py [--steps K] [--warmup W] [--quick]
     python bench.py --profile FORM [--workload rmat20|rmat24]   (kernel-only driver
         for rocprofv3: sweeps of one form, or one k = 64 batched solve with
-        FORM = batched, then a reference copy kernel)
+        FORM = batched, or the sweep's gathers alone with FORM = probe-fp64|fp32,
+        then a reference copy kernel)
     python bench.py --pmc-summary KEY FETCH_CSV WRITE_CSV DRIVER_LOG  (counter runs of
         that driver -> HBM bytes per sweep, into profiles/traffic.json)
     python bench.py --study [WORKLOAD ...]   (convergence study: thresholds 1e-6..1e-15,
@@ -58,6 +59,7 @@ D = 0.85
 # the kernels and the plan that shapes their launches
 KERNEL_SOURCES = ("sweep.hip", "plan.hip", "device_common.h", "internal.h")
 BATCHED_SOURCES = ("batched.hip", "plan.hip", "device_common.h", "internal.h")
+PROBE_SOURCES = ("probe.hip", "plan.hip", "device_common.h", "internal.h")
 COPY_BYTES = 256 << 20  # the reference copy kernel reads and writes this many bytes
 
 
@@ -380,6 +382,8 @@ def headline_rmat24(torch, fpr, oracle, steps, warmup, cores, cpu_baseline):
     floor = {p: g.probe_gathers(p, "graph")[0] for p in ("fp64", "fp32")}
     uni_us = g.probe_gathers("fp64", "uniform")[0]
     gather_probe = dict(fp64_us=round(floor["fp64"], 1), fp32_us=round(floor["fp32"], 1),
+                        fp64_traffic=traffic_record("probe_fp64_rmat24", PROBE_SOURCES),
+                        fp32_traffic=traffic_record("probe_fp32_rmat24", PROBE_SOURCES),
                         uniform_fp64_us=round(uni_us, 1), uniform_g_gathers_s=sig(m / (uni_us * 1e-6) / 1e9),
                         uniform_line_fill_tbs=sig(m * 128 / (uni_us * 1e-6) / 1e12))
     log("rmat24 gathers alone: FP64 %.1f us, FP32 %.1f us per sweep; %d uniform FP64 gathers %.1f us"
@@ -516,6 +520,25 @@ def profile_driver(args):
                           "source_sha": kernel_source_sha(BATCHED_SOURCES)}), flush=True)
         g.close()
         return
+    if args.profile.startswith("probe-"):
+        # the sweep's memory gathers alone (pr_probe_gathers, this plan's slots):
+        # one untimed and `sweeps` timed launches, each one sweep's gathers
+        prec = args.profile.split("-")[1]
+        g = fpr.Graph(w["n"], w["src"], w["dst"])
+        best, mean = g.probe_gathers(prec, "graph", reps=args.profile_sweeps)
+        torch.cuda.synchronize()
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": args.profile, "workload": args.workload, "n": g.n, "m": g.m,
+                          "sweeps": args.profile_sweeps + 1, "best_us": best, "mean_us": mean,
+                          "copy_bytes": COPY_BYTES, "b_alg": b_alg(g.n, g.m, 8 if prec == "fp64" else 4),
+                          "source_sha": kernel_source_sha(PROBE_SOURCES)}),
+              flush=True)
+        g.close()
+        return
     mode, prec = args.profile.split("-")[:2]
     g = fpr.Graph(w["n"], w["src"], w["dst"], plan=dict(with_cl=1 if "edge_list" in mode else 0,
                                                         with_inplace=1 if mode == "inplace" else 0))
@@ -602,7 +625,8 @@ def pmc_summary(args):
     key, fetch_csv, write_csv, driver_log = args.pmc_summary
     drv = json.loads([ln for ln in open(driver_log) if ln.startswith('{"profile"')][-1])
     kname = ("k_vsweep<" if drv["profile"] == "batched" else
-             "k_inplace<" if drv["profile"].startswith("inplace") else "k_sweep<")
+             "k_inplace<" if drv["profile"].startswith("inplace") else
+             "k_probe_gather<" if drv["profile"].startswith("probe") else "k_sweep<")
 
     def read(path, counter):
         sweep, copy = [], []
@@ -647,7 +671,8 @@ def main():
     ap.add_argument("--only", default=None, metavar="LEGS",
                     help="comma-separated legs to run alone (rmat20,er10k,adjoint,road8m), without the "
                          "headline: a quick measurement, not the benchmark line")
-    ap.add_argument("--profile", default=None, help="{jacobi,fused,edge_list}-{fp64,fp32} | batched")
+    ap.add_argument("--profile", default=None,
+                    help="{jacobi,fused,edge_list,inplace}-{fp64,fp32} | batched | probe-{fp64,fp32}")
     ap.add_argument("--profile-sweeps", type=int, default=20)
     ap.add_argument("--workload", default="rmat24")
     ap.add_argument("--scales", nargs="*", type=int, default=None, metavar="SCALE",
