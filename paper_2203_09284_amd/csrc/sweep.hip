@@ -731,8 +731,14 @@ void k_inplace(SweepArgs<T> a) {
       const uint32_t e1 = act ? sld(a.rptr + (b0 + i + 1)) : 0u;
       double xo = 0.0, iw = 0.0, pu = C.inv_n;
       if (act) {
-        xo = (double)C.x[b0 + i];
         iw = sld(C.inv_w + (b0 + i));
+        if constexpr (sizeof(T) == 8) {
+          // the rank from the contribution staged in LDS (c = x / W), or the
+          // slot itself for a dangling vertex
+          xo = iw != 0.0 ? (double)blk[i] / iw : (double)blk[i];
+        } else {
+          xo = (double)C.x[b0 + i];
+        }
         if (!(C.flags & kFlagUniformP)) pu = sld(C.p + u);
       }
       const uint32_t L = act ? e1 - e0 : 0u;
@@ -784,13 +790,14 @@ void k_inplace(SweepArgs<T> a) {
       if (act) {
         const double xn = C.tele * pu + C.d * (sum + C.dterm);
         const T xs = (T)xn;
-        C.x[b0 + i] = xs;
+        if constexpr (sizeof(T) != 8) C.x[b0 + i] = xs;
         const double xd = (double)xs;
         if (iw != 0.0) {
           const T cv = (T)(xd * iw);
           blk[i] = cv;
           c[b0 + i] = cv;
         } else {
+          if constexpr (sizeof(T) == 8) c[b0 + i] = xs;  // never gathered: holds the rank
           red.dang += xd;
         }
         red.chg += fabs(xd - xo);
@@ -958,6 +965,7 @@ struct InitArgs {
   int uniform_p;
   int raw;         // adjoint: gathered value = x for every vertex
   int x_at_slot;   // x stored by gpos too (the in-place form's interleaved layout)
+  int dangling_x;  // in-place FP64: a dangling vertex's slot of c holds its rank
 };
 
 template <typename T>
@@ -974,6 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs<T> a) {
     const double iw = a.inv_w[u];
     if (a.raw) a.c[slot] = xs;
     else if (iw != 0.0) a.c[slot] = (T)(xd * iw);
+    else if (a.dangling_x) a.c[slot] = xs;
     if (iw == 0.0) dang += xd;
     tot += xd;
   }
@@ -1029,14 +1038,21 @@ __global__ __launch_bounds__(kFinBlock) void k_init_final(const double *part, in
   st->raw = INFINITY;
 }
 
-// x64[u] = x[u] * scale (FP32 or FP64 source; scale = 1/S for mass-scaled iterates)
+// x64[u] = x[u] * scale (FP32 or FP64 source; scale = 1/S for mass-scaled
+// iterates), x read at map[u] when a map is given.  With iw (the in-place FP64
+// form, whose source is its contribution array): the rank is the contribution
+// divided by 1/W, or the slot itself for a dangling vertex (iw = 0).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_to64(const T *x, double *out, int64_t n,
                                                  const SweepState *st, int scaled,
-                                                 const uint32_t *map = nullptr) {
+                                                 const uint32_t *map = nullptr, const double *iw = nullptr) {
   const double scale = scaled ? 1.0 / st->S : 1.0;
-  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kBlock)
-    out[u] = (double)x[map ? (size_t)map[u] : (size_t)u] * scale;
+  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kBlock) {
+    const size_t at = map ? (size_t)map[u] : (size_t)u;
+    double v = (double)x[at];
+    if (iw && iw[at] != 0.0) v /= iw[at];
+    out[u] = v * scale;
+  }
 }
 
 constexpr int kInitGrid = 1024;
@@ -1103,6 +1119,7 @@ int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T 
   InitArgs<T> a;
   a.gpos = vertex_order ? P.ip_pos : P.gpos;
   a.x_at_slot = vertex_order ? 1 : 0;
+  a.dangling_x = vertex_order && sizeof(T) == 8 ? 1 : 0;
   a.inv_w = g->inv_w;
   a.p = p;
   a.x_in = x_in;
@@ -1384,9 +1401,11 @@ struct SolveBufs {
 template <typename T>
 void bufs_of(const SolveBufs &b, T *&c0, T *&c1);
 
-// The in-place form updates one contribution array, and keeps its ranks in
-// the plan's interleaved order in the precision's second contribution buffer
-// (the caller's, or the library's once allocated).
+// The in-place form updates one contribution array.  In FP32 it keeps its
+// ranks in the plan's interleaved order in the precision's second
+// contribution buffer (the caller's, or the library's once allocated); in
+// FP64 it keeps none (the kernel reads a rank back from its contribution),
+// and that buffer only receives the start vector.
 template <typename T>
 int inplace_x(pr_graph *g, const SolveBufs &b, T *&xs) {
   T *c0 = nullptr, *c1 = nullptr;
@@ -1398,6 +1417,14 @@ int inplace_x(pr_graph *g, const SolveBufs &b, T *&xs) {
   }
   xs = c1;
   return PR_OK;
+}
+
+// Where the in-place FP64 form's final ranks are read from: its contribution
+// array (the caller's, or the library's), divided back by 1/W.
+const double *inplace_c64(pr_graph *g, const SolveBufs &b) {
+  double *c0 = nullptr, *c1 = nullptr;
+  bufs_of<double>(b, c0, c1);
+  return c0 ? c0 : g->c64[0];
 }
 
 template <typename T>
@@ -1591,8 +1618,9 @@ int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o
                                   form, trace, false, &it, &r, bufs)))
       return rc;
     if (scaled || ip) {
-      hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const double *)xs,
-                         x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0, map);
+      hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
+                         ip ? inplace_c64(g, bufs) : (const double *)xs, x, g->n, (const SweepState *)g->fwd.st,
+                         scaled ? 1 : 0, map, ip ? (const double *)g->fwd.ip_iw : nullptr);
     }
   } else {
     float *x32 = bufs.x32;
@@ -1620,7 +1648,9 @@ int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o
         return rc;
       if (scaled || ip)
         hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
-                           (const double *)xs, x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0, map);
+                           ip ? inplace_c64(g, bufs) : (const double *)xs, x, g->n,
+                           (const SweepState *)g->fwd.st, scaled ? 1 : 0, map,
+                           ip ? (const double *)g->fwd.ip_iw : nullptr);
       it += it2;
       r = r2;
     }
@@ -1818,9 +1848,14 @@ int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, doubl
   }
   if (sweeps > 0 && (rc = run_sweeps<T>(g, a, o.mode, o.use_hip_graph != 0, sweeps))) return rc;
   if (elapsed_ms) PR_HIP(hipEventRecord(e1, g->work));
-  if (sizeof(T) != 8 || (flags & kFlagScaled) || vo)
-    hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const T *)xs, x, g->n,
-                       (const SweepState *)P.st, (flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr);
+  if (sizeof(T) != 8 || (flags & kFlagScaled) || vo) {
+    // the in-place FP64 form reads its ranks back from its contributions
+    const bool from_c = vo && sizeof(T) == 8;
+    hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
+                       from_c ? (const T *)contrib<T>(g, 0) : (const T *)xs, x, g->n, (const SweepState *)P.st,
+                       (flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr,
+                       from_c ? (const double *)P.ip_iw : nullptr);
+  }
   PR_HIP(hipGetLastError());
   if ((rc = poll_state(g, P))) return rc;
   if (resid) *resid = sweeps > 0 ? g->host_st->resid : INFINITY;
@@ -1882,9 +1917,13 @@ int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps,
     PR_HIP(hipEventRecord(ev[3 * k + 2], g->work));
   }
   PR_HIP(hipGetLastError());
-  if (sizeof(T) != 8 || (a.flags & kFlagScaled) || vo)
-    hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work, (const T *)xs, x, g->n,
-                       (const SweepState *)P.st, (a.flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr);
+  if (sizeof(T) != 8 || (a.flags & kFlagScaled) || vo) {
+    const bool from_c = vo && sizeof(T) == 8;
+    hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
+                       from_c ? (const T *)contrib<T>(g, 0) : (const T *)xs, x, g->n, (const SweepState *)P.st,
+                       (a.flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr,
+                       from_c ? (const double *)P.ip_iw : nullptr);
+  }
   PR_HIP(hipStreamSynchronize(g->work));
   double ts = 0.0, tf = 0.0;
   for (int k = 0; k < sweeps; ++k) {
