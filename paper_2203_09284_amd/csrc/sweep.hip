@@ -650,7 +650,9 @@ void k_sweep(SweepArgs<T> a) {
 // lane walks its own run of consecutive vertices in order.  The plan stores
 // the block interleaved (that vertex at position 64 k + l, in c and in every
 // per-position array), so the 64 lanes of a step read and write consecutive
-// positions; only the caller's x (and p) are read and written by vertex.
+// positions; only p is read by vertex.  There is no rank array: a vertex's
+// slot of c holds x / W, or x itself for a dangling vertex (never gathered),
+// and the ranks are read back from c after the last sweep.
 // A source inside the block is read from LDS, where it already holds this
 // sweep's value once its lane has passed it (the earlier vertices of every
 // run); a source outside the block is read from c as it stands, this sweep's
@@ -663,7 +665,8 @@ void k_sweep(SweepArgs<T> a) {
 // striding the list.
 // The update is Eq. 1 with the lagged dangling mass and, with kFlagScaled,
 // the mass-scaled teleport of the fused form; the new contribution goes to
-// LDS and to c.  Reductions as in k_sweep (one partial per workgroup).
+// LDS and to c, and the change |x' - x| is read off c.  Reductions as in
+// k_sweep (one partial per workgroup).
 constexpr int kIpShort = 32;  // longest row a single lane sums
 
 // Edge e's value for the in-place form (ok: e is an edge of the row; a lane
@@ -729,16 +732,9 @@ void k_inplace(SweepArgs<T> a) {
       // update operands, independent of the sums
       const uint32_t e0 = act ? sld(a.rptr + (b0 + i)) : 0u;
       const uint32_t e1 = act ? sld(a.rptr + (b0 + i + 1)) : 0u;
-      double xo = 0.0, iw = 0.0, pu = C.inv_n;
+      double iw = 0.0, pu = C.inv_n;
       if (act) {
         iw = sld(C.inv_w + (b0 + i));
-        if constexpr (sizeof(T) == 8) {
-          // the rank from the contribution staged in LDS (c = x / W), or the
-          // slot itself for a dangling vertex
-          xo = iw != 0.0 ? (double)blk[i] / iw : (double)blk[i];
-        } else {
-          xo = (double)C.x[b0 + i];
-        }
         if (!(C.flags & kFlagUniformP)) pu = sld(C.p + u);
       }
       const uint32_t L = act ? e1 - e0 : 0u;
@@ -788,19 +784,24 @@ void k_inplace(SweepArgs<T> a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (act) {
+        // no rank array: the slot of c holds x / W, or x itself for a
+        // dangling vertex (never gathered), and the change is read off c
+        // (the previous value is the block's LDS copy): |x' - x| =
+        // |c' - c| / (1/W), exactly 0 once c stops changing
         const double xn = C.tele * pu + C.d * (sum + C.dterm);
         const T xs = (T)xn;
-        if constexpr (sizeof(T) != 8) C.x[b0 + i] = xs;
         const double xd = (double)xs;
+        const double co = (double)blk[i];
         if (iw != 0.0) {
           const T cv = (T)(xd * iw);
           blk[i] = cv;
           c[b0 + i] = cv;
+          red.chg += fabs((double)cv - co) / iw;
         } else {
-          if constexpr (sizeof(T) == 8) c[b0 + i] = xs;  // never gathered: holds the rank
+          c[b0 + i] = xs;
           red.dang += xd;
+          red.chg += fabs(xd - co);
         }
-        red.chg += fabs(xd - xo);
         red.tot += xd;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -965,7 +966,7 @@ struct InitArgs {
   int uniform_p;
   int raw;         // adjoint: gathered value = x for every vertex
   int x_at_slot;   // x stored by gpos too (the in-place form's interleaved layout)
-  int dangling_x;  // in-place FP64: a dangling vertex's slot of c holds its rank
+  int dangling_x;  // in-place form: a dangling vertex's slot of c holds its rank
 };
 
 template <typename T>
@@ -1119,7 +1120,7 @@ int launch_init(pr_graph *g, DevPlan &P, const double *p, const double *x_in, T 
   InitArgs<T> a;
   a.gpos = vertex_order ? P.ip_pos : P.gpos;
   a.x_at_slot = vertex_order ? 1 : 0;
-  a.dangling_x = vertex_order && sizeof(T) == 8 ? 1 : 0;
+  a.dangling_x = vertex_order ? 1 : 0;
   a.inv_w = g->inv_w;
   a.p = p;
   a.x_in = x_in;
@@ -1401,11 +1402,11 @@ struct SolveBufs {
 template <typename T>
 void bufs_of(const SolveBufs &b, T *&c0, T *&c1);
 
-// The in-place form updates one contribution array.  In FP32 it keeps its
-// ranks in the plan's interleaved order in the precision's second
-// contribution buffer (the caller's, or the library's once allocated); in
-// FP64 it keeps none (the kernel reads a rank back from its contribution),
-// and that buffer only receives the start vector.
+// The in-place form updates one contribution array and keeps no rank array
+// (the kernel reads a rank back from its contribution); the precision's
+// second contribution buffer (the caller's, or the library's once
+// allocated) only receives the start vector, in the plan's interleaved
+// order.
 template <typename T>
 int inplace_x(pr_graph *g, const SolveBufs &b, T *&xs) {
   T *c0 = nullptr, *c1 = nullptr;
@@ -1419,12 +1420,13 @@ int inplace_x(pr_graph *g, const SolveBufs &b, T *&xs) {
   return PR_OK;
 }
 
-// Where the in-place FP64 form's final ranks are read from: its contribution
+// Where the in-place form's final ranks are read from: its contribution
 // array (the caller's, or the library's), divided back by 1/W.
-const double *inplace_c64(pr_graph *g, const SolveBufs &b) {
-  double *c0 = nullptr, *c1 = nullptr;
-  bufs_of<double>(b, c0, c1);
-  return c0 ? c0 : g->c64[0];
+template <typename T>
+const T *inplace_c(pr_graph *g, const SolveBufs &b) {
+  T *c0 = nullptr, *c1 = nullptr;
+  bufs_of<T>(b, c0, c1);
+  return c0 ? c0 : contrib<T>(g, 0);
 }
 
 template <typename T>
@@ -1619,7 +1621,7 @@ int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o
       return rc;
     if (scaled || ip) {
       hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
-                         ip ? inplace_c64(g, bufs) : (const double *)xs, x, g->n, (const SweepState *)g->fwd.st,
+                         ip ? inplace_c<double>(g, bufs) : (const double *)xs, x, g->n, (const SweepState *)g->fwd.st,
                          scaled ? 1 : 0, map, ip ? (const double *)g->fwd.ip_iw : nullptr);
     }
   } else {
@@ -1637,7 +1639,8 @@ int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o
       return rc;
     target = rtol > 0.0 ? rtol : tol32;
     hipLaunchKernelGGL(k_to64<float>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
-                       (const float *)x32, x, g->n, (const SweepState *)g->fwd.st, scaled ? 1 : 0, map);
+                       ip ? inplace_c<float>(g, bufs) : (const float *)x32, x, g->n, (const SweepState *)g->fwd.st,
+                       scaled ? 1 : 0, map, ip ? (const double *)g->fwd.ip_iw : nullptr);
     if (rtol > 0.0 && it < max_iter) {
       int it2 = 0;
       double r2 = INFINITY;
@@ -1648,7 +1651,7 @@ int solve_impl(pr_graph *g, double d, double tol, int max_iter, const pr_opts &o
         return rc;
       if (scaled || ip)
         hipLaunchKernelGGL(k_to64<double>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
-                           ip ? inplace_c64(g, bufs) : (const double *)xs, x, g->n,
+                           ip ? inplace_c<double>(g, bufs) : (const double *)xs, x, g->n,
                            (const SweepState *)g->fwd.st, scaled ? 1 : 0, map,
                            ip ? (const double *)g->fwd.ip_iw : nullptr);
       it += it2;
@@ -1849,8 +1852,8 @@ int iterate_impl(pr_graph *g, double d, const pr_opts &o, const double *p, doubl
   if (sweeps > 0 && (rc = run_sweeps<T>(g, a, o.mode, o.use_hip_graph != 0, sweeps))) return rc;
   if (elapsed_ms) PR_HIP(hipEventRecord(e1, g->work));
   if (sizeof(T) != 8 || (flags & kFlagScaled) || vo) {
-    // the in-place FP64 form reads its ranks back from its contributions
-    const bool from_c = vo && sizeof(T) == 8;
+    // the in-place form reads its ranks back from its contributions
+    const bool from_c = vo;
     hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
                        from_c ? (const T *)contrib<T>(g, 0) : (const T *)xs, x, g->n, (const SweepState *)P.st,
                        (flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr,
@@ -1918,7 +1921,7 @@ int profile_impl(pr_graph *g, double d, const pr_opts &o, double *x, int sweeps,
   }
   PR_HIP(hipGetLastError());
   if (sizeof(T) != 8 || (a.flags & kFlagScaled) || vo) {
-    const bool from_c = vo && sizeof(T) == 8;
+    const bool from_c = vo;
     hipLaunchKernelGGL(k_to64<T>, dim3(kInitGrid), dim3(kBlock), 0, g->work,
                        from_c ? (const T *)contrib<T>(g, 0) : (const T *)xs, x, g->n, (const SweepState *)P.st,
                        (a.flags & kFlagScaled) ? 1 : 0, vo ? P.ip_pos : nullptr,
