@@ -18,7 +18,7 @@
 // every column is summed in the same order whatever the tile width, so the
 // results do not depend on it.
 //
-// Arithmetic.  Ranks and contributions are FP32; sums use Neumaier
+// Arithmetic.  Ranks and contributions are FP32; sums use Kahan
 // compensation per lane and TwoSum when quarters combine (in quarter order).
 // Per-column residuals and dangling mass are summed in 64-bit fixed point
 // (2^-60 units), exact and order-free, then read as FP64.
@@ -104,8 +104,42 @@ struct VArgs {
   int par;  // sweep parity: 0 reads c0 and writes c1
 };
 
+// Compensated FP32 sum of one column: Kahan's update (the running low part c
+// joins each term before the term joins s; the sum is s + c).  The terms of a
+// PageRank sum all have one sign, where Kahan's error bound holds in any
+// order; the update takes four operations per term against eight for the
+// magnitude-tested form of LaneSum, which counts here: 64 columns per in-edge.
+// Partial sums combine by TwoSum of their leading parts, compensations added.
+struct KSum {
+  float s = 0.0f, c = 0.0f;
+  __device__ __forceinline__ void add(float v) {
+#pragma clang fp contract(off)
+    if constexpr (FPR_NAIVE_SUM) {
+      s = s + v;
+      return;
+    }
+    const float y = v + c;
+    const float t = s + y;
+    c = y - (t - s);
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return (double)s + (double)c; }
+  __device__ __forceinline__ void combine_with(const KSum &l) {
+#pragma clang fp contract(off)
+    if constexpr (FPR_NAIVE_SUM) {
+      s = s + l.s;
+      return;
+    }
+    const float t = s + l.s;
+    const float bp = t - s;
+    const float err = (s - (t - bp)) + (l.s - bp);
+    c = c + l.c + err;
+    s = t;
+  }
+};
+
 struct Sum4 {
-  LaneSum<float> v[4];
+  KSum v[4];
   __device__ __forceinline__ void add(const float4 &a) {
     v[0].add(a.x);
     v[1].add(a.y);

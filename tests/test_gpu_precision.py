@@ -89,3 +89,45 @@ def test_fp32_without_refinement_at_rmat20(mode):
     say("rmat20 %s FP32 only: %d sweeps, residual %.2e, L1 vs oracle %.3e" % (mode, it, res, err))
     assert err <= 1e-5
     g.close()
+
+
+def sinking_tiny_graph(T=2000, fan=1000, n=100000, out1=100):
+    """For a personalized solve seeded at vertex 0: 0 -> 1 is the seed's only
+    out-edge, 1 -> 0 and 1 -> `out1` dangling sinks; T sources without
+    in-edges (vertices 2..T+1) each point to vertex 1 and to fan - 1 sinks.
+    Their only rank is their share of the redistributed dangling mass, so each
+    adds about 6e-9 to vertex 1's sum, below half an FP32 ulp of the large
+    term from vertex 0 (about 0.15), which comes first in the row."""
+    tiny = np.arange(2, T + 2, dtype=np.int64)
+    sinks = np.arange(T + 2, n, dtype=np.int64)
+    src = [np.array([0, 1]), np.full(out1, 1), tiny]
+    dst = [np.array([1, 0]), sinks[:out1], np.ones(T, np.int64)]
+    for k in range(fan - 1):
+        src.append(tiny)
+        dst.append(sinks[(tiny * 7919 + k * 104729) % len(sinks)])
+    return n, np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32)
+
+
+def test_batched_compensated_column_sum_beats_plain_sum():
+    """The batched sweep's compensated column sums against plain ones: the lane
+    group whose share of vertex 1's row starts with the large term loses every
+    tiny term without compensation (about 3e-6 per sweep), which shifts the
+    rank of vertex 1 well past the solve's own error."""
+    fpr = _fpr()
+    n, src, dst = sinking_tiny_graph()
+    og = oracle.csr(n, src, dst)
+    p = np.zeros(n)
+    p[0] = 1.0
+    xs, _, _ = oracle.jacobi(og, D, tol=1e-14, max_iter=5000, p=p)
+    errs = {}
+    for lib in ("", "naive"):
+        g = fpr.Graph(n, src, dst, library=lib)
+        seeds = torch.zeros(64, dtype=torch.int32, device="cuda")
+        X, its, res = g.solve_batched(seeds, d=D, tol=1e-7, max_iter=500, tile=64)
+        x = X[:, 0].double().cpu().numpy()
+        errs[lib] = (abs(x[1] - xs[1]), l1(x, xs), int(its.max()))
+        say("%-6s batched: |err| at vertex 1 %.3e, L1 %.3e (%d sweeps)" % (lib or "comp", *errs[lib]))
+        g.close()
+    comp, naive = errs[""], errs["naive"]
+    assert naive[0] >= 1e-6 and naive[0] >= 5 * comp[0]
+    assert comp[1] <= naive[1] and comp[1] <= 1e-5
