@@ -102,3 +102,18 @@ def test_host_thread_scaling_leg():
     # is asynchronous across threads but still reaches the tolerance
     assert all(r["ec_sweeps"] == it_ec for r in rows)
     assert all(1 <= r["fused_sweeps"] < 1000 and np.isfinite(r["fused_speedup_vs_ec"]) for r in rows)
+
+
+def test_committed_traffic_records_match_the_committed_sources():
+    """Every counter record the benchmark reads was taken with the kernel
+    sources as committed (a change to a kernel source without new counter
+    runs would make the bench report null traffic)."""
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    used = {"fused_fp64_rmat24": bench.KERNEL_SOURCES, "fused_fp32_rmat24": bench.KERNEL_SOURCES,
+            "fused_fp64_rmat20": bench.KERNEL_SOURCES, "inplace_fp64_road8m": bench.KERNEL_SOURCES,
+            "batched_rmat20": bench.BATCHED_SOURCES, "probe_fp64_rmat24": bench.PROBE_SOURCES,
+            "probe_fp32_rmat24": bench.PROBE_SOURCES}
+    for key, files in used.items():
+        assert key in rec, key
+        assert rec[key]["source_sha"] == bench.kernel_source_sha(files), key
+        assert bench.traffic_record(key, files) == rec[key]["bytes_per_sweep"], key
