@@ -173,4 +173,10 @@ def test_inplace_interleaved_blocks(kind):
     xi = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
     g.iterate(xi, 400, d=D, mode="inplace", p=_p_dev(p))
     assert l1(xi.cpu().numpy(), xr) <= 1e-9
+    # FP32 sweeps alone (no refinement): the ranks read back from the FP32
+    # contributions meet the FP32 bar
+    xf = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+    g.iterate(xf, 400, d=D, mode="inplace", precision="fp32", p=_p_dev(p))
+    say("  fp32 iterate L1=%.2e" % l1(xf.cpu().numpy(), xr))
+    assert l1(xf.cpu().numpy(), xr) <= 1e-5
     g.close()
